@@ -1,0 +1,109 @@
+/*
+ * vegas_oracle.h -- CPU ORACLE for the per-event VEGAS iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, serial FP64 implementation
+ * written from the method's definition.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it.  It shares no source
+ * with the HIP library (paper_1503_06182_amd/csrc, include/vegas.h): the
+ * parameter layout below is restated here on purpose, not included.
+ *
+ * What it follows (Campbell, Ellis, Giele, "A Multi-Threaded Version of MCFM",
+ * EPJC 2015):
+ *   Sec. 2.1  VEGAS: iterations of event sets; after each iteration the grid is
+ *             re-optimised from the weights of ALL events of that iteration;
+ *             events are independent; the grid update itself is serial.
+ *   Sec. 2.2  every event draws its own group of random numbers so that the set
+ *             of events does not depend on how the work is split; sums are
+ *             made accurate (Kahan) so results do not depend on the split.
+ *   Sec. 3.2  an LO process with n final-state particles needs 3n-4 phase-space
+ *             integrations plus two parton momentum fractions.
+ * The paper prints no formula for the grid, the refinement, the phase space or
+ * the matrix elements; every such step below is the reading listed in the
+ * design notes ("paper silent" items), written from the textbook mathematics.
+ */
+#ifndef VEGAS_ORACLE_H
+#define VEGAS_ORACLE_H
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* process identifiers (same numbering as the library's; restated) */
+enum {
+  ORA_GAUSS = 0,     /* separable normalised Gaussian, any ndim             */
+  ORA_GENZ = 1,      /* Genz test families 1..6, any ndim                   */
+  ORA_EEMUMU = 2,    /* e+e- -> mu+mu- (QED, fixed s), ndim 2                */
+  ORA_DY_Z = 3,      /* q qbar -> photon/Z -> l+l-, hadronic, ndim 3         */
+  ORA_W_PLUS = 4,    /* u dbar -> W+ -> e+ nu, hadronic with cuts, ndim 4     */
+  ORA_WW_4L = 5      /* q qbar -> W+W- -> e+ nu mu- nubar, partonic, ndim 8   */
+};
+
+/* physics parameter vector layout (restated; see design notes) */
+enum {
+  ORA_P_ALPHA = 0, ORA_P_SW2 = 1, ORA_P_MZ = 2, ORA_P_GZ = 3, ORA_P_MW = 4,
+  ORA_P_GW = 5, ORA_P_SQRTS = 6, ORA_P_PDF_A = 7, ORA_P_PDF_a = 8,
+  ORA_P_PDF_b = 9, ORA_P_MLO = 10, ORA_P_MHI = 11, ORA_P_PTMIN = 12,
+  ORA_P_ETAMAX = 13, ORA_P_VUD = 14, ORA_P_CONV = 15, ORA_NPHYS = 16
+};
+
+/* ---- counter-based random numbers (Philox4x32-10, Salmon et al. 2011) ---- */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* ndim uniforms of event `event` in iteration `iter`, each in (0,1) */
+void ora_uniforms(uint64_t seed, uint32_t iter, uint64_t event, int ndim, double *u);
+
+/* ---- integrands: f(x) on the unit hypercube, cut events give 0 ---- */
+int ora_ndim(int process, int ndim_requested);
+double ora_integrand(int process, int ndim, const double *params, int nparams,
+                     const double *x);
+
+/* ---- physics building blocks exposed for the tests ---- */
+double ora_me_dy(const double *params, double shat, double c, int flavour);   /* <|M|^2> */
+double ora_sigmahat_dy(const double *params, double shat, int flavour);      /* closed form */
+double ora_me_eemumu_dirac(const double *params, double s, double c, double phi);
+int ora_spinor_check(const double p[4], double *max_dirac_residual, double *max_current_err);
+double ora_ww_me2(const double *params, const double mom[6][4], double m2p, double m2m,
+                  int flavour, int helicity);                 /* |M|^2, no averages */
+double ora_ww_onshell_me2(const double *params, double shat, double cth, double phi,
+                          int flavour, int helicity, int pol_p, int pol_m, int sign_t);
+void ora_ww_momenta(const double *params, const double *x, double mom[6][4],
+                    double *m2p, double *m2m, double *jac);
+
+/* ---- the VEGAS state machine ---- */
+typedef struct ora_state ora_state;
+ora_state *ora_create(int process, int ndim, int nbins, uint64_t seed, double alpha,
+                      const double *params, int nparams);
+void ora_destroy(ora_state *s);
+/* one iteration of n events at the current grid; out = {I_j, var_j, n_nonzero, n_nonfinite} */
+int ora_iterate(ora_state *s, int64_t n, double out[4]);
+int ora_refine(ora_state *s);
+/* out = {I, sigma, chi2/dof, n_iter} */
+int ora_result(const ora_state *s, double out[4]);
+int ora_get_grid(const ora_state *s, double *edges);
+int ora_set_grid(ora_state *s, const double *edges);
+int ora_get_hist(const ora_state *s, double *d, double sums[2]);
+int ora_set_iteration(ora_state *s, uint32_t iter);
+uint32_t ora_get_iteration(const ora_state *s);
+/* weights (and bin indices, [n][ndim]) of events [first, first+n) of iteration iter at the current grid */
+int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t n,
+                      double *w, uint8_t *bins);
+/* grid map of one point: u[ndim] -> x[ndim], jacobian, bins */
+int ora_grid_map(const ora_state *s, const double *u, double *x, double *jac, int *bins);
+/* refinement of a stand-alone grid from a given histogram (used by the tests) */
+int ora_refine_grid(int ndim, int nbins, double alpha, const double *d, double *edges);
+/* damped importance m[0..n-1] of one dimension's histogram (0 if it is empty) */
+int ora_refine_weights(int n, double alpha, const double *d, double *m);
+
+/* ---- adjoint oracle for the Drell-Yan integrand (forward-mode derivatives) ----
+ * theta = (M_Z, Gamma_Z, sin^2 theta_W, pdf a, pdf b).  The proposal (grid, BW and
+ * tau mappings) stays at the nominal parameters; only |M|^2 and the PDFs move. */
+int ora_dy_grad(const ora_state *s, uint32_t iter, int64_t n, const double *theta,
+                double *sigma, double dsigma[5]);
+double ora_dy_weight_theta(const ora_state *s, uint32_t iter, int64_t event,
+                           const double *theta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
