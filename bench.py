@@ -1,0 +1,165 @@
+"""Benchmark of the per-event VEGAS iteration on one MI355X.
+
+Workload (default): pp -> W+ -> e+ nu at sqrt(S) = 13 TeV, 4 dimensions, 100
+bins per dimension, 1e6 events per iteration, Breit-Wigner mapping, lepton
+pT > 20 GeV and |eta| < 2.5, synthetic PDFs A x^-0.5 (1-x)^3, seed 1.
+One step = one full VEGAS iteration: events -> exact accumulation ->
+finalisation (vegas_iterate) -> grid refinement (vegas_refine).
+
+Prints one JSON line: events/s over the timed steps, the variance-weighted
+effective events/s 1/(eps^2 T) of the timed iterations' combined estimate, the
+roofline of the dominant kernel (timed with HIP events on the library's own
+stream) and the CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import struct
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per event of the event kernel, FP64 FLOPs (add, mul, and
+# fma counted as 2; transcendental calls as the FP64 VALU operations their
+# library expansion issues), from the rocprofv3 FP64 instruction counters of
+# one launch divided by the events of that launch.
+FLOP_PER_EVENT = {"w_plus": None, "dy_z": None, "ww_4l": None}
+PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l"])
+    ap.add_argument("--events", type=int, default=0, help="events per iteration (0: workload's)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32me"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--cpu-events", type=int, default=4_000_000)
+    return ap.parse_args()
+
+
+def combine(history):
+    """Inverse-variance combination of (I_j, var_j) pairs (for the report)."""
+    ws = sum(1.0 / v for _, v in history)
+    I = sum(i / v for i, v in history) / ws
+    return I, (1.0 / ws) ** 0.5
+
+
+def history_from_state(blob, ndim, nbins):
+    head = struct.calcsize("<Q4iQ")
+    _magic, _proc, _nd, _nb, it, _seed = struct.unpack_from("<Q3iIQ", blob, 0)
+    off = head + 8 * ndim * (nbins + 1)
+    vals = struct.unpack_from(f"<{2 * it}d", blob, off)
+    return [(vals[2 * j], vals[2 * j + 1]) for j in range(it)]
+
+
+def cpu_baseline(cfg, iters, events):
+    import oracle
+    o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"])
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        o.iterate(events)
+        o.refine()
+    dt = time.perf_counter() - t0
+    return {"value": iters * events / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations x {events} events of the same workload, serial "
+                      f"FP64 C oracle on one host core, {dt:.1f} s"}
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1503_06182_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    cfg = W.config(args.workload)
+    N = args.events or cfg["n_events"]
+    prec = P.FP32_ME if args.precision == "fp32me" else P.FP64
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"], precision=prec, max_events=N)
+    for _ in range(args.warmup):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    st = g.stage_times()
+    hist = history_from_state(g.get_state(), cfg["ndim"], cfg["nbins"])
+    timed = hist[args.warmup:]
+    I, sig = combine(timed)
+    eps = sig / abs(I)
+    events_per_s = args.steps * N / T
+    eff = 1.0 / (eps * eps * T)
+
+    ms_ev, n_ev = st["event"]
+    ms_acc, n_acc = st["accumulate"]
+    avg_ev = ms_ev / max(n_ev, 1) * 1e-3
+    avg_acc = ms_acc / max(n_acc, 1) * 1e-3
+    flop = FLOP_PER_EVENT.get(args.workload)
+    # record bytes per event: w (8) + packed bin words (4 per 4 dimensions), written
+    # by the event kernel and read back by the accumulation kernel
+    rec_bytes = 8 + 4 * ((cfg["ndim"] + 3) // 4)
+    if flop is not None:
+        achieved = flop * N / avg_ev / 1e12
+        roof = {"kernel": "k_event", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_ev * 1e3, "flop_per_event": flop}
+    else:
+        roof = {"kernel": "k_event", "bound": "alu", "achieved": None,
+                "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None, "avg_launch_ms": avg_ev * 1e3}
+    line = {
+        "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
+        "value": events_per_s,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == P.FP64 else "f32-me/f64",
+        "data": "synthetic (counter-based Philox stream, seed 1; parametric PDFs)",
+        "config": {"workload": args.workload, "events_per_iteration": N, "ndim": cfg["ndim"],
+                   "nbins": cfg["nbins"], "iterations_timed": args.steps},
+        "effective_events_per_s": eff,
+        "time_to_1e-3_s": 1e6 / eff,
+        "integral_pb": I,
+        "rel_error": eps,
+        "stage_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in st.items()},
+        "accumulate_hbm_gbs": rec_bytes * N / avg_acc / 1e9,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters,
+                                            min(args.cpu_events, 10 * N))
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

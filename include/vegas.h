@@ -1,0 +1,187 @@
+/*
+ * vegas.h -- C ABI of the MI355X (gfx950) VEGAS hot-path library.
+ *
+ * The library estimates a multi-dimensional integral by VEGAS: iterations of
+ * independent events, all events of an iteration combined once, then a serial
+ * re-optimisation of the adaptive grid (Campbell, Ellis, Giele, "A
+ * Multi-Threaded Version of MCFM", Sec. 2.1; abstract).  Every step of an
+ * iteration runs in the library's HIP kernels on the caller's stream.
+ *
+ * Conventions for every function:
+ *   - returns VEGAS_OK (0) or a negative vegas_status; no C++ exception
+ *     crosses the ABI; vegas_strerror() gives a message, including the HIP
+ *     error text of the last VEGAS_EHIP on that thread;
+ *   - a handle is not thread-safe; separate handles are independent;
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *     pointers are caller-owned device memory on the handle's device, ordered
+ *     on the handle's stream.
+ *   - results do not depend on the launch configuration (waves per block,
+ *     number of blocks): the per-iteration sums are exact integer fixed-point
+ *     accumulations, so every launch gives byte-identical numbers (Sec. 2.2:
+ *     results independent of the number of threads).
+ */
+#ifndef VEGAS_H
+#define VEGAS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VEGAS_OK = 0,
+  VEGAS_EINVAL = -1, /* bad configuration or argument                         */
+  VEGAS_ESTATE = -2, /* call order (e.g. refine before any iterate)            */
+  VEGAS_ENOMEM = -3, /* workspace too small or device allocation failed        */
+  VEGAS_EHIP = -4    /* HIP runtime error; text kept for vegas_strerror         */
+} vegas_status;
+
+/* integrands (processes) */
+typedef enum {
+  VEGAS_GAUSS = 0,  /* separable normalised Gaussian on [0,1]^ndim; params (mu, sigma)     */
+  VEGAS_GENZ = 1,   /* Genz families 1..6; params (family, a[ndim], w[ndim])                */
+  VEGAS_EEMUMU = 2, /* e+e- -> mu+mu- at fixed s, ndim 2                                     */
+  VEGAS_DY_Z = 3,   /* q qbar -> photon/Z -> l+l-, hadronic, ndim 3 (m^2 by Breit-Wigner,
+                       ln x1, cos theta)                                                    */
+  VEGAS_W_PLUS = 4, /* u dbar -> W+ -> e+ nu, hadronic, lepton pT / |eta| cuts, ndim 4      */
+  VEGAS_WW_4L = 5   /* q qbar -> W+W- -> e+ nu mu- nubar, partonic at fixed sqrt(shat),
+                       doubly resonant tree amplitudes, ndim 8 = 3*4 - 4 (Sec. 3.2)         */
+} vegas_process;
+
+/* arithmetic of the matrix element */
+typedef enum {
+  VEGAS_FP64 = 0,    /* everything in binary64                                          */
+  VEGAS_FP32_ME = 1  /* WW_4L only: spinors, currents and amplitudes in binary32; mappings,
+                        Jacobians, Breit-Wigner, weights, sums and refinement in binary64 */
+} vegas_precision;
+
+/* physics parameter vector (processes 2..5), length VEGAS_NPHYS */
+enum {
+  VEGAS_P_ALPHA = 0,  /* alpha_em                                      */
+  VEGAS_P_SW2 = 1,    /* sin^2 theta_W                                 */
+  VEGAS_P_MZ = 2, VEGAS_P_GZ = 3, VEGAS_P_MW = 4, VEGAS_P_GW = 5,
+  VEGAS_P_SQRTS = 6,  /* hadronic sqrt(S), or sqrt(shat) for EEMUMU/WW_4L */
+  VEGAS_P_PDF_A = 7, VEGAS_P_PDF_a = 8, VEGAS_P_PDF_b = 9, /* f(x) = A x^a (1-x)^b */
+  VEGAS_P_MLO = 10, VEGAS_P_MHI = 11, /* Breit-Wigner mass window; MHI <= 0: sqrt(S) */
+  VEGAS_P_PTMIN = 12, VEGAS_P_ETAMAX = 13, /* charged-lepton cuts (W_PLUS)           */
+  VEGAS_P_VUD = 14,
+  VEGAS_P_CONV = 15,  /* (hbar c)^2 in pb GeV^2                        */
+  VEGAS_NPHYS = 16
+};
+
+#define VEGAS_MAX_DIM 16
+#define VEGAS_MAX_BINS 255
+#define VEGAS_MAX_PARAMS 64
+#define VEGAS_MAX_ITER 4096
+
+typedef struct {
+  int32_t process;         /* vegas_process                                          */
+  int32_t ndim;            /* GAUSS/GENZ: 1..16; others must equal their dimension   */
+  int32_t nbins;           /* bins per dimension, 2..255                              */
+  int32_t precision;       /* vegas_precision                                        */
+  uint64_t seed;           /* key of the counter-based random numbers                */
+  double alpha;            /* grid damping exponent (1.5 typical), >= 0              */
+  const double *params;    /* host, copied at init; may be NULL if nparams == 0      */
+  int32_t nparams;         /* <= VEGAS_MAX_PARAMS                                     */
+  int32_t waves_per_block; /* launch knob: 0 = auto, else 1, 2, 4, 8 or 16            */
+  int32_t max_blocks;      /* launch knob: 0 = auto, else cap on blocks per launch    */
+} vegas_config;
+
+typedef struct {
+  double integral;      /* I_j = S1 / N                                    */
+  double variance;      /* var_j = (S2 / N - I_j^2) / (N - 1)              */
+  int64_t n_events;     /* N, cut-rejected events included                 */
+  int64_t n_nonzero;    /* events with w != 0                              */
+  int64_t n_nonfinite;  /* events whose w or w^2 was not finite (dropped)  */
+  uint32_t iteration;   /* index j of this iteration (keys the random stream) */
+} vegas_iter_result;
+
+typedef struct vegas_state *vegas_handle;
+
+/* Device bytes a workspace must hold for cfg and up to max_events per iteration.
+ * Errors: VEGAS_EINVAL (bad cfg, max_events < 2 or >= 2^31). */
+int vegas_workspace_size(const vegas_config *cfg, int64_t max_events, size_t *bytes);
+
+/* Create a handle: validate cfg, carve device buffers out of `workspace`
+ * (device, caller-owned, >= vegas_workspace_size bytes, 256-byte aligned; the
+ * library never frees it) or, if workspace is NULL, allocate them itself;
+ * set the uniform grid e_k = k / nbins (Sec. 2.1: the grid is then optimised
+ * after each iteration).  stream: hipStream_t or NULL for the null stream;
+ * the handle is bound to the current device.
+ * Errors: VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EHIP. */
+int vegas_init(const vegas_config *cfg, int64_t max_events, void *workspace, size_t ws_bytes,
+               void *stream, vegas_handle *out);
+
+/* One iteration of n_events events at the current grid (Sec. 2.1: the events
+ * are generated and evaluated independently, then all events of the iteration
+ * are combined).  Event i of iteration j draws its point from the
+ * counter-based generator keyed by (seed, j, i) (Sec. 2.2: the same events for
+ * any split of the work), maps it through the grid, evaluates the integrand and
+ * accumulates w, w^2 and the per-bin histogram of w^2 exactly.  j is the
+ * handle's iteration counter, incremented by this call.
+ * out (host, nullable): if given, the call waits for the stream and fills it;
+ * if NULL the call is asynchronous on the stream.
+ * Errors: VEGAS_EINVAL (n_events < 2 or above max_events), VEGAS_ESTATE
+ * (more than VEGAS_MAX_ITER iterations), VEGAS_EHIP. */
+int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result *out);
+
+/* Re-optimise the grid from the last iteration's histogram (Sec. 2.1: serial
+ * grid optimisation between iterations): per dimension, neighbour smoothing,
+ * r_k = dbar_k / sum dbar, damping m_k = ((r_k - 1)/ln r_k)^alpha, new edges at
+ * equal cumulative m.  Asynchronous on the stream.
+ * Errors: VEGAS_ESTATE (no iteration since init or since the last refine). */
+int vegas_refine(vegas_handle h);
+
+/* Inverse-variance combination of all iterations so far (Sec. 2.1: several
+ * iterations of sets of events): integral, its error and chi^2 per degree of
+ * freedom.  If an iteration has zero variance the plain mean of such
+ * iterations is returned with error 0.  Waits for the stream; host outputs.
+ * Errors: VEGAS_ESTATE (no iteration yet). */
+int vegas_result(vegas_handle h, double *integral, double *error, double *chi2_dof,
+                 int32_t *n_iter);
+
+/* Grid edges, host array [ndim][nbins+1] (waits for the stream). */
+int vegas_get_grid(vegas_handle h, double *edges);
+/* Replace the grid (host [ndim][nbins+1]; e_0 = 0, e_n = 1, non-decreasing).
+ * Errors: VEGAS_EINVAL. */
+int vegas_set_grid(vegas_handle h, const double *edges);
+
+/* Last iteration's per-bin histogram d [ndim][nbins] (sum of w^2 over the
+ * events in each bin) and sums {S1, S2}; host arrays.  Errors: VEGAS_ESTATE. */
+int vegas_get_hist(vegas_handle h, double *d, double *sums);
+
+/* Weights of events [first, first+n) of the last iteration, host w[n], and
+ * their bin indices, host bins[n][ndim] (nullable).  Errors: VEGAS_EINVAL,
+ * VEGAS_ESTATE. */
+int vegas_get_weights(vegas_handle h, int64_t first, int64_t n, double *w, uint8_t *bins);
+
+/* Checkpoint: grid, iteration counter and the per-iteration estimates.
+ * vegas_get_state with buf == NULL sets *bytes to the size needed.  A restored
+ * handle continues bit-identically, because events are keyed by (seed, j, i).
+ * Errors: VEGAS_EINVAL (size or configuration mismatch). */
+int vegas_get_state(vegas_handle h, void *buf, size_t *bytes);
+int vegas_set_state(vegas_handle h, const void *buf, size_t bytes);
+
+/* Change the launch configuration (must not change any result). */
+int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks);
+
+/* Per-stage kernel timing (off by default).  When on, every launch is
+ * bracketed by HIP events recorded on the handle's stream.  vegas_stage_times
+ * waits for the stream and returns, for the stages {events, accumulation,
+ * finalisation, refinement}, the summed kernel milliseconds ms[4] and launch
+ * counts launches[4] (host arrays, either nullable) since the last reset;
+ * reset != 0 clears them. */
+int vegas_set_timing(vegas_handle h, int32_t enable);
+int vegas_stage_times(vegas_handle h, double *ms, int64_t *launches, int32_t reset);
+
+/* Release the handle (and the buffers the library allocated itself). */
+int vegas_destroy(vegas_handle h);
+
+/* Message for a status code. */
+const char *vegas_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -138,15 +138,24 @@ static phys unpack(const double *p) {
 }
 
 /* Breit-Wigner mapping of r in [0,1] onto m^2 in [m2lo, m2hi]:
- * rho uniform between atan((m2lo-M^2)/(M G)) and atan((m2hi-M^2)/(M G)),
- * m^2 = M^2 + M G tan(rho); jac = dm^2/dr. */
+ * rho uniform between rho_lo = atan(t_lo), t_lo = (m2lo-M^2)/(M G), and
+ * rho_hi = atan((m2hi-M^2)/(M G)); m^2 = M^2 + M G tan(rho); jac = dm^2/dr.
+ * Below the pole (rho < 0) the same m^2 is taken from the lower edge by the
+ * tangent addition theorem, m^2 = m2lo + M G (1 + t_lo^2) tan(d) / (1 - t_lo tan(d)),
+ * d = rho - rho_lo, which avoids the cancellation of M^2 + M G tan(rho) as m^2 -> 0. */
 static void bw_map(double M, double G, double m2lo, double m2hi, double r, double *m2,
                    double *jac) {
   double MG = M * G;
-  double rlo = atan((m2lo - M * M) / MG);
+  double tlo = (m2lo - M * M) / MG;
+  double rlo = atan(tlo);
   double rhi = atan((m2hi - M * M) / MG);
   double rho = rlo + r * (rhi - rlo);
-  *m2 = M * M + MG * tan(rho);
+  if (rho < 0.0) {
+    double td = tan(r * (rhi - rlo));
+    *m2 = m2lo + MG * (1.0 + tlo * tlo) * td / (1.0 - tlo * td);
+  } else {
+    *m2 = M * M + MG * tan(rho);
+  }
   double dm = *m2 - M * M;
   *jac = (rhi - rlo) * (dm * dm + MG * MG) / MG;
 }
@@ -243,10 +252,10 @@ static double f_w(const double *par, const double *x) {
   double c = 2.0 * x[2] - 1.0, phi = 2.0 * PI * x[3];
   /* e+ momentum in the partonic rest frame, then boost along z */
   double E = 0.5 * sqrt(m2);
-  double s = sqrt(1.0 - c * c);
+  double s = sqrt((1.0 - c) * (1.0 + c));
   double p[4] = {E, E * s * cos(phi), E * s * sin(phi), E * c};
   double beta = (x1 - x2) / (x1 + x2);
-  double gam = 1.0 / sqrt(1.0 - beta * beta);
+  double gam = 1.0 / sqrt((1.0 - beta) * (1.0 + beta));
   double Elab = gam * (p[0] + beta * p[3]);
   double pzlab = gam * (p[3] + beta * p[0]);
   double pt = sqrt(p[1] * p[1] + p[2] * p[2]);
@@ -416,7 +425,7 @@ double ora_me_eemumu_dirac(const double *params, double s, double c, double phi)
   init_gamma();
   phys P = unpack(params);
   double e2 = 4.0 * PI * P.alpha;
-  double E = 0.5 * sqrt(s), sn = sqrt(1.0 - c * c);
+  double E = 0.5 * sqrt(s), sn = sqrt((1.0 - c) * (1.0 + c));
   double p1[4] = {E, 0, 0, E}, p2[4] = {E, 0, 0, -E};
   double p3[4] = {E, E * sn * cos(phi), E * sn * sin(phi), E * c};
   double p4[4] = {E, -p3[1], -p3[2], -p3[3]};
@@ -530,18 +539,18 @@ void ora_ww_momenta(const double *params, const double *x, double mom[6][4], dou
   if (!(lam > 0.0)) return;
   double q = sqrt(lam) / (2.0 * rs);
   double Ep = (shat + mp2 - mm2) / (2.0 * rs), Em = (shat - mp2 + mm2) / (2.0 * rs);
-  double c = 2.0 * x[2] - 1.0, phi = 2.0 * PI * x[3], s = sqrt(1.0 - c * c);
+  double c = 2.0 * x[2] - 1.0, phi = 2.0 * PI * x[3], s = sqrt((1.0 - c) * (1.0 + c));
   double n[3] = {s * cos(phi), s * sin(phi), c};
   double qp[4] = {Ep, q * n[0], q * n[1], q * n[2]};
   double qm[4] = {Em, -q * n[0], -q * n[1], -q * n[2]};
   /* W+ -> e+ nu */
-  double c3 = 2.0 * x[4] - 1.0, f3 = 2.0 * PI * x[5], s3 = sqrt(1.0 - c3 * c3);
+  double c3 = 2.0 * x[4] - 1.0, f3 = 2.0 * PI * x[5], s3 = sqrt((1.0 - c3) * (1.0 + c3));
   double k3[4] = {0.5 * mp, 0.5 * mp * s3 * cos(f3), 0.5 * mp * s3 * sin(f3), 0.5 * mp * c3};
   double k4[4] = {0.5 * mp, -k3[1], -k3[2], -k3[3]};
   boost_from_rest(qp, mp, k3, mom[0]);
   boost_from_rest(qp, mp, k4, mom[1]);
   /* W- -> mu- nubar */
-  double c5 = 2.0 * x[6] - 1.0, f5 = 2.0 * PI * x[7], s5 = sqrt(1.0 - c5 * c5);
+  double c5 = 2.0 * x[6] - 1.0, f5 = 2.0 * PI * x[7], s5 = sqrt((1.0 - c5) * (1.0 + c5));
   double k5[4] = {0.5 * mm, 0.5 * mm * s5 * cos(f5), 0.5 * mm * s5 * sin(f5), 0.5 * mm * c5};
   double k6[4] = {0.5 * mm, -k5[1], -k5[2], -k5[3]};
   boost_from_rest(qm, mm, k5, mom[2]);

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) VEGAS hot path: counter-keyed events, grid map, phase space,
+matrix elements, exact per-iteration combine and grid refinement, behind the C
+ABI of include/vegas.h.  ``vegas`` is the ctypes binding."""
+from .vegas import (DY_Z, EEMUMU, FP32_ME, FP64, GAUSS, GENZ, W_PLUS, WW_4L, Integrator,
+                    VegasError, load, workspace_size)
+
+__all__ = ["Integrator", "VegasError", "load", "workspace_size", "GAUSS", "GENZ", "EEMUMU",
+           "DY_Z", "W_PLUS", "WW_4L", "FP64", "FP32_ME"]

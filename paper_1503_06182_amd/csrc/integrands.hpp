@@ -1,0 +1,422 @@
+// integrands.hpp -- per-event integrands f(x) on [0,1]^D for the gfx950 kernels.
+//
+// The paper evaluates a phase-space point and a matrix element times parton
+// densities per event (Sec. 2.1); it prints neither.  The readings implemented
+// here: Breit-Wigner mapping of resonant masses, the (tau, ln x1) mapping of the
+// parton fractions, massless two-body decays with Lorentz boosts, chiral
+// couplings, parametric PDFs A x^a (1-x)^b, and 3n-4 phase-space dimensions
+// for n final-state particles (Sec. 3.2).  Every configuration-wide constant
+// (couplings, mapping ranges) is computed once on the host into PhysConst and
+// reaches the kernel as a by-value argument (constant/scalar memory).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vg {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct PhysConst {
+  int process, ndim, nbins, family;
+  double conv;                // (hbar c)^2 in pb GeV^2
+  // Breit-Wigner mapping of the first resonance: m^2 = M2 + MG tan(rho_lo + x rho_rng)
+  double M2, MG, rho_lo, rho_rng, m2lo, tlo;
+  double invS;                // 1 / S (hadronic)
+  double pdfA, pdfa, pdfb;
+  // Drell-Yan: Q_q Q_l and chiral Z couplings g[q][h] * g_l[h'] products
+  double qql[2];              // Q_q * Q_l for q = u, d
+  double gg[2][4];            // g_q,h g_l,h' for (h,h') = LL, LR, RL, RR
+  double e4_12;               // e^4 / 12
+  double mzgz, mz2;
+  // W+
+  double g4v2_24;             // g^4 |V|^2 / 24
+  double ptmin2, th2;         // pT^2 cut, tanh(eta_max)^2
+  // WW
+  double rs, shat, gs;        // sqrt(shat), shat, g / sqrt(2)
+  double cs_re[2][2], cs_im[2][2];  // s-channel photon+Z coefficient, [q][h]
+  double ct;                  // exchange-diagram coefficient: -g^2 / 2
+  double csR2;                // |Cs[u][R]|^2 + |Cs[d][R]|^2
+  // e+e- -> mu+mu-
+  double s_ee, e4;
+  // Gaussian test integrand
+  double mu, inv2s2, gnorm;   // exp(-(x-mu)^2 inv2s2) * gnorm per dimension
+  // Genz families
+  double ga[16], gw[16];
+};
+
+// ---------------------------------------------------------------------------
+// mappings (rounding kept as in their plain definitions: no contraction)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bw_map(double r, double M2, double MG, double m2lo, double tlo,
+                                         double rlo, double rrng, double& jac) {
+#pragma clang fp contract(off)
+  const double rho = rlo + r * rrng;
+  double m2;
+  if (rho < 0.0) {
+    // below the pole: measured from the window's lower edge (tangent addition
+    // theorem), free of the cancellation in M^2 + M G tan(rho) as m^2 -> m2lo
+    const double td = tan(r * rrng);
+    m2 = m2lo + MG * (1.0 + tlo * tlo) * td / (1.0 - tlo * td);
+  } else {
+    m2 = M2 + MG * tan(rho);
+  }
+  const double dm = m2 - M2;
+  jac = rrng * (dm * dm + MG * MG) / MG;
+  return m2;
+}
+
+// A x^a (1-x)^b from ln x and ln(1-x)
+__device__ __forceinline__ double pdf_l(const PhysConst& c, double lnx, double ln1mx) {
+  return c.pdfA * exp(c.pdfa * lnx + c.pdfb * ln1mx);
+}
+
+// ---------------------------------------------------------------------------
+// test integrands
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ double f_gauss(const PhysConst& c, const double* x) {
+  const int nd = D > 0 ? D : c.ndim;
+  double s = 0.0, norm = 1.0;
+#pragma unroll
+  for (int d = 0; d < (D > 0 ? D : 16); ++d) {
+    if (d >= nd) break;
+    const double z = x[d] - c.mu;
+    s += z * z;
+    norm *= c.gnorm;
+  }
+  return norm * exp(-s * c.inv2s2);
+}
+
+template <int D>
+__device__ __forceinline__ double f_genz(const PhysConst& c, const double* x) {
+  const int nd = D > 0 ? D : c.ndim;
+  double s = 0.0, f = 1.0;
+  switch (c.family) {
+    case 1:
+      for (int d = 0; d < nd; ++d) s += c.ga[d] * x[d];
+      return cos(2.0 * kPi * c.gw[0] + s);
+    case 2:
+      for (int d = 0; d < nd; ++d) {
+        const double z = x[d] - c.gw[d];
+        f *= 1.0 / (1.0 / (c.ga[d] * c.ga[d]) + z * z);
+      }
+      return f;
+    case 3:
+      for (int d = 0; d < nd; ++d) s += c.ga[d] * x[d];
+      return pow(1.0 + s, -static_cast<double>(nd + 1));
+    case 4:
+      for (int d = 0; d < nd; ++d) {
+        const double z = x[d] - c.gw[d];
+        s += c.ga[d] * c.ga[d] * z * z;
+      }
+      return exp(-s);
+    case 5:
+      for (int d = 0; d < nd; ++d) s += c.ga[d] * fabs(x[d] - c.gw[d]);
+      return exp(-s);
+    case 6:
+      if (x[0] > c.gw[0]) return 0.0;
+      if (nd > 1 && x[1] > c.gw[1]) return 0.0;
+      for (int d = 0; d < nd; ++d) s += c.ga[d] * x[d];
+      return exp(s);
+    default:
+      return __builtin_nan("");
+  }
+}
+
+// e+e- -> mu+mu-: <|M|^2> = e^4 (1 + c^2); flux 1/(2s), dPhi_2 = dOmega/(32 pi^2),
+// solid-angle Jacobian 4 pi -> f = conv e^4 (1 + c^2) / (16 pi s)
+__device__ __forceinline__ double f_eemumu(const PhysConst& c, const double* x) {
+  const double cs = 2.0 * x[0] - 1.0;
+  return c.conv * c.e4 * (1.0 + cs * cs) / (16.0 * kPi * c.s_ee);
+}
+
+// ---------------------------------------------------------------------------
+// q qbar -> photon/Z -> l- l+ (both beam orderings).  With one PDF for all
+// four flavours the two orderings sum to sum_{hh'} |A_hh'|^2 * 2 (1 + c^2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
+  double jbw;
+  const double m2 = bw_map(x[0], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  double L, l1, l2;
+  {
+#pragma clang fp contract(off)
+    L = log(m2 * c.invS);
+    l1 = x[1] * L;
+    l2 = L - l1;
+  }
+  const double jtau = -L * c.invS;
+  const double f1 = pdf_l(c, l1, log(-expm1(l1)));
+  const double f2 = pdf_l(c, l2, log(-expm1(l2)));
+  const double cs = 2.0 * x[2] - 1.0;
+  // 1 / (shat - MZ^2 + i MZ GZ)
+  const double ds = m2 - c.mz2;
+  const double den = 1.0 / (ds * ds + c.mzgz * c.mzgz);
+  const double pre = ds * den, pim = -c.mzgz * den;
+  const double inv_s = 1.0 / m2;
+  double sum = 0.0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int hh = 0; hh < 4; ++hh) {
+      const double re = c.qql[q] * inv_s + c.gg[q][hh] * pre;
+      const double im = c.gg[q][hh] * pim;
+      sum += re * re + im * im;
+    }
+  const double me = c.e4_12 * m2 * m2 * sum * 2.0 * (1.0 + cs * cs);
+  // conv * J_bw * J_tau * J_cos(2) * flux 1/(2 shat) * 2 pi / (32 pi^2)
+  return c.conv * jbw * jtau * 2.0 * (0.5 * inv_s) * (1.0 / (16.0 * kPi)) * f1 * f2 * me;
+}
+
+// ---------------------------------------------------------------------------
+// u dbar -> W+ -> e+ nu (both orderings) with e+ cuts pT > ptmin, |eta| < etamax.
+// Orderings sum to g^4 |V|^2 shat^2 (1 + c^2) / (24 |D|^2); the cuts use the
+// boost-invariant pT^2 = (shat/4)(1 - c^2) and the lab polar cosine
+// (c + beta)/(1 + beta c), beta = (x1 - x2)/(x1 + x2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
+  double jbw;
+  const double m2 = bw_map(x[0], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  double L, l1, l2;
+  {
+#pragma clang fp contract(off)
+    L = log(m2 * c.invS);
+    l1 = x[1] * L;
+    l2 = L - l1;
+  }
+  const double jtau = -L * c.invS;
+  const double cs = 2.0 * x[2] - 1.0;
+  const double x1 = exp(l1), x2 = exp(l2);
+  const double pt2 = 0.25 * m2 * (1.0 - cs) * (1.0 + cs);
+  const double beta = (x1 - x2) / (x1 + x2);
+  const double num = cs + beta, dnm = 1.0 + beta * cs;
+  const bool pass = (pt2 > c.ptmin2) && (num * num < c.th2 * dnm * dnm);
+  if (!pass) return 0.0;
+  const double ds = m2 - c.M2;
+  const double den = ds * ds + c.MG * c.MG;
+  const double me = c.g4v2_24 * m2 * m2 * (1.0 + cs * cs) / den;
+  const double f1 = pdf_l(c, l1, log(-expm1(l1)));
+  const double f2 = pdf_l(c, l2, log(-expm1(l2)));
+  // conv * J_bw * J_tau * flux 1/(2 shat) * (2 * 2 pi)/(32 pi^2)
+  return c.conv * jbw * jtau * (0.5 / m2) * (1.0 / (8.0 * kPi)) * f1 * f2 * me;
+}
+
+// ---------------------------------------------------------------------------
+// q qbar -> W+ W- -> e+ nu mu- nubar: helicity amplitudes in two-component
+// (Weyl) form.  Quarks along +-z; lepton helicities fixed by V-A; the quark-pair
+// currents are then j_L = rs (0, 1, -i, 0) and j_R = rs (0, 1, i, 0).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct cx {
+  R re, im;
+};
+template <typename R>
+__device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cconjmul(cx<R> a, cx<R> b) {  // conj(a) * b
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ R cabs2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// helicity-minus massless 2-spinor (left-chiral), phase chosen per hemisphere
+template <typename R>
+__device__ __forceinline__ void spinor_m(const R p[4], cx<R>& s0, cx<R>& s1) {
+  if (p[3] >= R(0)) {
+    const R r = sqrt(p[0] + p[3]);
+    const R ir = R(1) / r;
+    s0 = {-p[1] * ir, p[2] * ir};
+    s1 = {r, R(0)};
+  } else {
+    const R r = sqrt(p[0] - p[3]);
+    const R ir = R(1) / r;
+    s0 = {-r, R(0)};
+    s1 = {p[1] * ir, p[2] * ir};
+  }
+}
+
+// J^mu = a^dagger sigma-bar^mu b (contravariant components)
+template <typename R>
+__device__ __forceinline__ void current(cx<R> a0, cx<R> a1, cx<R> b0, cx<R> b1, cx<R> J[4]) {
+  const cx<R> t00 = cconjmul(a0, b0), t11 = cconjmul(a1, b1);
+  const cx<R> t01 = cconjmul(a0, b1), t10 = cconjmul(a1, b0);
+  J[0] = cadd(t00, t11);
+  J[1] = {-(t01.re + t10.re), -(t01.im + t10.im)};
+  const cx<R> d = csub(t01, t10);
+  J[2] = {-d.im, d.re};  // i * d
+  J[3] = csub(t11, t00);
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> mdot(const cx<R> a[4], const cx<R> b[4]) {
+  cx<R> s = cmul(a[0], b[0]);
+  s = csub(s, cmul(a[1], b[1]));
+  s = csub(s, cmul(a[2], b[2]));
+  return csub(s, cmul(a[3], b[3]));
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> mdot_r(const R a[4], const cx<R> b[4]) {
+  return {a[0] * b[0].re - a[1] * b[1].re - a[2] * b[2].re - a[3] * b[3].re,
+          a[0] * b[0].im - a[1] * b[1].im - a[2] * b[2].im - a[3] * b[3].im};
+}
+
+// [ (sigma-bar.e2)(sigma.k)(sigma-bar.e1) ]_{01}; sigma-bar.e = e^0 + sigma.e,
+// sigma.k = k^0 - sigma.k (k real)
+template <typename R>
+__device__ __forceinline__ cx<R> chain01(const cx<R> e2[4], const R k[4], const cx<R> e1[4]) {
+  const cx<R> A00 = cadd(e2[0], e2[3]);
+  const cx<R> A01 = {e2[1].re + e2[2].im, e2[1].im - e2[2].re};  // e2^1 - i e2^2
+  const cx<R> C01 = {e1[1].re + e1[2].im, e1[1].im - e1[2].re};  // e1^1 - i e1^2
+  const cx<R> C11 = csub(e1[0], e1[3]);
+  const R B00 = k[0] - k[3], B11 = k[0] + k[3];
+  const cx<R> B01 = {-k[1], k[2]};   // -(k1 - i k2)
+  const cx<R> B10 = {-k[1], -k[2]};  // -(k1 + i k2)
+  const cx<R> y0 = cadd(cscale(C01, B00), cmul(B01, C11));
+  const cx<R> y1 = cadd(cmul(B10, C01), cscale(C11, B11));
+  return cadd(cmul(A00, y0), cmul(A01, y1));
+}
+
+// sum over q in {u, d} and quark helicity of |M|^2 (no averages)
+template <typename R>
+__device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p4[4], const R p5[4],
+                                    const R p6[4], R mp2, R mm2) {
+  cx<R> a3_0, a3_1, a4_0, a4_1, a5_0, a5_1, a6_0, a6_1;
+  spinor_m(p3, a3_0, a3_1);
+  spinor_m(p4, a4_0, a4_1);
+  spinor_m(p5, a5_0, a5_1);
+  spinor_m(p6, a6_0, a6_1);
+  cx<R> Jp[4], Jm[4];
+  current(a4_0, a4_1, a3_0, a3_1, Jp);  // ubar(nu) gamma P_L v(e+)
+  current(a5_0, a5_1, a6_0, a6_1, Jm);  // ubar(mu-) gamma P_L v(nubar)
+  const R MW2 = static_cast<R>(c.M2), MWGW = static_cast<R>(c.MG), gs = static_cast<R>(c.gs);
+  // g/sqrt2 / (m^2 - MW^2 + i MW GW)
+  const R dp = mp2 - MW2, dm = mm2 - MW2;
+  const R np = gs / (dp * dp + MWGW * MWGW), nm = gs / (dm * dm + MWGW * MWGW);
+  const cx<R> cp = {dp * np, -MWGW * np}, cm = {dm * nm, -MWGW * nm};
+  cx<R> ep[4], em[4];
+  R qp[4], qm[4], Ppq[4], Pmq[4], dq[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    ep[mu] = cmul(Jp[mu], cp);
+    em[mu] = cmul(Jm[mu], cm);
+    qp[mu] = p3[mu] + p4[mu];
+    qm[mu] = p5[mu] + p6[mu];
+  }
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const R PP = qp[mu] + qm[mu];
+    Ppq[mu] = PP + qp[mu];
+    Pmq[mu] = PP + qm[mu];
+    dq[mu] = qm[mu] - qp[mu];
+  }
+  // triple-gauge vertex contracted with ep, em
+  const cx<R> a1 = mdot_r(Ppq, em), a2 = mdot(ep, em), a3 = mdot_r(Pmq, ep);
+  cx<R> V1, V2;
+  V1 = csub(cadd(cmul(ep[1], a1), cscale(a2, dq[1])), cmul(em[1], a3));
+  V2 = csub(cadd(cmul(ep[2], a1), cscale(a2, dq[2])), cmul(em[2], a3));
+  const R rs = static_cast<R>(c.rs);
+  // j_L.V = -rs (V1 - i V2), j_R.V = -rs (V1 + i V2)
+  const cx<R> AL = {-rs * (V1.re + V2.im), -rs * (V1.im - V2.re)};
+  const cx<R> AR = {-rs * (V1.re - V2.im), -rs * (V1.im + V2.re)};
+  // exchange diagrams: u quark emits W+ first (k = p1 - qp), d quark emits W- first (k = p1 - qm);
+  // p1 = (rs/2, 0, 0, rs/2); vbar(p2) ... u(p1) picks -rs * [..]_{01}
+  const R half = rs * R(0.5);
+  R ku[4] = {half - qp[0], -qp[1], -qp[2], half - qp[3]};
+  R kd[4] = {half - qm[0], -qm[1], -qm[2], half - qm[3]};
+  const R tu = ku[0] * ku[0] - ku[1] * ku[1] - ku[2] * ku[2] - ku[3] * ku[3];
+  const R td = kd[0] * kd[0] - kd[1] * kd[1] - kd[2] * kd[2] - kd[3] * kd[3];
+  const cx<R> Tu = chain01(em, ku, ep);
+  const cx<R> Td = chain01(ep, kd, em);
+  const R ct = static_cast<R>(c.ct);
+  const R fu = -rs * ct / tu, fd = -rs * ct / td;
+  const cx<R> csuL = {static_cast<R>(c.cs_re[0][0]), static_cast<R>(c.cs_im[0][0])};
+  const cx<R> csdL = {static_cast<R>(c.cs_re[1][0]), static_cast<R>(c.cs_im[1][0])};
+  const cx<R> MuL = cadd(cmul(csuL, AL), cscale(Tu, fu));
+  const cx<R> MdL = cadd(cmul(csdL, AL), cscale(Td, fd));
+  return cabs2(MuL) + cabs2(MdL) + static_cast<R>(c.csR2) * cabs2(AR);
+}
+
+// rest frame of Q (mass m) -> frame of Q, for k and its back-to-back partner
+__device__ __forceinline__ void boost_pair(const double Q[4], double m, const double k[4],
+                                           double a[4], double b[4]) {
+  const double qk = Q[1] * k[1] + Q[2] * k[2] + Q[3] * k[3];
+  const double im = 1.0 / m, iqm = 1.0 / (Q[0] + m);
+  const double Ea = (Q[0] * k[0] + qk) * im;
+  const double Eb = (Q[0] * k[0] - qk) * im;
+  const double fa = (k[0] + Ea) * iqm, fb = (k[0] + Eb) * iqm;
+  a[0] = Ea;
+  b[0] = Eb;
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    a[i] = k[i] + fa * Q[i];
+    b[i] = -k[i] + fb * Q[i];
+  }
+}
+
+// WW_4L: x0 -> m+^2 (BW on [0, shat]), x1 -> m-^2 (BW on [0, (rs - m+)^2]),
+// x2, x3 -> W+ direction, x4..x7 -> lepton directions in the W rest frames.
+template <typename R>
+__device__ __forceinline__ double f_ww(const PhysConst& c, const double* x) {
+  double jp, jm;
+  const double mp2 = bw_map(x[0], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jp);
+  if (!(mp2 > 0.0)) return 0.0;
+  const double mp = sqrt(mp2);
+  const double up = (c.rs - mp) * (c.rs - mp);
+  const double rrng2 = atan((up - c.M2) / c.MG) - c.rho_lo;
+  const double mm2 = bw_map(x[1], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, rrng2, jm);
+  if (!(mm2 > 0.0)) return 0.0;
+  const double mm = sqrt(mm2);
+  const double sh = c.shat;
+  const double lam = (sh - mp2 - mm2) * (sh - mp2 - mm2) - 4.0 * mp2 * mm2;
+  if (!(lam > 0.0)) return 0.0;
+  const double sl = sqrt(lam);
+  const double i2rs = 1.0 / (2.0 * c.rs);
+  const double q = sl * i2rs;
+  const double Ep = (sh + mp2 - mm2) * i2rs, Em = (sh - mp2 + mm2) * i2rs;
+  const double ct = 2.0 * x[2] - 1.0, st = sqrt((1.0 - ct) * (1.0 + ct));
+  double sf, cf;
+  sincos(2.0 * kPi * x[3], &sf, &cf);
+  const double qp[4] = {Ep, q * st * cf, q * st * sf, q * ct};
+  const double qm[4] = {Em, -qp[1], -qp[2], -qp[3]};
+  double p3[4], p4[4], p5[4], p6[4];
+  {
+    const double c3 = 2.0 * x[4] - 1.0, s3 = sqrt((1.0 - c3) * (1.0 + c3));
+    double s, cc;
+    sincos(2.0 * kPi * x[5], &s, &cc);
+    const double h = 0.5 * mp;
+    const double k[4] = {h, h * s3 * cc, h * s3 * s, h * c3};
+    boost_pair(qp, mp, k, p3, p4);
+  }
+  {
+    const double c5 = 2.0 * x[6] - 1.0, s5 = sqrt((1.0 - c5) * (1.0 + c5));
+    double s, cc;
+    sincos(2.0 * kPi * x[7], &s, &cc);
+    const double h = 0.5 * mm;
+    const double k[4] = {h, h * s5 * cc, h * s5 * s, h * c5};
+    boost_pair(qm, mm, k, p5, p6);
+  }
+  R r3[4], r4[4], r5[4], r6[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r3[i] = static_cast<R>(p3[i]);
+    r4[i] = static_cast<R>(p4[i]);
+    r5[i] = static_cast<R>(p5[i]);
+    r6[i] = static_cast<R>(p6[i]);
+  }
+  const double me = static_cast<double>(
+      ww_me2<R>(c, r3, r4, r5, r6, static_cast<R>(mp2), static_cast<R>(mm2)));
+  // dPhi_2(P) (4 pi) * dm+^2/(2 pi) * dm-^2/(2 pi) * [dPhi_2(W) (4 pi)]^2
+  const double jac = sl / (8.0 * kPi * sh) * (jp / (2.0 * kPi)) * (jm / (2.0 * kPi)) *
+                     (1.0 / (64.0 * kPi * kPi));
+  return c.conv * (0.5 / sh) * (1.0 / 12.0) * me * jac;
+}
+
+}  // namespace vg

@@ -1,0 +1,1015 @@
+// vegas.hip -- gfx950 kernels and the C-ABI host library for the per-event
+// VEGAS iteration (Campbell, Ellis, Giele, "A Multi-Threaded Version of MCFM",
+// Sec. 2.1-2.2).
+//
+// One iteration is four launches on the handle's stream:
+//   k_event     one event per lane (grid-stride): Philox point -> grid map ->
+//               phase space -> PDFs x |M|^2 -> weight; writes the event record
+//               (w, packed bin indices) and the exact maxima that fix the
+//               fixed-point scales (max |w|, and max w^2 per grid bin).
+//   k_accum     reads the records and accumulates S1 = sum w, S2 = sum w^2 and
+//               d[dim][bin] = sum w^2 as exact integer digits (LDS atomics,
+//               then one global atomic per non-zero digit per block).
+//   k_finalize  one block: digits -> doubles, I_j, var_j, clears the digits.
+//   k_refine    (vegas_refine) one block, one wave per dimension: smoothing,
+//               damping, equal-importance rebinning.
+// Integer accumulation is associative, so every launch configuration gives
+// byte-identical results (the paper's independence from the thread count,
+// Sec. 2.2, made structural).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vegas.h"
+#include "device_common.hpp"
+#include "integrands.hpp"
+
+namespace vg {
+
+constexpr int kWave = 64;
+constexpr int kMaxGrid = 4096;  // default cap on blocks per launch (grid-stride beyond)
+
+struct DevBufs {
+  double* edges;            // [D][n+1]
+  double* rec_w;            // [maxN]
+  uint32_t* rec_bins;       // [ceil(D/4)][maxN], 4 bins of 8 bits per word
+  unsigned long long* maxw; // [1] bits of max |w| ; [1] spare
+  unsigned long long* binmax;  // [D*n] bits of max w^2 per bin
+  long long* acc;           // [(2 + D*n) * 3] digit sums
+  unsigned long long* cnt;  // [2] n_nonzero, n_nonfinite
+  double* hist;             // [D*n + 2] d, S1, S2 of the last iteration
+  double* history;          // [VEGAS_MAX_ITER][2] I_j, var_j
+  double* iter_out;         // [8] I_j, var_j, nz, nnf (as doubles), n
+  double* result;           // [4] I, sigma, chi2/dof, n_iter
+  int* scale;               // [2 + D*n] fixed-point exponents of the last iteration
+};
+
+// ---------------------------------------------------------------------------
+// grid map: k = floor(u n) clamped, delta = u n - k, x = fma(delta, h, e_k),
+// J = prod n h (plain roundings, no contraction)
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ double grid_map(const double* __restrict__ e_lds, int n, int ndim,
+                                           const double* u, double* x, int* bins) {
+#pragma clang fp contract(off)
+  const int nd = D > 0 ? D : ndim;
+  const double dn = static_cast<double>(n);
+  double J = 1.0;
+#pragma unroll
+  for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
+    if (d >= nd) break;
+    const double t = u[d] * dn;
+    int k = static_cast<int>(t);
+    k = k > n - 1 ? n - 1 : k;
+    const double delta = t - static_cast<double>(k);
+    const double* e = e_lds + d * (n + 1);
+    const double lo = e[k];
+    const double h = e[k + 1] - lo;
+    x[d] = __fma_rn(delta, h, lo);
+    J *= dn * h;
+    bins[d] = k;
+  }
+  return J;
+}
+
+template <int PROC, int PREC, int D>
+__device__ __forceinline__ double integrand(const PhysConst& c, const double* x) {
+  if constexpr (PROC == VEGAS_GAUSS) return f_gauss<D>(c, x);
+  else if constexpr (PROC == VEGAS_GENZ) return f_genz<D>(c, x);
+  else if constexpr (PROC == VEGAS_EEMUMU) return f_eemumu(c, x);
+  else if constexpr (PROC == VEGAS_DY_Z) return f_dy(c, x);
+  else if constexpr (PROC == VEGAS_W_PLUS) return f_w(c, x);
+  else if constexpr (PREC == VEGAS_FP32_ME) return f_ww<float>(c, x);
+  else return f_ww<double>(c, x);
+}
+
+struct EventArgs {
+  PhysConst pc;
+  DevBufs b;
+  uint64_t seed;
+  int64_t nev;
+  int64_t stride_rec;  // maxN (record plane stride)
+  uint32_t iter;
+  int ndim, nbins;
+};
+
+// ---------------------------------------------------------------------------
+// K1: events
+// ---------------------------------------------------------------------------
+template <int PROC, int PREC, int D, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_event(EventArgs a) {
+  extern __shared__ unsigned char smem[];
+  const int n = a.nbins, nd = D > 0 ? D : a.ndim;
+  double* e_lds = reinterpret_cast<double*>(smem);
+  unsigned long long* bmax = reinterpret_cast<unsigned long long*>(e_lds + nd * (n + 1));
+  for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x) e_lds[i] = a.b.edges[i];
+  for (int i = threadIdx.x; i < nd * n; i += blockDim.x) bmax[i] = 0ull;
+  __syncthreads();
+
+  unsigned long long wmax = 0ull, nz = 0ull, nnf = 0ull;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
+    double u[D > 0 ? D : VEGAS_MAX_DIM], x[D > 0 ? D : VEGAS_MAX_DIM];
+    int bins[D > 0 ? D : VEGAS_MAX_DIM];
+    event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
+    const double J = grid_map<D>(e_lds, n, nd, u, x, bins);
+    const double f = integrand<PROC, PREC, D>(a.pc, x);
+    double w = J * f;
+    double w2 = w * w;
+    if (!isfinite(w2)) {
+      ++nnf;
+      w = 0.0;
+      w2 = 0.0;
+    } else if (w != 0.0) {
+      ++nz;
+    }
+    a.b.rec_w[i] = w;
+#pragma unroll
+    for (int g = 0; g < (D > 0 ? (D + 3) / 4 : 4); ++g) {
+      if (4 * g >= nd) break;
+      uint32_t word = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 * g + j < nd) word |= static_cast<uint32_t>(bins[4 * g + j]) << (8 * j);
+      a.b.rec_bins[g * a.stride_rec + i] = word;
+    }
+    const unsigned long long wb = static_cast<unsigned long long>(__double_as_longlong(fabs(w)));
+    wmax = wb > wmax ? wb : wmax;
+    if (w2 != 0.0) {
+      const unsigned long long b2 = static_cast<unsigned long long>(__double_as_longlong(w2));
+#pragma unroll
+      for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
+        if (d >= nd) break;
+        atomicMax(&bmax[d * n + bins[d]], b2);
+      }
+    }
+  }
+  wmax = wave_max_u64(wmax);
+  const long long snz = wave_sum_i64(static_cast<long long>(nz));
+  const long long snf = wave_sum_i64(static_cast<long long>(nnf));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (wmax) atomicMax(&a.b.maxw[0], wmax);
+    if (snz) atomicAdd(&a.b.cnt[0], static_cast<unsigned long long>(snz));
+    if (snf) atomicAdd(&a.b.cnt[1], static_cast<unsigned long long>(snf));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nd * n; i += blockDim.x)
+    if (bmax[i]) atomicMax(&a.b.binmax[i], bmax[i]);
+}
+
+// ---------------------------------------------------------------------------
+// K2: exact accumulation of S1, S2 and d from the records
+// ---------------------------------------------------------------------------
+struct AccArgs {
+  DevBufs b;
+  int64_t nev;
+  int64_t stride_rec;
+  int ndim, nbins;
+};
+
+__global__ void k_accum(AccArgs a) {
+  extern __shared__ unsigned char smem[];
+  const int n = a.nbins, nd = a.ndim, nslot = nd * n;
+  long long* acc = reinterpret_cast<long long*>(smem);  // [nslot][3]
+  int* esc = reinterpret_cast<int*>(acc + 3 * nslot);     // [nslot]
+  for (int i = threadIdx.x; i < 3 * nslot; i += blockDim.x) acc[i] = 0;
+  for (int i = threadIdx.x; i < nslot; i += blockDim.x)
+    esc[i] = fx_exponent(__longlong_as_double(static_cast<long long>(a.b.binmax[i])));
+  const double wmax = __longlong_as_double(static_cast<long long>(a.b.maxw[0]));
+  const int E1 = fx_exponent(wmax);
+  const int E2 = fx_exponent(wmax * wmax);
+  __syncthreads();
+
+  long long s1_0 = 0, s1_1 = 0, s1_2 = 0, s2_0 = 0, s2_1 = 0, s2_2 = 0;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
+    const double w = a.b.rec_w[i];
+    if (w == 0.0) continue;
+    const double w2 = w * w;
+    long long d0, d1, d2;
+    fx_digits(w, E1, d0, d1, d2);
+    s1_0 += d0;
+    s1_1 += d1;
+    s1_2 += d2;
+    fx_digits(w2, E2, d0, d1, d2);
+    s2_0 += d0;
+    s2_1 += d1;
+    s2_2 += d2;
+    for (int g = 0; 4 * g < nd; ++g) {
+      const uint32_t word = a.b.rec_bins[g * a.stride_rec + i];
+      for (int j = 0; j < 4 && 4 * g + j < nd; ++j) {
+        const int d = 4 * g + j;
+        const int slot = d * n + static_cast<int>((word >> (8 * j)) & 0xffu);
+        fx_digits(w2, esc[slot], d0, d1, d2);
+        unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + 3 * slot);
+        if (d0) atomicAdd(p + 0, static_cast<unsigned long long>(d0));
+        if (d1) atomicAdd(p + 1, static_cast<unsigned long long>(d1));
+        if (d2) atomicAdd(p + 2, static_cast<unsigned long long>(d2));
+      }
+    }
+  }
+  // S1, S2: per-lane registers -> wave butterfly -> one global atomic per wave
+  s1_0 = wave_sum_i64(s1_0);
+  s1_1 = wave_sum_i64(s1_1);
+  s1_2 = wave_sum_i64(s1_2);
+  s2_0 = wave_sum_i64(s2_0);
+  s2_1 = wave_sum_i64(s2_1);
+  s2_2 = wave_sum_i64(s2_2);
+  unsigned long long* g = reinterpret_cast<unsigned long long*>(a.b.acc);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (s1_0) atomicAdd(g + 0, static_cast<unsigned long long>(s1_0));
+    if (s1_1) atomicAdd(g + 1, static_cast<unsigned long long>(s1_1));
+    if (s1_2) atomicAdd(g + 2, static_cast<unsigned long long>(s1_2));
+    if (s2_0) atomicAdd(g + 3, static_cast<unsigned long long>(s2_0));
+    if (s2_1) atomicAdd(g + 4, static_cast<unsigned long long>(s2_1));
+    if (s2_2) atomicAdd(g + 5, static_cast<unsigned long long>(s2_2));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * nslot; i += blockDim.x)
+    if (acc[i]) atomicAdd(g + 6 + i, static_cast<unsigned long long>(acc[i]));
+}
+
+// ---------------------------------------------------------------------------
+// K3: digits -> doubles, I_j and var_j; clear the accumulators for the next iteration
+// ---------------------------------------------------------------------------
+__global__ void k_finalize(DevBufs b, int ndim, int nbins, int64_t nev, uint32_t iter) {
+  const int nslot = ndim * nbins;
+  const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
+  const int E1 = fx_exponent(wmax), E2 = fx_exponent(wmax * wmax);
+  for (int s = threadIdx.x; s < nslot + 2; s += blockDim.x) {
+    int E;
+    long long* p;
+    double* out;
+    if (s < nslot) {
+      E = fx_exponent(__longlong_as_double(static_cast<long long>(b.binmax[s])));
+      p = b.acc + 6 + 3 * s;
+      out = b.hist + s;
+    } else {
+      E = s == nslot ? E1 : E2;
+      p = b.acc + 3 * (s - nslot);
+      out = b.hist + s;
+    }
+    *out = fx_value(p[0], p[1], p[2], E);
+    b.scale[s] = E;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double S1 = b.hist[nslot], S2 = b.hist[nslot + 1];
+    const double N = static_cast<double>(nev);
+    const double I = S1 / N;
+    const double var = fma(-I, I, S2 / N) / (N - 1.0);
+    b.history[2 * iter] = I;
+    b.history[2 * iter + 1] = var;
+    b.iter_out[0] = I;
+    b.iter_out[1] = var;
+    b.iter_out[2] = static_cast<double>(b.cnt[0]);
+    b.iter_out[3] = static_cast<double>(b.cnt[1]);
+    b.iter_out[4] = N;
+    b.cnt[0] = 0;
+    b.cnt[1] = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * (nslot + 2); i += blockDim.x) b.acc[i] = 0;
+  for (int i = threadIdx.x; i < nslot; i += blockDim.x) b.binmax[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) b.maxw[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// K4: grid refinement, one single-wave block per dimension
+// ---------------------------------------------------------------------------
+__global__ void k_refine(DevBufs b, int nbins, double alpha) {
+  __shared__ double dm[VEGAS_MAX_BINS + 1];   // smoothed histogram, then damped importance
+  __shared__ double en[VEGAS_MAX_BINS + 1];   // new edges
+  __shared__ double ssum[2];
+  const int d = blockIdx.x, lane = threadIdx.x;
+  const int n = nbins;
+  const double* h = b.hist + d * n;
+  double* e = b.edges + d * (n + 1);
+  for (int k = lane; k < n; k += kWave) {
+    double v;
+    if (k == 0) v = (h[0] + h[1]) / 2.0;
+    else if (k == n - 1) v = (h[n - 2] + h[n - 1]) / 2.0;
+    else v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
+    dm[k] = v;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double s = 0.0, sb = 0.0;
+    for (int k = 0; k < n; ++k) {
+      s += h[k];
+      sb += dm[k];
+    }
+    ssum[0] = s;
+    ssum[1] = sb;
+  }
+  __syncthreads();
+  if (!(ssum[0] > 0.0)) return;  // whole block: empty histogram keeps this dimension's grid
+  const double sb = ssum[1];
+  for (int k = lane; k < n; k += kWave) {
+    const double r = dm[k] / sb;
+    double m;
+    if (r == 0.0) m = 0.0;
+    else if (r == 1.0) m = 1.0;
+    else m = pow((r - 1.0) / log(r), alpha);
+    dm[k] = m;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double msum = 0.0;
+    for (int k = 0; k < n; ++k) msum += dm[k];
+    const double stp = msum / n;
+    en[0] = 0.0;
+    en[n] = 1.0;
+    int j = 0;
+    double cum = 0.0;
+    for (int k = 1; k < n; ++k) {
+      const double target = k * stp;
+      while (j < n - 1 && cum + dm[j] < target) {
+        cum += dm[j];
+        ++j;
+      }
+      double frac = dm[j] > 0.0 ? (target - cum) / dm[j] : 0.0;
+      frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+      en[k] = e[j] + frac * (e[j + 1] - e[j]);
+    }
+  }
+  __syncthreads();
+  for (int k = lane; k <= n; k += kWave) e[k] = en[k];
+}
+
+// ---------------------------------------------------------------------------
+// K5: inverse-variance combination over the iterations
+// ---------------------------------------------------------------------------
+__global__ void k_result(DevBufs b, int n_iter) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int nzero = 0;
+  double zsum = 0.0, ws = 0.0, iws = 0.0;
+  for (int j = 0; j < n_iter; ++j) {
+    const double I = b.history[2 * j], v = b.history[2 * j + 1];
+    if (v <= 0.0) {
+      ++nzero;
+      zsum += I;
+    } else {
+      ws += 1.0 / v;
+      iws += I / v;
+    }
+  }
+  if (nzero) {
+    b.result[0] = zsum / nzero;
+    b.result[1] = 0.0;
+    b.result[2] = 0.0;
+  } else {
+    const double I = iws / ws;
+    double chi = 0.0;
+    for (int j = 0; j < n_iter; ++j) {
+      const double dI = b.history[2 * j] - I;
+      chi += dI * dI / b.history[2 * j + 1];
+    }
+    b.result[0] = I;
+    b.result[1] = sqrt(1.0 / ws);
+    b.result[2] = n_iter > 1 ? chi / (n_iter - 1) : 0.0;
+  }
+  b.result[3] = n_iter;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0ull;
+}
+
+__global__ void k_uniform_grid(double* edges, int ndim, int nbins) {
+  for (int i = threadIdx.x; i < ndim * (nbins + 1); i += blockDim.x) {
+    const int k = i % (nbins + 1);
+    edges[i] = static_cast<double>(k) / nbins;
+  }
+}
+
+}  // namespace vg
+
+// ===========================================================================
+// host library
+// ===========================================================================
+using namespace vg;
+
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+struct Layout {
+  size_t edges, rec_w, rec_bins, maxw, binmax, acc, cnt, hist, history, iter_out, result, scale, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+Layout make_layout(int D, int n, int64_t maxN) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const int words = (D + 3) / 4;
+  L.edges = take(sizeof(double) * D * (n + 1));
+  L.rec_w = take(sizeof(double) * maxN);
+  L.rec_bins = take(sizeof(uint32_t) * words * maxN);
+  L.maxw = take(sizeof(unsigned long long) * 2);
+  L.binmax = take(sizeof(unsigned long long) * D * n);
+  L.acc = take(sizeof(long long) * 3 * (2 + D * n));
+  L.cnt = take(sizeof(unsigned long long) * 2);
+  L.hist = take(sizeof(double) * (D * n + 2));
+  L.history = take(sizeof(double) * 2 * VEGAS_MAX_ITER);
+  L.iter_out = take(sizeof(double) * 8);
+  L.result = take(sizeof(double) * 4);
+  L.scale = take(sizeof(int) * (D * n + 2));
+  L.total = off;
+  return L;
+}
+
+int process_ndim(int process, int requested) {
+  switch (process) {
+    case VEGAS_GAUSS:
+    case VEGAS_GENZ: return requested;
+    case VEGAS_EEMUMU: return 2;
+    case VEGAS_DY_Z: return 3;
+    case VEGAS_W_PLUS: return 4;
+    case VEGAS_WW_4L: return 8;
+    default: return -1;
+  }
+}
+
+int validate(const vegas_config* c, int64_t max_events) {
+  if (!c) return VEGAS_EINVAL;
+  if (c->process < VEGAS_GAUSS || c->process > VEGAS_WW_4L) return VEGAS_EINVAL;
+  const int D = process_ndim(c->process, c->ndim);
+  if (D < 1 || D > VEGAS_MAX_DIM || D != c->ndim) return VEGAS_EINVAL;
+  if (c->nbins < 2 || c->nbins > VEGAS_MAX_BINS) return VEGAS_EINVAL;
+  if (!(c->alpha >= 0.0) || !std::isfinite(c->alpha)) return VEGAS_EINVAL;
+  if (c->nparams < 0 || c->nparams > VEGAS_MAX_PARAMS) return VEGAS_EINVAL;
+  if (c->nparams > 0 && !c->params) return VEGAS_EINVAL;
+  if (c->precision != VEGAS_FP64 && c->precision != VEGAS_FP32_ME) return VEGAS_EINVAL;
+  if (c->precision == VEGAS_FP32_ME && c->process != VEGAS_WW_4L) return VEGAS_EINVAL;
+  const int w = c->waves_per_block;
+  if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8 || w == 16)) return VEGAS_EINVAL;
+  if (c->max_blocks < 0) return VEGAS_EINVAL;
+  if (max_events < 2 || max_events >= (int64_t(1) << 31)) return VEGAS_EINVAL;
+  switch (c->process) {
+    case VEGAS_GAUSS:
+      if (c->nparams < 2 || !(c->params[1] > 0.0)) return VEGAS_EINVAL;
+      break;
+    case VEGAS_GENZ:
+      if (c->nparams < 1 + 2 * D) return VEGAS_EINVAL;
+      break;
+    default:
+      if (c->nparams < VEGAS_NPHYS) return VEGAS_EINVAL;
+  }
+  return VEGAS_OK;
+}
+
+// configuration-wide constants, computed once on the host
+PhysConst make_consts(const vegas_config* c, const double* p) {
+  PhysConst k;
+  std::memset(&k, 0, sizeof(k));
+  k.process = c->process;
+  k.ndim = c->ndim;
+  k.nbins = c->nbins;
+  if (c->process == VEGAS_GAUSS) {
+    const double mu = p[0], sg = p[1];
+    k.mu = mu;
+    k.inv2s2 = 1.0 / (2.0 * sg * sg);
+    k.gnorm = 1.0 / (sg * std::sqrt(2.0 * kPi));
+    return k;
+  }
+  if (c->process == VEGAS_GENZ) {
+    k.family = static_cast<int>(p[0]);
+    for (int d = 0; d < c->ndim; ++d) {
+      k.ga[d] = p[1 + d];
+      k.gw[d] = p[1 + c->ndim + d];
+    }
+    return k;
+  }
+  const double alpha = p[VEGAS_P_ALPHA], sw2 = p[VEGAS_P_SW2];
+  const double MZ = p[VEGAS_P_MZ], GZ = p[VEGAS_P_GZ], MW = p[VEGAS_P_MW], GW = p[VEGAS_P_GW];
+  const double rs = p[VEGAS_P_SQRTS];
+  const double sw = std::sqrt(sw2), cw = std::sqrt(1.0 - sw2);
+  const double e2 = 4.0 * kPi * alpha;
+  const double g2 = e2 / sw2;
+  k.conv = p[VEGAS_P_CONV];
+  k.pdfA = p[VEGAS_P_PDF_A];
+  k.pdfa = p[VEGAS_P_PDF_a];
+  k.pdfb = p[VEGAS_P_PDF_b];
+  k.invS = 1.0 / (rs * rs);
+  k.e4 = e2 * e2;
+  k.s_ee = rs * rs;
+  if (c->process == VEGAS_DY_Z) {
+    k.M2 = MZ * MZ;
+    k.MG = MZ * GZ;
+    const double lo = p[VEGAS_P_MLO], hi = p[VEGAS_P_MHI] > 0 ? p[VEGAS_P_MHI] : rs;
+    k.m2lo = lo * lo;
+    k.tlo = (k.m2lo - MZ * MZ) / k.MG;
+    k.rho_lo = std::atan(k.tlo);
+    k.rho_rng = std::atan((hi * hi - MZ * MZ) / k.MG) - k.rho_lo;
+    k.mz2 = MZ * MZ;
+    k.mzgz = MZ * GZ;
+    k.e4_12 = e2 * e2 / 12.0;
+    const double gl[2] = {(-0.5 + sw2) / (sw * cw), sw / cw};
+    for (int q = 0; q < 2; ++q) {
+      const double Q = q == 0 ? 2.0 / 3.0 : -1.0 / 3.0, T3 = q == 0 ? 0.5 : -0.5;
+      const double gq[2] = {(T3 - Q * sw2) / (sw * cw), -Q * sw / cw};
+      k.qql[q] = -Q;
+      for (int h = 0; h < 2; ++h)
+        for (int hp = 0; hp < 2; ++hp) k.gg[q][2 * h + hp] = gq[h] * gl[hp];
+    }
+  } else if (c->process == VEGAS_W_PLUS) {
+    k.M2 = MW * MW;
+    k.MG = MW * GW;
+    const double lo = p[VEGAS_P_MLO], hi = p[VEGAS_P_MHI] > 0 ? p[VEGAS_P_MHI] : rs;
+    k.m2lo = lo * lo;
+    k.tlo = (k.m2lo - MW * MW) / k.MG;
+    k.rho_lo = std::atan(k.tlo);
+    k.rho_rng = std::atan((hi * hi - MW * MW) / k.MG) - k.rho_lo;
+    const double v = p[VEGAS_P_VUD];
+    k.g4v2_24 = g2 * g2 * v * v / 24.0;
+    k.ptmin2 = p[VEGAS_P_PTMIN] * p[VEGAS_P_PTMIN];
+    const double th = std::tanh(p[VEGAS_P_ETAMAX]);
+    k.th2 = th * th;
+  } else if (c->process == VEGAS_WW_4L) {
+    k.M2 = MW * MW;
+    k.MG = MW * GW;
+    k.rs = rs;
+    k.shat = rs * rs;
+    k.m2lo = 0.0;
+    k.tlo = (0.0 - MW * MW) / k.MG;
+    k.rho_lo = std::atan(k.tlo);
+    k.rho_rng = std::atan((k.shat - MW * MW) / k.MG) - k.rho_lo;
+    k.gs = std::sqrt(g2) / std::sqrt(2.0);
+    k.ct = -0.5 * g2;
+    // Cs = e^2 (Q/shat + gZ (cw/sw) / (shat - MZ^2 + i MZ GZ))
+    const double dr = k.shat - MZ * MZ, di = MZ * GZ, dd = dr * dr + di * di;
+    double csr2 = 0.0;
+    for (int q = 0; q < 2; ++q) {
+      const double Q = q == 0 ? 2.0 / 3.0 : -1.0 / 3.0, T3 = q == 0 ? 0.5 : -0.5;
+      for (int h = 0; h < 2; ++h) {
+        const double gz = h == 0 ? (T3 - Q * sw2) / (sw * cw) : -Q * sw / cw;
+        const double f = gz * cw / sw;
+        k.cs_re[q][h] = e2 * (Q / k.shat + f * dr / dd);
+        k.cs_im[q][h] = e2 * (-f * di / dd);
+      }
+      csr2 += k.cs_re[q][1] * k.cs_re[q][1] + k.cs_im[q][1] * k.cs_im[q][1];
+    }
+    k.csR2 = csr2;
+  }
+  return k;
+}
+
+}  // namespace
+
+struct vegas_state {
+  vegas_config cfg;
+  double params[VEGAS_MAX_PARAMS];
+  int D, n;
+  int64_t maxN;
+  hipStream_t stream;
+  int device;
+  void* base;
+  bool owns;
+  Layout L;
+  DevBufs b;
+  PhysConst pc;
+  uint32_t iter;      // next iteration index
+  bool have_hist;     // an iteration ran since init / the last refine
+  bool any_iter;
+  int64_t last_n;
+  int wpb, max_blocks;
+  int event_lds;
+  // optional per-stage kernel timing with HIP events on the handle's stream
+  bool timing;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;  // (stage, start/stop)
+  double stage_ms[4];
+  int64_t stage_n[4];
+};
+
+#define VG_HIP(call)                                                  \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) {                                           \
+      g_last_hip_error = std::string(#call) + ": " + hipGetErrorString(e_); \
+      return VEGAS_EHIP;                                              \
+    }                                                                 \
+  } while (0)
+
+namespace {
+
+int pick_threads(const vegas_state* h) { return kWave * (h->wpb > 0 ? h->wpb : 4); }
+
+int pick_blocks(const vegas_state* h, int64_t nev, int threads) {
+  int64_t nb = (nev + threads - 1) / threads;
+  const int cap = h->max_blocks > 0 ? h->max_blocks : kMaxGrid;
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  return static_cast<int>(nb);
+}
+
+// two instantiations per integrand: up to 4 waves per block (the register budget of a
+// 256-thread block, the performance path) and up to 16 waves (for the launch knob)
+hipEvent_t pool_event(vegas_state* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// record a start event before a stage's launch (no-op unless timing is on)
+hipEvent_t stage_begin(vegas_state* h) {
+  if (!h->timing) return nullptr;
+  hipEvent_t e = pool_event(h);
+  if (e) (void)hipEventRecord(e, h->stream);
+  return e;
+}
+
+void stage_end(vegas_state* h, int stage, hipEvent_t start) {
+  if (!h->timing || !start) return;
+  hipEvent_t e = pool_event(h);
+  if (!e) return;
+  (void)hipEventRecord(e, h->stream);
+  h->ev_pending.push_back({stage, {start, e}});
+}
+
+// fold finished event pairs into the per-stage totals (the stream must be idle)
+void stage_collect(vegas_state* h) {
+  for (auto& p : h->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+      h->stage_ms[p.first] += ms;
+      h->stage_n[p.first] += 1;
+    }
+    h->ev_pool.push_back(p.second.first);
+    h->ev_pool.push_back(p.second.second);
+  }
+  h->ev_pending.clear();
+}
+
+template <int PROC, int PREC, int D>
+hipError_t launch_event_t(const EventArgs& a, int blocks, int threads, int lds, hipStream_t s) {
+  if (threads <= 256)
+    hipLaunchKernelGGL((k_event<PROC, PREC, D, 256>), dim3(blocks), dim3(threads), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_event<PROC, PREC, D, 1024>), dim3(blocks), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_event(const vegas_state* h, const EventArgs& a, int blocks, int threads) {
+  const int lds = h->event_lds;
+  hipStream_t s = h->stream;
+  switch (h->cfg.process) {
+    case VEGAS_GAUSS: return launch_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(a, blocks, threads, lds, s);
+    case VEGAS_GENZ: return launch_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(a, blocks, threads, lds, s);
+    case VEGAS_EEMUMU: return launch_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(a, blocks, threads, lds, s);
+    case VEGAS_DY_Z: return launch_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(a, blocks, threads, lds, s);
+    case VEGAS_W_PLUS: return launch_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(a, blocks, threads, lds, s);
+    case VEGAS_WW_4L:
+      if (h->cfg.precision == VEGAS_FP32_ME)
+        return launch_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(a, blocks, threads, lds, s);
+      return launch_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(a, blocks, threads, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vegas_strerror(int status) {
+  switch (status) {
+    case VEGAS_OK: return "ok";
+    case VEGAS_EINVAL: return "invalid configuration or argument";
+    case VEGAS_ESTATE: return "call out of order";
+    case VEGAS_ENOMEM: return "workspace too small or device allocation failed";
+    case VEGAS_EHIP: return g_last_hip_error.empty() ? "HIP runtime error" : g_last_hip_error.c_str();
+    default: return "unknown status";
+  }
+}
+
+int vegas_workspace_size(const vegas_config* cfg, int64_t max_events, size_t* bytes) {
+  const int v = validate(cfg, max_events);
+  if (v != VEGAS_OK) return v;
+  if (!bytes) return VEGAS_EINVAL;
+  *bytes = make_layout(cfg->ndim, cfg->nbins, max_events).total;
+  return VEGAS_OK;
+}
+
+int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, size_t ws_bytes,
+               void* stream, vegas_handle* out) {
+  if (!out) return VEGAS_EINVAL;
+  *out = nullptr;
+  const int v = validate(cfg, max_events);
+  if (v != VEGAS_OK) return v;
+  const int D = cfg->ndim, n = cfg->nbins;
+  Layout L = make_layout(D, n, max_events);
+  if (workspace && (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255)))
+    return VEGAS_ENOMEM;
+  vegas_state* h = new (std::nothrow) vegas_state();
+  if (!h) return VEGAS_ENOMEM;
+  h->cfg = *cfg;
+  std::memset(h->params, 0, sizeof(h->params));
+  if (cfg->nparams) std::memcpy(h->params, cfg->params, sizeof(double) * cfg->nparams);
+  h->cfg.params = h->params;
+  h->D = D;
+  h->n = n;
+  h->maxN = max_events;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->L = L;
+  h->wpb = cfg->waves_per_block;
+  h->max_blocks = cfg->max_blocks;
+  h->event_lds = static_cast<int>(sizeof(double) * D * (n + 1) + sizeof(unsigned long long) * D * n);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return VEGAS_EHIP;
+  }
+  if (workspace) {
+    h->base = workspace;
+    h->owns = false;
+  } else {
+    if (hipMalloc(&h->base, L.total) != hipSuccess) {
+      delete h;
+      return VEGAS_ENOMEM;
+    }
+    h->owns = true;
+  }
+  char* B = static_cast<char*>(h->base);
+  h->b.edges = reinterpret_cast<double*>(B + L.edges);
+  h->b.rec_w = reinterpret_cast<double*>(B + L.rec_w);
+  h->b.rec_bins = reinterpret_cast<uint32_t*>(B + L.rec_bins);
+  h->b.maxw = reinterpret_cast<unsigned long long*>(B + L.maxw);
+  h->b.binmax = reinterpret_cast<unsigned long long*>(B + L.binmax);
+  h->b.acc = reinterpret_cast<long long*>(B + L.acc);
+  h->b.cnt = reinterpret_cast<unsigned long long*>(B + L.cnt);
+  h->b.hist = reinterpret_cast<double*>(B + L.hist);
+  h->b.history = reinterpret_cast<double*>(B + L.history);
+  h->b.iter_out = reinterpret_cast<double*>(B + L.iter_out);
+  h->b.result = reinterpret_cast<double*>(B + L.result);
+  h->b.scale = reinterpret_cast<int*>(B + L.scale);
+  h->pc = make_consts(&h->cfg, h->params);
+  // zero the small state (accumulators, maxima, counters, history) with a fill kernel
+  const size_t small_begin = L.maxw, small_end = L.total;
+  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, h->stream,
+                     reinterpret_cast<unsigned long long*>(B + small_begin),
+                     static_cast<int64_t>((small_end - small_begin) / 8));
+  hipLaunchKernelGGL(k_uniform_grid, dim3(1), dim3(256), 0, h->stream, h->b.edges, D, n);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+    g_last_hip_error = "vegas_init: initial fill failed";
+    if (h->owns) (void)hipFree(h->base);
+    delete h;
+    return VEGAS_EHIP;
+  }
+  *out = h;
+  return VEGAS_OK;
+}
+
+int vegas_destroy(vegas_handle h) {
+  if (!h) return VEGAS_EINVAL;
+  int rc = VEGAS_OK;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) rc = VEGAS_EHIP;
+  for (auto& p : h->ev_pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->owns) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = VEGAS_EHIP;
+    if (hipFree(h->base) != hipSuccess) rc = VEGAS_EHIP;
+  }
+  delete h;
+  return rc;
+}
+
+int vegas_set_timing(vegas_handle h, int32_t enable) {
+  if (!h) return VEGAS_EINVAL;
+  h->timing = enable != 0;
+  return VEGAS_OK;
+}
+
+int vegas_stage_times(vegas_handle h, double* ms, int64_t* launches, int32_t reset) {
+  if (!h) return VEGAS_EINVAL;
+  VG_HIP(hipStreamSynchronize(h->stream));
+  stage_collect(h);
+  for (int i = 0; i < 4; ++i) {
+    if (ms) ms[i] = h->stage_ms[i];
+    if (launches) launches[i] = h->stage_n[i];
+  }
+  if (reset)
+    for (int i = 0; i < 4; ++i) {
+      h->stage_ms[i] = 0.0;
+      h->stage_n[i] = 0;
+    }
+  return VEGAS_OK;
+}
+
+int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks) {
+  if (!h) return VEGAS_EINVAL;
+  const int w = waves_per_block;
+  if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8 || w == 16) || max_blocks < 0) return VEGAS_EINVAL;
+  h->wpb = w;
+  h->max_blocks = max_blocks;
+  return VEGAS_OK;
+}
+
+int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
+  if (!h) return VEGAS_EINVAL;
+  if (n_events < 2 || n_events > h->maxN) return VEGAS_EINVAL;
+  if (h->iter >= VEGAS_MAX_ITER) return VEGAS_ESTATE;
+  const int threads = pick_threads(h);
+  EventArgs ea;
+  ea.pc = h->pc;
+  ea.b = h->b;
+  ea.seed = h->cfg.seed;
+  ea.nev = n_events;
+  ea.stride_rec = h->maxN;
+  ea.iter = h->iter;
+  ea.ndim = h->D;
+  ea.nbins = h->n;
+  hipEvent_t t0 = stage_begin(h);
+  VG_HIP(launch_event(h, ea, pick_blocks(h, n_events, threads), threads));
+  stage_end(h, 0, t0);
+  AccArgs aa;
+  aa.b = h->b;
+  aa.nev = n_events;
+  aa.stride_rec = h->maxN;
+  aa.ndim = h->D;
+  aa.nbins = h->n;
+  const int acc_lds = static_cast<int>(sizeof(long long) * 3 * h->D * h->n + sizeof(int) * h->D * h->n);
+  t0 = stage_begin(h);
+  hipLaunchKernelGGL(k_accum, dim3(pick_blocks(h, n_events, threads)), dim3(threads), acc_lds, h->stream, aa);
+  VG_HIP(hipGetLastError());
+  stage_end(h, 1, t0);
+  t0 = stage_begin(h);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->b, h->D, h->n, n_events, h->iter);
+  VG_HIP(hipGetLastError());
+  stage_end(h, 2, t0);
+  const uint32_t j = h->iter;
+  h->iter++;
+  h->have_hist = true;
+  h->any_iter = true;
+  h->last_n = n_events;
+  if (out) {
+    double o[5];
+    VG_HIP(hipMemcpyAsync(o, h->b.iter_out, sizeof(o), hipMemcpyDeviceToHost, h->stream));
+    VG_HIP(hipStreamSynchronize(h->stream));
+    out->integral = o[0];
+    out->variance = o[1];
+    out->n_nonzero = static_cast<int64_t>(o[2]);
+    out->n_nonfinite = static_cast<int64_t>(o[3]);
+    out->n_events = n_events;
+    out->iteration = j;
+  }
+  return VEGAS_OK;
+}
+
+int vegas_refine(vegas_handle h) {
+  if (!h) return VEGAS_EINVAL;
+  if (!h->have_hist) return VEGAS_ESTATE;
+  hipEvent_t t0 = stage_begin(h);
+  hipLaunchKernelGGL(k_refine, dim3(h->D), dim3(kWave), 0, h->stream, h->b, h->n, h->cfg.alpha);
+  VG_HIP(hipGetLastError());
+  stage_end(h, 3, t0);
+  h->have_hist = false;
+  return VEGAS_OK;
+}
+
+int vegas_result(vegas_handle h, double* integral, double* error, double* chi2_dof, int32_t* n_iter) {
+  if (!h) return VEGAS_EINVAL;
+  if (!h->any_iter || h->iter == 0) return VEGAS_ESTATE;
+  hipLaunchKernelGGL(k_result, dim3(1), dim3(64), 0, h->stream, h->b, static_cast<int>(h->iter));
+  VG_HIP(hipGetLastError());
+  double r[4];
+  VG_HIP(hipMemcpyAsync(r, h->b.result, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  if (integral) *integral = r[0];
+  if (error) *error = r[1];
+  if (chi2_dof) *chi2_dof = r[2];
+  if (n_iter) *n_iter = static_cast<int32_t>(r[3]);
+  return VEGAS_OK;
+}
+
+int vegas_get_grid(vegas_handle h, double* edges) {
+  if (!h || !edges) return VEGAS_EINVAL;
+  VG_HIP(hipMemcpyAsync(edges, h->b.edges, sizeof(double) * h->D * (h->n + 1), hipMemcpyDeviceToHost,
+                        h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  return VEGAS_OK;
+}
+
+int vegas_set_grid(vegas_handle h, const double* edges) {
+  if (!h || !edges) return VEGAS_EINVAL;
+  const int n = h->n;
+  for (int d = 0; d < h->D; ++d) {
+    const double* e = edges + d * (n + 1);
+    if (e[0] != 0.0 || e[n] != 1.0) return VEGAS_EINVAL;
+    for (int k = 0; k < n; ++k)
+      if (!(e[k + 1] >= e[k])) return VEGAS_EINVAL;
+  }
+  VG_HIP(hipMemcpyAsync(h->b.edges, edges, sizeof(double) * h->D * (n + 1), hipMemcpyHostToDevice,
+                        h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  return VEGAS_OK;
+}
+
+int vegas_get_hist(vegas_handle h, double* d, double* sums) {
+  if (!h) return VEGAS_EINVAL;
+  if (!h->any_iter) return VEGAS_ESTATE;
+  const int ns = h->D * h->n;
+  std::vector<double> buf(ns + 2);
+  VG_HIP(hipMemcpyAsync(buf.data(), h->b.hist, sizeof(double) * (ns + 2), hipMemcpyDeviceToHost, h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  if (d) std::memcpy(d, buf.data(), sizeof(double) * ns);
+  if (sums) {
+    sums[0] = buf[ns];
+    sums[1] = buf[ns + 1];
+  }
+  return VEGAS_OK;
+}
+
+int vegas_get_weights(vegas_handle h, int64_t first, int64_t n, double* w, uint8_t* bins) {
+  if (!h || !w || first < 0 || n < 0) return VEGAS_EINVAL;
+  if (!h->any_iter) return VEGAS_ESTATE;
+  if (first + n > h->last_n) return VEGAS_EINVAL;
+  if (n == 0) return VEGAS_OK;
+  VG_HIP(hipMemcpyAsync(w, h->b.rec_w + first, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  std::vector<uint32_t> words;
+  const int nw = (h->D + 3) / 4;
+  if (bins) {
+    words.resize(static_cast<size_t>(nw) * n);
+    for (int g = 0; g < nw; ++g)
+      VG_HIP(hipMemcpyAsync(words.data() + g * n, h->b.rec_bins + g * h->maxN + first, sizeof(uint32_t) * n,
+                            hipMemcpyDeviceToHost, h->stream));
+  }
+  VG_HIP(hipStreamSynchronize(h->stream));
+  if (bins)
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < h->D; ++d) bins[i * h->D + d] = static_cast<uint8_t>(words[(d / 4) * n + i] >> (8 * (d % 4)));
+  return VEGAS_OK;
+}
+
+// checkpoint layout: header {magic, process, ndim, nbins, iter, seed} then edges, history
+namespace {
+struct CkptHeader {
+  uint64_t magic;
+  int32_t process, ndim, nbins;
+  uint32_t iter;
+  uint64_t seed;
+};
+constexpr uint64_t kMagic = 0x5645474153434b31ull;  // "VEGASCK1"
+}  // namespace
+
+int vegas_get_state(vegas_handle h, void* buf, size_t* bytes) {
+  if (!h || !bytes) return VEGAS_EINVAL;
+  const size_t ne = static_cast<size_t>(h->D) * (h->n + 1), nh = 2 * static_cast<size_t>(h->iter);
+  const size_t need = sizeof(CkptHeader) + sizeof(double) * (ne + nh);
+  if (!buf) {
+    *bytes = need;
+    return VEGAS_OK;
+  }
+  if (*bytes < need) return VEGAS_EINVAL;
+  CkptHeader hd{kMagic, h->cfg.process, h->D, h->n, h->iter, h->cfg.seed};
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &hd, sizeof(hd));
+  double* e = reinterpret_cast<double*>(p + sizeof(hd));
+  VG_HIP(hipMemcpyAsync(e, h->b.edges, sizeof(double) * ne, hipMemcpyDeviceToHost, h->stream));
+  if (nh) VG_HIP(hipMemcpyAsync(e + ne, h->b.history, sizeof(double) * nh, hipMemcpyDeviceToHost, h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  *bytes = need;
+  return VEGAS_OK;
+}
+
+int vegas_set_state(vegas_handle h, const void* buf, size_t bytes) {
+  if (!h || !buf || bytes < sizeof(CkptHeader)) return VEGAS_EINVAL;
+  CkptHeader hd;
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != kMagic || hd.process != h->cfg.process || hd.ndim != h->D || hd.nbins != h->n ||
+      hd.seed != h->cfg.seed || hd.iter > VEGAS_MAX_ITER)
+    return VEGAS_EINVAL;
+  const size_t ne = static_cast<size_t>(h->D) * (h->n + 1), nh = 2 * static_cast<size_t>(hd.iter);
+  if (bytes != sizeof(CkptHeader) + sizeof(double) * (ne + nh)) return VEGAS_EINVAL;
+  const double* e = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(hd));
+  VG_HIP(hipMemcpyAsync(h->b.edges, e, sizeof(double) * ne, hipMemcpyHostToDevice, h->stream));
+  if (nh) VG_HIP(hipMemcpyAsync(h->b.history, e + ne, sizeof(double) * nh, hipMemcpyHostToDevice, h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  h->iter = hd.iter;
+  h->any_iter = hd.iter > 0;
+  h->have_hist = false;
+  h->last_n = 0;
+  return VEGAS_OK;
+}
+
+}  // extern "C"

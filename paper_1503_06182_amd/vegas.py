@@ -1,0 +1,210 @@
+"""ctypes binding of the gfx950 VEGAS library (libvegas.so, C ABI in include/vegas.h).
+
+Argument marshalling only: every step of an iteration runs in the library's
+HIP kernels.  PyTorch supplies the device workspace and the stream.  If the
+library is not built, importing works but every call raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvegas.so")
+
+GAUSS, GENZ, EEMUMU, DY_Z, W_PLUS, WW_4L = range(6)
+FP64, FP32_ME = 0, 1
+OK, EINVAL, ESTATE, ENOMEM, EHIP = 0, -1, -2, -3, -4
+NPHYS = 16
+MAX_ITER = 4096
+
+EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
+           "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
+           "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
+           "vegas_strerror", "vegas_set_timing", "vegas_stage_times"]
+
+
+class VegasError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.vegas_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+class Config(C.Structure):
+    _fields_ = [("process", C.c_int32), ("ndim", C.c_int32), ("nbins", C.c_int32),
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("alpha", C.c_double),
+                ("params", C.POINTER(C.c_double)), ("nparams", C.c_int32),
+                ("waves_per_block", C.c_int32), ("max_blocks", C.c_int32)]
+
+
+class IterResult(C.Structure):
+    _fields_ = [("integral", C.c_double), ("variance", C.c_double), ("n_events", C.c_int64),
+                ("n_nonzero", C.c_int64), ("n_nonfinite", C.c_int64), ("iteration", C.c_uint32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libvegas.so; raises if it is not built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.vegas_workspace_size.argtypes = [C.POINTER(Config), i64, C.POINTER(C.c_size_t)]
+    L.vegas_init.argtypes = [C.POINTER(Config), i64, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.vegas_iterate.argtypes = [vp, i64, C.POINTER(IterResult)]
+    L.vegas_refine.argtypes = [vp]
+    L.vegas_result.argtypes = [vp, dp, dp, dp, C.POINTER(i32)]
+    L.vegas_get_grid.argtypes = [vp, vp]
+    L.vegas_set_grid.argtypes = [vp, vp]
+    L.vegas_get_hist.argtypes = [vp, vp, vp]
+    L.vegas_get_weights.argtypes = [vp, i64, i64, vp, vp]
+    L.vegas_get_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.vegas_set_state.argtypes = [vp, vp, C.c_size_t]
+    L.vegas_set_launch.argtypes = [vp, i32, i32]
+    L.vegas_destroy.argtypes = [vp]
+    L.vegas_set_timing.argtypes = [vp, i32]
+    L.vegas_stage_times.argtypes = [vp, vp, vp, i32]
+    L.vegas_strerror.argtypes = [C.c_int]
+    L.vegas_strerror.restype = C.c_char_p
+    if hasattr(L, "vegas_grad"):
+        L.vegas_grad.argtypes = [vp, vp, i32, i64, i32, vp, vp]
+    _lib = L
+    return L
+
+
+def _check(status, where):
+    if status != OK:
+        raise VegasError(status, where)
+
+
+def make_config(process, ndim, nbins, seed=1, alpha=1.5, params=(), precision=FP64,
+                waves_per_block=0, max_blocks=0):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    cfg = Config(process, ndim, nbins, precision, seed, alpha,
+                 p.ctypes.data_as(C.POINTER(C.c_double)) if p.size else None, p.size,
+                 waves_per_block, max_blocks)
+    return cfg, p
+
+
+def workspace_size(process, ndim, nbins, max_events, params=(), precision=FP64) -> int:
+    L = load()
+    cfg, _keep = make_config(process, ndim, nbins, params=params, precision=precision)
+    b = C.c_size_t()
+    _check(L.vegas_workspace_size(C.byref(cfg), max_events, C.byref(b)), "vegas_workspace_size")
+    return b.value
+
+
+class Integrator:
+    """One VEGAS handle on the current torch device and stream.
+
+    The device workspace is a torch uint8 tensor owned by this object; the
+    stream is torch.cuda.current_stream() unless one is given.
+    """
+
+    def __init__(self, process, ndim, nbins, seed=1, alpha=1.5, params=(), precision=FP64,
+                 max_events=1_000_000, waves_per_block=0, max_blocks=0, stream=None):
+        import torch
+        L = load()
+        self._L = L
+        self.ndim, self.nbins, self.process = ndim, nbins, process
+        cfg, self._params = make_config(process, ndim, nbins, seed, alpha, params, precision,
+                                        waves_per_block, max_blocks)
+        nbytes = C.c_size_t()
+        _check(L.vegas_workspace_size(C.byref(cfg), max_events, C.byref(nbytes)),
+               "vegas_workspace_size")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(L.vegas_init(C.byref(cfg), max_events, C.c_void_p(aligned), nbytes.value,
+                            C.c_void_p(self.stream.cuda_stream), C.byref(h)), "vegas_init")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.vegas_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, n, sync=True):
+        if not sync:
+            _check(self._L.vegas_iterate(self._h, n, None), "vegas_iterate")
+            return None
+        r = IterResult()
+        _check(self._L.vegas_iterate(self._h, n, C.byref(r)), "vegas_iterate")
+        return {"I": r.integral, "var": r.variance, "n_events": r.n_events,
+                "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration}
+
+    def refine(self):
+        _check(self._L.vegas_refine(self._h), "vegas_refine")
+
+    def result(self):
+        I, e, c = C.c_double(), C.c_double(), C.c_double()
+        n = C.c_int32()
+        _check(self._L.vegas_result(self._h, C.byref(I), C.byref(e), C.byref(c), C.byref(n)),
+               "vegas_result")
+        return {"I": I.value, "sigma": e.value, "chi2_dof": c.value, "n_iter": n.value}
+
+    def get_grid(self):
+        e = np.zeros((self.ndim, self.nbins + 1))
+        _check(self._L.vegas_get_grid(self._h, e.ctypes.data), "vegas_get_grid")
+        return e
+
+    def set_grid(self, edges):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        _check(self._L.vegas_set_grid(self._h, e.ctypes.data), "vegas_set_grid")
+
+    def get_hist(self):
+        d = np.zeros((self.ndim, self.nbins))
+        s = np.zeros(2)
+        _check(self._L.vegas_get_hist(self._h, d.ctypes.data, s.ctypes.data), "vegas_get_hist")
+        return d, s
+
+    def get_weights(self, first, n, with_bins=True):
+        w = np.zeros(n)
+        b = np.zeros((n, self.ndim), dtype=np.uint8) if with_bins else None
+        _check(self._L.vegas_get_weights(self._h, first, n, w.ctypes.data,
+                                         b.ctypes.data if with_bins else None),
+               "vegas_get_weights")
+        return (w, b) if with_bins else w
+
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        _check(self._L.vegas_get_state(self._h, None, C.byref(n)), "vegas_get_state")
+        buf = C.create_string_buffer(n.value)
+        _check(self._L.vegas_get_state(self._h, buf, C.byref(n)), "vegas_get_state")
+        return buf.raw[:n.value]
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(self._L.vegas_set_state(self._h, buf, len(blob)), "vegas_set_state")
+
+    def set_timing(self, enable=True):
+        _check(self._L.vegas_set_timing(self._h, 1 if enable else 0), "vegas_set_timing")
+
+    def stage_times(self, reset=False):
+        """Summed kernel milliseconds and launch counts per stage since the last reset."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        _check(self._L.vegas_stage_times(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0),
+               "vegas_stage_times")
+        names = ("event", "accumulate", "finalize", "refine")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+
+    def set_launch(self, waves_per_block, max_blocks=0):
+        _check(self._L.vegas_set_launch(self._h, waves_per_block, max_blocks), "vegas_set_launch")

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Bars (stated in the design notes): per-event weights within 1e-12 relative in
+FP64; per-iteration integral, variance, S1, S2 and histogram within 1e-10
+relative with the grid injected into the oracle; bin indices bit-exact; cut
+decisions identical (flips counted, none allowed); byte-identical results for
+every launch configuration (the GPU form of the paper's thread-count
+independence, Sec. 2.2).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_EVENT = 1e-12
+REL_ITER = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1503_06182_amd as P
+    P.load()
+    return P
+
+
+def make_pair(P, cfg, max_events, **kw):
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"], max_events=max_events, **kw)
+    o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"])
+    return g, o
+
+
+def cases():
+    out = []
+    for name in ("gauss4", "eemumu", "dy_z", "w_plus", "ww_4l"):
+        out.append((name, W.config(name)))
+    for fam in (1, 2, 3, 4, 5, 6):
+        out.append((f"genz{fam}", dict(process=W.GENZ, ndim=5, nbins=40, seed=9, alpha=1.5,
+                                       params=W.genz_params(fam, 5, seed=fam, difficulty=6.0))))
+    return out
+
+
+def compare_weights(wg, wo, tag):
+    """|w_gpu - w_oracle| <= 1e-12 |w_oracle| + 1e-14 mean|w_oracle|.  The absolute
+    floor only matters for integrands that pass through zero (the oscillatory
+    Genz family), where a relative bar is ill-conditioned."""
+    assert wg.shape == wo.shape
+    zg, zo = wg == 0.0, wo == 0.0
+    flips = int(np.count_nonzero(zg != zo))
+    assert flips == 0, f"{tag}: {flips} cut flips"
+    floor = 1e-14 * np.mean(np.abs(wo))
+    bad = np.abs(wg - wo) > REL_EVENT * np.abs(wo) + floor
+    nz = ~zo
+    rel = np.abs(wg[nz] - wo[nz]) / np.abs(wo[nz])
+    assert not bad.any(), f"{tag}: {int(bad.sum())} events off, max rel {rel.max():.3e}"
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    den = np.maximum(np.abs(b), 1e-300)
+    return np.max(np.abs(a - b) / den)
+
+
+@pytest.mark.parametrize("name,cfg", cases(), ids=[c[0] for c in cases()])
+def test_iterations_match_oracle(P, name, cfg):
+    """Three iterations (with refinement) at a size that spans many blocks and a
+    ragged tail; grid injected into the oracle before each iteration."""
+    n = 6007 if cfg["process"] != W.WW_4L else 4099
+    g, o = make_pair(P, cfg, n)
+    for it in range(3):
+        o.set_grid(g.get_grid())
+        o.iteration = it
+        rg = g.iterate(n)
+        ro = o.iterate(n)
+        wg, bg = g.get_weights(0, n)
+        wo, bo = o.event_weights(it, 0, n)
+        assert np.array_equal(bg, bo), f"{name} it{it}: bin indices differ"
+        compare_weights(wg, wo, f"{name} it{it}")
+        assert rg["n_nonzero"] == ro["n_nonzero"] and rg["n_nonfinite"] == ro["n_nonfinite"]
+        assert rel(rg["I"], ro["I"]) < REL_ITER, (name, it, rg, ro)
+        assert rel(rg["var"], ro["var"]) < REL_ITER, (name, it, rg, ro)
+        dg, sg = g.get_hist()
+        do, so = o.get_hist()
+        assert rel(sg, so) < REL_ITER
+        m = do > 0
+        assert np.array_equal(dg > 0, m)
+        assert rel(dg[m], do[m]) < REL_ITER
+        g.refine()
+        o.refine()
+        assert np.max(np.abs(g.get_grid() - o.get_grid())) < 1e-12, f"{name} it{it}: grids"
+
+
+@pytest.mark.parametrize("name", ["dy_z", "gauss4"])
+def test_full_schedule_end_to_end(P, name):
+    """The whole schedule without grid injection: the grids drift only by
+    rounding, so the combined integral and error agree with the oracle's."""
+    cfg = W.config(name)
+    n = cfg["n_events"]
+    g, o = make_pair(P, cfg, n)
+    for _ in range(cfg["n_iter"]):
+        g.iterate(n)
+        g.refine()
+        o.iterate(n)
+        o.refine()
+    rg, ro = g.result(), o.result()
+    assert rel(rg["I"], ro["I"]) < REL_ITER
+    assert rel(rg["sigma"], ro["sigma"]) < 1e-8
+    assert abs(rg["chi2_dof"] - ro["chi2_dof"]) < 1e-6 * max(1.0, ro["chi2_dof"])
+    assert rg["n_iter"] == ro["n_iter"] == cfg["n_iter"]
+
+
+def run_schedule(P, cfg, n, n_iter, **launch):
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"], max_events=n, **launch)
+    blobs = []
+    for _ in range(n_iter):
+        r = g.iterate(n)
+        d, s = g.get_hist()
+        g.refine()
+        blobs.append(np.array([r["I"], r["var"]]).tobytes() + d.tobytes() + s.tobytes()
+                     + g.get_grid().tobytes())
+    res = g.result()
+    blobs.append(np.array([res["I"], res["sigma"], res["chi2_dof"]]).tobytes())
+    return b"".join(blobs)
+
+
+@pytest.mark.parametrize("name", ["w_plus", "ww_4l", "genz2"])
+def test_bit_identical_across_launch_configurations(P, name):
+    if name == "genz2":
+        cfg = dict(process=W.GENZ, ndim=5, nbins=40, seed=9, alpha=1.5,
+                   params=W.genz_params(2, 5, seed=2, difficulty=6.0))
+    else:
+        cfg = W.config(name)
+    n = 50_021 if name != "ww_4l" else 20_011
+    ref = run_schedule(P, cfg, n, 3)
+    for wpb, mb in ((1, 0), (2, 3), (4, 1), (8, 0), (16, 5), (4, 97)):
+        assert run_schedule(P, cfg, n, 3, waves_per_block=wpb, max_blocks=mb) == ref, (wpb, mb)
+
+
+def test_checkpoint_resume_is_bit_identical(P):
+    cfg = W.config("w_plus")
+    n = 40_000
+    a = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+    for _ in range(3):
+        a.iterate(n)
+        a.refine()
+    blob = a.get_state()
+    for _ in range(3):
+        a.iterate(n)
+        a.refine()
+    ra = a.result()
+    b = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+    b.set_state(blob)
+    for _ in range(3):
+        b.iterate(n)
+        b.refine()
+    rb = b.result()
+    assert ra == rb
+    assert np.array_equal(a.get_grid(), b.get_grid())
+
+
+def test_histogram_sums_and_zero_weight_edge_cases(P):
+    cfg = W.config("w_plus")
+    g = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=1000)
+    r = g.iterate(2)                       # minimum event count
+    assert r["n_events"] == 2
+    r = g.iterate(1000)
+    d, s = g.get_hist()
+    assert np.allclose(d.sum(axis=1), s[1], rtol=1e-14)
+    w = g.get_weights(0, 1000, with_bins=False)
+    assert np.isclose(w.sum(), s[0], rtol=1e-14) and np.isclose((w * w).sum(), s[1], rtol=1e-14)
+
+
+def test_nonfinite_weights_counted(P):
+    par = np.concatenate([[9.0], np.ones(3), np.full(3, 0.5)])  # unknown Genz family -> NaN
+    g = P.Integrator(W.GENZ, 3, 10, 1, 1.5, par, max_events=500)
+    r = g.iterate(500)
+    assert r["n_nonfinite"] == 500 and r["I"] == 0.0
+
+
+def test_errors_and_call_order(P):
+    cfg = W.config("dy_z")
+    g = P.Integrator(cfg["process"], 3, 50, 1, 1.5, cfg["params"], max_events=100)
+    with pytest.raises(P.VegasError) as e:
+        g.refine()
+    assert e.value.status == -2
+    with pytest.raises(P.VegasError):
+        g.iterate(101)
+    with pytest.raises(P.VegasError):
+        g.iterate(1)
+    with pytest.raises(P.VegasError):
+        g.result()
+    with pytest.raises(P.VegasError):
+        g.set_grid(np.zeros((3, 51)))
+    g.iterate(100)
+    g.refine()
+    with pytest.raises(P.VegasError):
+        g.refine()                      # one refine per iteration
+
+
+def test_full_size_sampled_parity_bench_workload(P):
+    """The measured workload (W+ at 1e6 events, default launch): sampled events
+    recomputed one by one by the oracle at the same grid."""
+    cfg = W.config("w_plus")
+    n = cfg["n_events"]
+    g, o = make_pair(P, cfg, n)
+    for it in range(3):
+        g.iterate(n)
+        g.refine()
+    o.set_grid(g.get_grid())
+    g.iterate(n)
+    wg = g.get_weights(0, n, with_bins=False)
+    idx = np.arange(0, n, 997)
+    wo = np.array([o.event_weights(3, int(i), 1)[0][0] for i in idx])
+    compare_weights(wg[idx], wo, "w_plus full size")
+    # the tail of the launch
+    wt, _ = o.event_weights(3, n - 300, 300)
+    compare_weights(wg[n - 300:], wt, "w_plus tail")
