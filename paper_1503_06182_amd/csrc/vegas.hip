@@ -31,21 +31,26 @@
 namespace vg {
 
 constexpr int kWave = 64;
-constexpr int kMaxGrid = 4096;  // default cap on blocks per launch (grid-stride beyond)
+
+constexpr int kMaxRowsEvent = 2048;  // cap on event-kernel blocks (rows of the per-bin max partials)
+constexpr int kMaxRowsAcc = 1024;    // cap on accumulation blocks (rows of the digit partials)
 
 struct DevBufs {
-  double* edges;            // [D][n+1]
-  double* rec_w;            // [maxN]
-  uint32_t* rec_bins;       // [ceil(D/4)][maxN], 4 bins of 8 bits per word
-  unsigned long long* maxw; // [1] bits of max |w| ; [1] spare
-  unsigned long long* binmax;  // [D*n] bits of max w^2 per bin
-  long long* acc;           // [(2 + D*n) * 3] digit sums
-  unsigned long long* cnt;  // [2] n_nonzero, n_nonfinite
-  double* hist;             // [D*n + 2] d, S1, S2 of the last iteration
-  double* history;          // [VEGAS_MAX_ITER][2] I_j, var_j
-  double* iter_out;         // [8] I_j, var_j, nz, nnf (as doubles), n
-  double* result;           // [4] I, sigma, chi2/dof, n_iter
-  int* scale;               // [2 + D*n] fixed-point exponents of the last iteration
+  double* edges;                 // [D][n+1]
+  double* rec_w;                 // [maxN]
+  uint32_t* rec_bins;            // [ceil(D/4)][maxN], 4 bins of 8 bits per word
+  unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max, cleared by k_binmax)
+  unsigned long long* cnt;       // [2] n_nonzero, n_nonfinite (atomic, cleared by k_binmax)
+  unsigned long long* it_scal;   // [4] this iteration's max |w| bits, n_nonzero, n_nonfinite
+  unsigned long long* part_max;  // [rows][D*n] per-block max of w^2 per bin (bits)
+  unsigned long long* binmax;    // [D*n] max of w^2 per bin (bits)
+  long long* part_acc;           // [rows][3*(2+D*n)] per-block digit sums: S1, S2, d[...]
+  long long* acc_tot;            // [3*(2+D*n)] digit sums over all blocks
+  double* hist;                  // [D*n + 2] d, S1, S2 of the last iteration
+  double* history;               // [VEGAS_MAX_ITER][2] I_j, var_j
+  double* iter_out;              // [8] I_j, var_j, nz, nnf, N
+  double* result;                // [4] I, sigma, chi2/dof, n_iter
+  int* scale;                    // [D*n + 2] fixed-point exponents of the last iteration
 };
 
 // ---------------------------------------------------------------------------
@@ -108,6 +113,12 @@ __global__ __launch_bounds__(MAXT) void k_event(EventArgs a) {
   unsigned long long* bmax = reinterpret_cast<unsigned long long*>(e_lds + nd * (n + 1));
   for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x) e_lds[i] = a.b.edges[i];
   for (int i = threadIdx.x; i < nd * n; i += blockDim.x) bmax[i] = 0ull;
+  if (blockIdx.x == 0) {
+    // clear the device-wide reduction targets of this iteration (the previous
+    // iteration's values were consumed by its finalisation, earlier on the stream)
+    for (int i = threadIdx.x; i < nd * n; i += blockDim.x) a.b.binmax[i] = 0ull;
+    for (int i = threadIdx.x; i < 3 * (2 + nd * n); i += blockDim.x) a.b.acc_tot[i] = 0;
+  }
   __syncthreads();
 
   unsigned long long wmax = 0ull, nz = 0ull, nnf = 0ull;
@@ -148,17 +159,78 @@ __global__ __launch_bounds__(MAXT) void k_event(EventArgs a) {
       }
     }
   }
+  // block totals (LDS) -> one device-wide atomic per block and quantity
+  __shared__ unsigned long long blk[3];
+  if (threadIdx.x < 3) blk[threadIdx.x] = 0ull;
+  __syncthreads();
   wmax = wave_max_u64(wmax);
   const long long snz = wave_sum_i64(static_cast<long long>(nz));
   const long long snf = wave_sum_i64(static_cast<long long>(nnf));
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (wmax) atomicMax(&a.b.maxw[0], wmax);
-    if (snz) atomicAdd(&a.b.cnt[0], static_cast<unsigned long long>(snz));
-    if (snf) atomicAdd(&a.b.cnt[1], static_cast<unsigned long long>(snf));
+    atomicMax(&blk[0], wmax);
+    atomicAdd(&blk[1], static_cast<unsigned long long>(snz));
+    atomicAdd(&blk[2], static_cast<unsigned long long>(snf));
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nd * n; i += blockDim.x)
-    if (bmax[i]) atomicMax(&a.b.binmax[i], bmax[i]);
+  if (threadIdx.x == 0) {
+    if (blk[0]) atomicMax(&a.b.maxw[0], blk[0]);
+    if (blk[1]) atomicAdd(&a.b.cnt[0], blk[1]);
+    if (blk[2]) atomicAdd(&a.b.cnt[1], blk[2]);
+  }
+  unsigned long long* row = a.b.part_max + static_cast<int64_t>(blockIdx.x) * nd * n;
+  for (int i = threadIdx.x; i < nd * n; i += blockDim.x) row[i] = bmax[i];
+}
+
+// ---------------------------------------------------------------------------
+// column reductions of the per-block partials: block (x, y) covers 32 columns and
+// rows [32 y, 32 y + 32) with 8 row groups, then one device-wide integer atomic
+// per column (max and sum are exact and order-free)
+// ---------------------------------------------------------------------------
+constexpr int kColTile = 32, kRowTile = 32;
+
+// per-bin maxima over the event kernel's blocks; block (0,0) also latches and
+// clears this iteration's device-wide max |w| and counters
+__global__ void k_binmax(DevBufs b, int nslot, int rows) {
+  __shared__ unsigned long long red[8][kColTile];
+  const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  const int col = blockIdx.x * kColTile + c;
+  unsigned long long m = 0ull;
+  if (col < nslot)
+    for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8) {
+      const unsigned long long v = b.part_max[static_cast<int64_t>(r) * nslot + col];
+      m = v > m ? v : m;
+    }
+  red[rg][c] = m;
+  __syncthreads();
+  if (rg == 0 && col < nslot) {
+    for (int g = 1; g < 8; ++g) m = red[g][c] > m ? red[g][c] : m;
+    if (m) atomicMax(&b.binmax[col], m);
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    b.it_scal[0] = b.maxw[0];
+    b.it_scal[1] = b.cnt[0];
+    b.it_scal[2] = b.cnt[1];
+    b.maxw[0] = 0ull;
+    b.cnt[0] = 0ull;
+    b.cnt[1] = 0ull;
+  }
+}
+
+// digit sums over the accumulation kernel's blocks
+__global__ void k_accsum(DevBufs b, int ncol, int rows) {
+  __shared__ long long red[8][kColTile];
+  const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  const int col = blockIdx.x * kColTile + c;
+  long long sum = 0;
+  if (col < ncol)
+    for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8)
+      sum += b.part_acc[static_cast<int64_t>(r) * ncol + col];
+  red[rg][c] = sum;
+  __syncthreads();
+  if (rg == 0 && col < ncol) {
+    for (int g = 1; g < 8; ++g) sum += red[g][c];
+    if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc_tot[col]), static_cast<unsigned long long>(sum));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -173,13 +245,13 @@ struct AccArgs {
 
 __global__ void k_accum(AccArgs a) {
   extern __shared__ unsigned char smem[];
-  const int n = a.nbins, nd = a.ndim, nslot = nd * n;
-  long long* acc = reinterpret_cast<long long*>(smem);  // [nslot][3]
-  int* esc = reinterpret_cast<int*>(acc + 3 * nslot);     // [nslot]
-  for (int i = threadIdx.x; i < 3 * nslot; i += blockDim.x) acc[i] = 0;
+  const int n = a.nbins, nd = a.ndim, nslot = nd * n, ncol = 3 * (2 + nslot);
+  long long* acc = reinterpret_cast<long long*>(smem);  // [2 + nslot][3]: S1, S2, d
+  int* esc = reinterpret_cast<int*>(acc + ncol);         // [nslot]
+  for (int i = threadIdx.x; i < ncol; i += blockDim.x) acc[i] = 0;
   for (int i = threadIdx.x; i < nslot; i += blockDim.x)
     esc[i] = fx_exponent(__longlong_as_double(static_cast<long long>(a.b.binmax[i])));
-  const double wmax = __longlong_as_double(static_cast<long long>(a.b.maxw[0]));
+  const double wmax = __longlong_as_double(static_cast<long long>(a.b.it_scal[0]));
   const int E1 = fx_exponent(wmax);
   const int E2 = fx_exponent(wmax * wmax);
   __syncthreads();
@@ -205,60 +277,55 @@ __global__ void k_accum(AccArgs a) {
         const int d = 4 * g + j;
         const int slot = d * n + static_cast<int>((word >> (8 * j)) & 0xffu);
         fx_digits(w2, esc[slot], d0, d1, d2);
-        unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + 3 * slot);
+        unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + 3 * (2 + slot));
         if (d0) atomicAdd(p + 0, static_cast<unsigned long long>(d0));
         if (d1) atomicAdd(p + 1, static_cast<unsigned long long>(d1));
         if (d2) atomicAdd(p + 2, static_cast<unsigned long long>(d2));
       }
     }
   }
-  // S1, S2: per-lane registers -> wave butterfly -> one global atomic per wave
+  // S1, S2: per-lane registers -> wave butterfly -> LDS
   s1_0 = wave_sum_i64(s1_0);
   s1_1 = wave_sum_i64(s1_1);
   s1_2 = wave_sum_i64(s1_2);
   s2_0 = wave_sum_i64(s2_0);
   s2_1 = wave_sum_i64(s2_1);
   s2_2 = wave_sum_i64(s2_2);
-  unsigned long long* g = reinterpret_cast<unsigned long long*>(a.b.acc);
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (s1_0) atomicAdd(g + 0, static_cast<unsigned long long>(s1_0));
-    if (s1_1) atomicAdd(g + 1, static_cast<unsigned long long>(s1_1));
-    if (s1_2) atomicAdd(g + 2, static_cast<unsigned long long>(s1_2));
-    if (s2_0) atomicAdd(g + 3, static_cast<unsigned long long>(s2_0));
-    if (s2_1) atomicAdd(g + 4, static_cast<unsigned long long>(s2_1));
-    if (s2_2) atomicAdd(g + 5, static_cast<unsigned long long>(s2_2));
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(acc);
+    atomicAdd(p + 0, static_cast<unsigned long long>(s1_0));
+    atomicAdd(p + 1, static_cast<unsigned long long>(s1_1));
+    atomicAdd(p + 2, static_cast<unsigned long long>(s1_2));
+    atomicAdd(p + 3, static_cast<unsigned long long>(s2_0));
+    atomicAdd(p + 4, static_cast<unsigned long long>(s2_1));
+    atomicAdd(p + 5, static_cast<unsigned long long>(s2_2));
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 3 * nslot; i += blockDim.x)
-    if (acc[i]) atomicAdd(g + 6 + i, static_cast<unsigned long long>(acc[i]));
+  long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * ncol;
+  for (int i = threadIdx.x; i < ncol; i += blockDim.x) row[i] = acc[i];
 }
 
 // ---------------------------------------------------------------------------
-// K3: digits -> doubles, I_j and var_j; clear the accumulators for the next iteration
+// K3: digit totals -> doubles (d, S1, S2), then I_j and var_j
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(DevBufs b, int ndim, int nbins, int64_t nev, uint32_t iter) {
-  const int nslot = ndim * nbins;
-  const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
-  const int E1 = fx_exponent(wmax), E2 = fx_exponent(wmax * wmax);
-  for (int s = threadIdx.x; s < nslot + 2; s += blockDim.x) {
+__global__ void k_finalize(DevBufs b, int nslot, int64_t nev, uint32_t iter) {
+  __shared__ double s12[2];
+  const double wmax = __longlong_as_double(static_cast<long long>(b.it_scal[0]));
+  for (int slot = threadIdx.x; slot < nslot + 2; slot += blockDim.x) {
     int E;
-    long long* p;
-    double* out;
-    if (s < nslot) {
-      E = fx_exponent(__longlong_as_double(static_cast<long long>(b.binmax[s])));
-      p = b.acc + 6 + 3 * s;
-      out = b.hist + s;
-    } else {
-      E = s == nslot ? E1 : E2;
-      p = b.acc + 3 * (s - nslot);
-      out = b.hist + s;
-    }
-    *out = fx_value(p[0], p[1], p[2], E);
-    b.scale[s] = E;
+    if (slot == 0) E = fx_exponent(wmax);
+    else if (slot == 1) E = fx_exponent(wmax * wmax);
+    else E = fx_exponent(__longlong_as_double(static_cast<long long>(b.binmax[slot - 2])));
+    const long long* t = b.acc_tot + 3 * slot;
+    const double v = fx_value(t[0], t[1], t[2], E);
+    const int h = slot < 2 ? nslot + slot : slot - 2;
+    b.hist[h] = v;
+    b.scale[h] = E;
+    if (slot < 2) s12[slot] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double S1 = b.hist[nslot], S2 = b.hist[nslot + 1];
+    const double S1 = s12[0], S2 = s12[1];
     const double N = static_cast<double>(nev);
     const double I = S1 / N;
     const double var = fma(-I, I, S2 / N) / (N - 1.0);
@@ -266,50 +333,46 @@ __global__ void k_finalize(DevBufs b, int ndim, int nbins, int64_t nev, uint32_t
     b.history[2 * iter + 1] = var;
     b.iter_out[0] = I;
     b.iter_out[1] = var;
-    b.iter_out[2] = static_cast<double>(b.cnt[0]);
-    b.iter_out[3] = static_cast<double>(b.cnt[1]);
+    b.iter_out[2] = static_cast<double>(b.it_scal[1]);
+    b.iter_out[3] = static_cast<double>(b.it_scal[2]);
     b.iter_out[4] = N;
-    b.cnt[0] = 0;
-    b.cnt[1] = 0;
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 3 * (nslot + 2); i += blockDim.x) b.acc[i] = 0;
-  for (int i = threadIdx.x; i < nslot; i += blockDim.x) b.binmax[i] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0) b.maxw[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // K4: grid refinement, one single-wave block per dimension
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ void k_refine(DevBufs b, int nbins, double alpha) {
-  __shared__ double dm[VEGAS_MAX_BINS + 1];   // smoothed histogram, then damped importance
-  __shared__ double en[VEGAS_MAX_BINS + 1];   // new edges
-  __shared__ double ssum[2];
+  __shared__ double hs[VEGAS_MAX_BINS + 1];   // histogram of this dimension
+  __shared__ double dm[VEGAS_MAX_BINS + 1];   // smoothed histogram, then damped importance m
+  __shared__ double cm[VEGAS_MAX_BINS + 1];   // cumulative importance: cm[k] = m_0 + ... + m_{k-1}
+  __shared__ double eo[VEGAS_MAX_BINS + 1];   // old edges
   const int d = blockIdx.x, lane = threadIdx.x;
   const int n = nbins;
-  const double* h = b.hist + d * n;
   double* e = b.edges + d * (n + 1);
+  for (int k = lane; k < n; k += kWave) hs[k] = b.hist[d * n + k];
+  for (int k = lane; k <= n; k += kWave) eo[k] = e[k];
+  __syncthreads();
+  double s = 0.0, sb = 0.0;
   for (int k = lane; k < n; k += kWave) {
     double v;
-    if (k == 0) v = (h[0] + h[1]) / 2.0;
-    else if (k == n - 1) v = (h[n - 2] + h[n - 1]) / 2.0;
-    else v = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
+    if (k == 0) v = (hs[0] + hs[1]) / 2.0;
+    else if (k == n - 1) v = (hs[n - 2] + hs[n - 1]) / 2.0;
+    else v = (hs[k - 1] + hs[k] + hs[k + 1]) / 3.0;
     dm[k] = v;
+    s += hs[k];
+    sb += v;
   }
+  s = wave_sum_f64(s);
+  sb = wave_sum_f64(sb);
+  if (!(s > 0.0)) return;  // whole block: an empty histogram keeps this dimension's grid
   __syncthreads();
-  if (lane == 0) {
-    double s = 0.0, sb = 0.0;
-    for (int k = 0; k < n; ++k) {
-      s += h[k];
-      sb += dm[k];
-    }
-    ssum[0] = s;
-    ssum[1] = sb;
-  }
-  __syncthreads();
-  if (!(ssum[0] > 0.0)) return;  // whole block: empty histogram keeps this dimension's grid
-  const double sb = ssum[1];
   for (int k = lane; k < n; k += kWave) {
     const double r = dm[k] / sb;
     double m;
@@ -319,27 +382,41 @@ __global__ void k_refine(DevBufs b, int nbins, double alpha) {
     dm[k] = m;
   }
   __syncthreads();
-  if (lane == 0) {
-    double msum = 0.0;
-    for (int k = 0; k < n; ++k) msum += dm[k];
-    const double stp = msum / n;
-    en[0] = 0.0;
-    en[n] = 1.0;
-    int j = 0;
-    double cum = 0.0;
-    for (int k = 1; k < n; ++k) {
-      const double target = k * stp;
-      while (j < n - 1 && cum + dm[j] < target) {
-        cum += dm[j];
-        ++j;
-      }
-      double frac = dm[j] > 0.0 ? (target - cum) / dm[j] : 0.0;
-      frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
-      en[k] = e[j] + frac * (e[j + 1] - e[j]);
-    }
+  // inclusive prefix sums: lane l sums bins [4l, 4l+4) in order, then a wave scan
+  double part = 0.0;
+  for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) part += dm[k];
+  double incl = part;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  double run = incl - part;  // exclusive prefix of this lane's chunk
+  if (lane == 0) cm[0] = 0.0;
+  for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) {
+    run += dm[k];
+    cm[k + 1] = run;
   }
   __syncthreads();
-  for (int k = lane; k <= n; k += kWave) e[k] = en[k];
+  const double stp = cm[n] / n;
+  // new interior edge k sits in the old bin j with cm[j] < k*stp <= cm[j+1]
+  for (int k = 1 + lane; k < n; k += kWave) {
+    const double target = k * stp;
+    int lo = 0, hi = n - 1;  // largest j in [0, n-1] with cm[j] < target
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cm[mid] < target) lo = mid;
+      else hi = mid - 1;
+    }
+    const int j = lo;
+    double frac = dm[j] > 0.0 ? (target - cm[j]) / dm[j] : 0.0;
+    frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+    e[k] = eo[j] + frac * (eo[j + 1] - eo[j]);
+  }
+  if (lane == 0) {
+    e[0] = 0.0;
+    e[n] = 1.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -402,7 +479,8 @@ namespace {
 thread_local std::string g_last_hip_error;
 
 struct Layout {
-  size_t edges, rec_w, rec_bins, maxw, binmax, acc, cnt, hist, history, iter_out, result, scale, total;
+  size_t edges, rec_w, rec_bins, maxw, cnt, it_scal, part_max, binmax, part_acc, acc_tot, hist, history,
+      iter_out, result, scale, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -420,9 +498,12 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.rec_w = take(sizeof(double) * maxN);
   L.rec_bins = take(sizeof(uint32_t) * words * maxN);
   L.maxw = take(sizeof(unsigned long long) * 2);
-  L.binmax = take(sizeof(unsigned long long) * D * n);
-  L.acc = take(sizeof(long long) * 3 * (2 + D * n));
   L.cnt = take(sizeof(unsigned long long) * 2);
+  L.it_scal = take(sizeof(unsigned long long) * 4);
+  L.part_max = take(sizeof(unsigned long long) * kMaxRowsEvent * D * n);
+  L.binmax = take(sizeof(unsigned long long) * D * n);
+  L.part_acc = take(sizeof(long long) * kMaxRowsAcc * 3 * (2 + D * n));
+  L.acc_tot = take(sizeof(long long) * 3 * (2 + D * n));
   L.hist = take(sizeof(double) * (D * n + 2));
   L.history = take(sizeof(double) * 2 * VEGAS_MAX_ITER);
   L.iter_out = take(sizeof(double) * 8);
@@ -587,7 +668,8 @@ struct vegas_state {
   bool any_iter;
   int64_t last_n;
   int wpb, max_blocks;
-  int event_lds;
+  int event_lds, acc_lds;
+  int ncu, occ_event, occ_acc;  // CUs, and resident 256-thread blocks per CU of each kernel
   // optional per-stage kernel timing with HIP events on the handle's stream
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -609,10 +691,15 @@ namespace {
 
 int pick_threads(const vegas_state* h) { return kWave * (h->wpb > 0 ? h->wpb : 4); }
 
-int pick_blocks(const vegas_state* h, int64_t nev, int threads) {
+// grid-stride launches: enough blocks to fill every CU at the kernel's occupancy
+// (one resident wave of blocks), capped by the partial-buffer rows and the knob
+int pick_blocks(const vegas_state* h, int64_t nev, int threads, int occ, int rows_cap) {
   int64_t nb = (nev + threads - 1) / threads;
-  const int cap = h->max_blocks > 0 ? h->max_blocks : kMaxGrid;
-  if (nb > cap) nb = cap;
+  int64_t fill = static_cast<int64_t>(h->ncu) * (occ > 0 ? occ : 1) * 256 / threads;
+  if (fill < 1) fill = 1;
+  if (nb > fill) nb = fill;
+  if (h->max_blocks > 0 && nb > h->max_blocks) nb = h->max_blocks;
+  if (nb > rows_cap) nb = rows_cap;
   if (nb < 1) nb = 1;
   return static_cast<int>(nb);
 }
@@ -686,6 +773,30 @@ hipError_t launch_event(const vegas_state* h, const EventArgs& a, int blocks, in
   return hipErrorInvalidValue;
 }
 
+template <int PROC, int PREC, int D>
+int occupancy_event_t(int lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256>),
+                                                    256, lds) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int occupancy_event(const vegas_state* h) {
+  const int lds = h->event_lds;
+  switch (h->cfg.process) {
+    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds);
+    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds);
+    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds);
+    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds);
+    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds);
+    case VEGAS_WW_4L:
+      if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds);
+      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds);
+  }
+  return 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -752,20 +863,37 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   h->b.rec_w = reinterpret_cast<double*>(B + L.rec_w);
   h->b.rec_bins = reinterpret_cast<uint32_t*>(B + L.rec_bins);
   h->b.maxw = reinterpret_cast<unsigned long long*>(B + L.maxw);
-  h->b.binmax = reinterpret_cast<unsigned long long*>(B + L.binmax);
-  h->b.acc = reinterpret_cast<long long*>(B + L.acc);
   h->b.cnt = reinterpret_cast<unsigned long long*>(B + L.cnt);
+  h->b.it_scal = reinterpret_cast<unsigned long long*>(B + L.it_scal);
+  h->b.part_max = reinterpret_cast<unsigned long long*>(B + L.part_max);
+  h->b.binmax = reinterpret_cast<unsigned long long*>(B + L.binmax);
+  h->b.part_acc = reinterpret_cast<long long*>(B + L.part_acc);
+  h->b.acc_tot = reinterpret_cast<long long*>(B + L.acc_tot);
   h->b.hist = reinterpret_cast<double*>(B + L.hist);
   h->b.history = reinterpret_cast<double*>(B + L.history);
   h->b.iter_out = reinterpret_cast<double*>(B + L.iter_out);
   h->b.result = reinterpret_cast<double*>(B + L.result);
   h->b.scale = reinterpret_cast<int*>(B + L.scale);
   h->pc = make_consts(&h->cfg, h->params);
-  // zero the small state (accumulators, maxima, counters, history) with a fill kernel
-  const size_t small_begin = L.maxw, small_end = L.total;
+  h->acc_lds = static_cast<int>(sizeof(long long) * 3 * (2 + D * n) + sizeof(int) * D * n);
+  {
+    hipDeviceProp_t prop;
+    h->ncu = hipGetDeviceProperties(&prop, h->device) == hipSuccess ? prop.multiProcessorCount : 256;
+    if (h->ncu < 1) h->ncu = 1;
+    h->occ_event = occupancy_event(h);
+    int nb = 0;
+    h->occ_acc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_accum), 256,
+                                                              h->acc_lds) == hipSuccess && nb > 0
+                     ? nb
+                     : 1;
+  }
+  // zero the device-wide atomics and every buffer after the partials with a fill kernel
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, h->stream,
+                     reinterpret_cast<unsigned long long*>(B + L.maxw),
+                     static_cast<int64_t>((L.part_max - L.maxw) / 8));
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, h->stream,
-                     reinterpret_cast<unsigned long long*>(B + small_begin),
-                     static_cast<int64_t>((small_end - small_begin) / 8));
+                     reinterpret_cast<unsigned long long*>(B + L.hist),
+                     static_cast<int64_t>((L.total - L.hist) / 8));
   hipLaunchKernelGGL(k_uniform_grid, dim3(1), dim3(256), 0, h->stream, h->b.edges, D, n);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
     g_last_hip_error = "vegas_init: initial fill failed";
@@ -830,6 +958,7 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
   if (n_events < 2 || n_events > h->maxN) return VEGAS_EINVAL;
   if (h->iter >= VEGAS_MAX_ITER) return VEGAS_ESTATE;
   const int threads = pick_threads(h);
+  const int nslot = h->D * h->n;
   EventArgs ea;
   ea.pc = h->pc;
   ea.b = h->b;
@@ -839,22 +968,30 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
   ea.iter = h->iter;
   ea.ndim = h->D;
   ea.nbins = h->n;
+  const int ev_blocks = pick_blocks(h, n_events, threads, h->occ_event, kMaxRowsEvent);
   hipEvent_t t0 = stage_begin(h);
-  VG_HIP(launch_event(h, ea, pick_blocks(h, n_events, threads), threads));
+  VG_HIP(launch_event(h, ea, ev_blocks, threads));
   stage_end(h, 0, t0);
+  t0 = stage_begin(h);
+  hipLaunchKernelGGL(k_binmax, dim3((nslot + kColTile - 1) / kColTile, (ev_blocks + kRowTile - 1) / kRowTile),
+                     dim3(256), 0, h->stream, h->b, nslot, ev_blocks);
+  VG_HIP(hipGetLastError());
   AccArgs aa;
   aa.b = h->b;
   aa.nev = n_events;
   aa.stride_rec = h->maxN;
   aa.ndim = h->D;
   aa.nbins = h->n;
-  const int acc_lds = static_cast<int>(sizeof(long long) * 3 * h->D * h->n + sizeof(int) * h->D * h->n);
-  t0 = stage_begin(h);
-  hipLaunchKernelGGL(k_accum, dim3(pick_blocks(h, n_events, threads)), dim3(threads), acc_lds, h->stream, aa);
+  const int acc_blocks = pick_blocks(h, n_events, threads, h->occ_acc, kMaxRowsAcc);
+  hipLaunchKernelGGL(k_accum, dim3(acc_blocks), dim3(threads), h->acc_lds, h->stream, aa);
   VG_HIP(hipGetLastError());
   stage_end(h, 1, t0);
   t0 = stage_begin(h);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->b, h->D, h->n, n_events, h->iter);
+  const int ncol = 3 * (2 + nslot);
+  hipLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (acc_blocks + kRowTile - 1) / kRowTile),
+                     dim3(256), 0, h->stream, h->b, ncol, acc_blocks);
+  VG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->b, nslot, n_events, h->iter);
   VG_HIP(hipGetLastError());
   stage_end(h, 2, t0);
   const uint32_t j = h->iter;
