@@ -37,7 +37,7 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l"])
+    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "adjoint"])
     ap.add_argument("--events", type=int, default=0, help="events per iteration (0: workload's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32me"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,8 +88,44 @@ def cpu_baseline(cfg, iters, events):
                       f"FP64 C oracle on one host core, {dt:.1f} s"}
 
 
+def bench_adjoint(args):
+    """Drell-Yan adjoint: 64 parameter points x 1e6 events, FP64, at the grid reached
+    after the workload's 5 iterations; one step = one vegas_grad call."""
+    import torch
+
+    import paper_1503_06182_amd as P
+    import workloads as W
+    torch.cuda.set_device(0)
+    cfg = W.config("dy_z")
+    g = P.Integrator(cfg["process"], 3, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"],
+                     max_events=cfg["n_events"])
+    for _ in range(cfg["n_iter"]):
+        g.iterate(cfg["n_events"])
+        g.refine()
+    theta = torch.tensor(W.adjoint_points(64), device="cuda")
+    N = args.events or 1_000_000
+    for _ in range(args.warmup):
+        g.grad(theta, N, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sig, ds = g.grad(theta, N, 5)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    line = {"metric": "adjoint point-events/s (sigma and 5 derivatives per point and event)",
+            "value": args.steps * N * 64 / T, "unit": "point-events/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "adjoint", "points": 64, "events": N},
+            "sigma_mean_pb": float(sig.mean())}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse_args()
+    if args.workload == "adjoint":
+        bench_adjoint(args)
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return

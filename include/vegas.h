@@ -175,6 +175,22 @@ int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks
 int vegas_set_timing(vegas_handle h, int32_t enable);
 int vegas_stage_times(vegas_handle h, double *ms, int64_t *launches, int32_t reset);
 
+/* Adjoint of the Drell-Yan estimator (process VEGAS_DY_Z only).  For B parameter
+ * points theta_b = (M_Z, Gamma_Z, sin^2 theta_W, PDF a, PDF b) (device, [B][5],
+ * 1 <= B <= 64) computes sigma_b = (1/N) sum_i w_i(theta_b) and its gradient
+ * dsigma_b/dtheta (device outputs sigma[B], dsigma[B][5]) over events
+ * i < n_events of iteration index `iteration` at the handle's current grid:
+ * common random numbers for all points, the proposal (grid, Breit-Wigner and
+ * tau mappings) held at the handle's nominal parameters, a hand-written reverse
+ * sweep through |M|^2 and the PDFs per (event, point).  Results do not depend
+ * on the launch configuration.  Asynchronous on the stream; scratch of
+ * 8 * 6 * B * (ceil(n/64) + ceil(n/16384)) bytes is allocated by the library on
+ * first use and kept until vegas_destroy.  (Paper Sec. 2.1 fixes the estimator;
+ * the derivative is this library's extension.)
+ * Errors: VEGAS_EINVAL (other process, B or n out of range, NULL), VEGAS_ENOMEM. */
+int vegas_grad(vegas_handle h, const double *params_dev, int32_t B, int64_t n_events, uint32_t iteration,
+               double *sigma_dev, double *dsigma_dev);
+
 /* Release the handle (and the buffers the library allocated itself). */
 int vegas_destroy(vegas_handle h);
 

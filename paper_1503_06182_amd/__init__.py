@@ -2,7 +2,7 @@
 matrix elements, exact per-iteration combine and grid refinement, behind the C
 ABI of include/vegas.h.  ``vegas`` is the ctypes binding."""
 from .vegas import (DY_Z, EEMUMU, FP32_ME, FP64, GAUSS, GENZ, W_PLUS, WW_4L, Integrator,
-                    VegasError, load, workspace_size)
+                    VegasError, load, vegas_sigma, workspace_size)
 
-__all__ = ["Integrator", "VegasError", "load", "workspace_size", "GAUSS", "GENZ", "EEMUMU",
+__all__ = ["Integrator", "VegasError", "vegas_sigma", "load", "workspace_size", "GAUSS", "GENZ", "EEMUMU",
            "DY_Z", "W_PLUS", "WW_4L", "FP64", "FP32_ME"]

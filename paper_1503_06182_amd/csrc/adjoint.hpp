@@ -1,0 +1,240 @@
+// adjoint.hpp -- hand-written reverse sweep of the Drell-Yan VEGAS estimator with
+// respect to theta = (M_Z, Gamma_Z, sin^2 theta_W, PDF exponent a, PDF exponent b).
+//
+// sigma(theta) = (1/N) sum_i w_i(theta) at a fixed grid and a fixed random stream
+// (common random numbers for every parameter point).  The proposal -- grid map,
+// Breit-Wigner and tau mappings -- stays at the nominal parameters of the handle,
+// so only |M|^2 and the PDFs carry theta, and the pathwise gradient of the
+// estimator is (1/N) sum_i dw_i/dtheta.
+//
+// Work split: one wave owns a tile of 64 consecutive events.  Phase 1, lane =
+// event: the theta-independent part of the event (prefactor, m^2, angular factor,
+// log x sums) goes to LDS.  Phase 2, lane = parameter point: the lane walks the
+// tile's events in order, evaluates w and runs the reverse sweep, and keeps six
+// running sums.  Tile sums are then added by a fixed tree over tile index
+// (chunks of 256 tiles), so the result does not depend on the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "integrands.hpp"
+
+namespace vg {
+
+constexpr int kGradMaxPoints = 64;
+constexpr int kGradVals = 6;  // w, dw/dMZ, dw/dGZ, dw/dsw2, dw/da, dw/db
+constexpr int kTreeRows = 256;
+
+struct GradArgs {
+  PhysConst pc;          // nominal constants of the handle (mappings)
+  const double* edges;   // grid [3][nbins+1]
+  const double* theta;   // [B][5]
+  double* tiles;         // [ntiles][6][B]
+  uint64_t seed;
+  int64_t nev;
+  int64_t ntiles;
+  uint32_t iter;
+  int nbins, B;
+  double e4_12;          // e^4 / 12 (alpha fixed)
+};
+
+// Z couplings g_L = (T3 - Q x)/sqrt(x(1-x)), g_R = -Q sqrt(x/(1-x)), x = sin^2 theta_W,
+// and their derivatives in x
+__device__ __forceinline__ void zcoup(double T3, double Q, double x, double& gL, double& gR, double& dgL,
+                                      double& dgR) {
+  const double sc = sqrt(x * (1.0 - x));
+  gL = (T3 - Q * x) / sc;
+  gR = -Q * sqrt(x / (1.0 - x));
+  dgL = -Q / sc - (T3 - Q * x) * (1.0 - 2.0 * x) / (2.0 * sc * x * (1.0 - x));
+  dgR = -Q / (2.0 * sqrt(x) * (1.0 - x) * sqrt(1.0 - x));
+}
+
+__global__ __launch_bounds__(256) void k_dy_grad(GradArgs a) {
+  extern __shared__ double sm[];
+  const int n = a.nbins;
+  double* e_lds = sm;                                    // [3][n+1]
+  double* evs = sm + 3 * (n + 1);                        // [4 waves][64 events][5]
+  for (int i = threadIdx.x; i < 3 * (n + 1); i += blockDim.x) e_lds[i] = a.edges[i];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  double* ev = evs + wave * 64 * 5;
+
+  // this lane's parameter point (phase 2): couplings and their sw2-derivatives
+  double M = 0, G = 0, x = 0.25, pa = 0, pb = 0;
+  if (lane < a.B) {
+    M = a.theta[5 * lane + 0];
+    G = a.theta[5 * lane + 1];
+    x = a.theta[5 * lane + 2];
+    pa = a.theta[5 * lane + 3];
+    pb = a.theta[5 * lane + 4];
+  }
+  double gg[2][4], dgg[2][4];
+  {
+    double lL, lR, dlL, dlR;
+    zcoup(-0.5, -1.0, x, lL, lR, dlL, dlR);
+    const double gl[2] = {lL, lR}, dgl[2] = {dlL, dlR};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      double qL, qR, dqL, dqR;
+      zcoup(q == 0 ? 0.5 : -0.5, q == 0 ? 2.0 / 3.0 : -1.0 / 3.0, x, qL, qR, dqL, dqR);
+      const double gq[2] = {qL, qR}, dgq[2] = {dqL, dqR};
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int hp = 0; hp < 2; ++hp) {
+          gg[q][2 * h + hp] = gq[h] * gl[hp];
+          dgg[q][2 * h + hp] = dgq[h] * gl[hp] + gq[h] * dgl[hp];
+        }
+    }
+  }
+  const double qql[2] = {-2.0 / 3.0, 1.0 / 3.0};  // Q_q Q_l, Q_l = -1
+  const double pdfA2 = a.pc.pdfA * a.pc.pdfA;
+  __syncthreads();
+
+  const int64_t groups = (a.ntiles + wpb - 1) / wpb;
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    const int64_t tile = grp * wpb + wave;
+    const bool tile_ok = tile < a.ntiles;
+    // ---- phase 1: lane = event, theta-independent part at the nominal proposal
+    if (tile_ok) {
+      const int64_t i = tile * 64 + lane;
+      double P = 0.0, m2 = 1.0, ang = 0.0, ls = 0.0, Ls = 0.0;
+      if (i < a.nev) {
+        double u[3], xx[3];
+        int bins[3];
+        event_uniforms<3>(a.seed, a.iter, static_cast<uint64_t>(i), 3, u);
+        double J = 1.0;
+        {
+#pragma clang fp contract(off)
+          const double dn = static_cast<double>(n);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double t = u[d] * dn;
+            int k = static_cast<int>(t);
+            k = k > n - 1 ? n - 1 : k;
+            const double delta = t - static_cast<double>(k);
+            const double* e = e_lds + d * (n + 1);
+            const double h = e[k + 1] - e[k];
+            xx[d] = __fma_rn(delta, h, e[k]);
+            J *= dn * h;
+            bins[d] = k;
+          }
+        }
+        double jbw;
+        m2 = bw_map(xx[0], a.pc.M2, a.pc.MG, a.pc.m2lo, a.pc.tlo, a.pc.rho_lo, a.pc.rho_rng, jbw);
+        double L, l1, l2;
+        {
+#pragma clang fp contract(off)
+          L = log(m2 * a.pc.invS);
+          l1 = xx[1] * L;
+          l2 = L - l1;
+        }
+        const double jtau = -L * a.pc.invS;
+        const double cs = 2.0 * xx[2] - 1.0;
+        P = a.pc.conv * J * jbw * jtau * 2.0 * (0.5 / m2) * (1.0 / (16.0 * kPi));
+        ang = 2.0 * (1.0 + cs * cs);
+        ls = l1 + l2;
+        Ls = log(-expm1(l1)) + log(-expm1(l2));
+      }
+      ev[lane * 5 + 0] = P;
+      ev[lane * 5 + 1] = m2;
+      ev[lane * 5 + 2] = ang;
+      ev[lane * 5 + 3] = ls;
+      ev[lane * 5 + 4] = Ls;
+    }
+    __syncthreads();
+    // ---- phase 2: lane = parameter point, events of the tile in order
+    if (tile_ok && lane < a.B) {
+      double S[kGradVals] = {0, 0, 0, 0, 0, 0};
+      const double MG = M * G;
+      for (int e = 0; e < 64; ++e) {
+        const double P = ev[e * 5 + 0];
+        if (P == 0.0) continue;
+        const double m2 = ev[e * 5 + 1], ang = ev[e * 5 + 2], ls = ev[e * 5 + 3], Ls = ev[e * 5 + 4];
+        // forward
+        const double ds = m2 - M * M;
+        const double Den = ds * ds + MG * MG;
+        const double iD = 1.0 / Den;
+        const double pre = ds * iD, pim = -MG * iD;
+        const double invs = 1.0 / m2;
+        double sumA = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double re = qql[q] * invs + gg[q][t] * pre;
+            const double im = gg[q][t] * pim;
+            sumA += re * re + im * im;
+          }
+        const double mef = a.e4_12 * m2 * m2 * ang;
+        const double ME = mef * sumA;
+        const double ff = pdfA2 * exp(pa * ls + pb * Ls);
+        const double w = P * ff * ME;
+        // reverse sweep, seeded with dw/dw = 1
+        const double ME_bar = P * ff;
+        const double ff_bar = P * ME;
+        const double a_bar = ff_bar * ff * ls;
+        const double b_bar = ff_bar * ff * Ls;
+        const double sumA_bar = ME_bar * mef;
+        double pre_bar = 0.0, pim_bar = 0.0, x_bar = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double re = qql[q] * invs + gg[q][t] * pre;
+            const double im = gg[q][t] * pim;
+            const double re_bar = 2.0 * re * sumA_bar, im_bar = 2.0 * im * sumA_bar;
+            pre_bar += re_bar * gg[q][t];
+            pim_bar += im_bar * gg[q][t];
+            x_bar += (re_bar * pre + im_bar * pim) * dgg[q][t];
+          }
+        double ds_bar = pre_bar * iD;
+        const double iD_bar = pre_bar * ds - pim_bar * MG;
+        double MG_bar = -pim_bar * iD;
+        const double Den_bar = -iD_bar * iD * iD;
+        ds_bar += Den_bar * 2.0 * ds;
+        MG_bar += Den_bar * 2.0 * MG;
+        const double M_bar = ds_bar * (-2.0 * M) + MG_bar * G;
+        const double G_bar = MG_bar * M;
+        S[0] += w;
+        S[1] += M_bar;
+        S[2] += G_bar;
+        S[3] += x_bar;
+        S[4] += a_bar;
+        S[5] += b_bar;
+      }
+#pragma unroll
+      for (int k = 0; k < kGradVals; ++k) a.tiles[(tile * kGradVals + k) * a.B + lane] = S[k];
+    }
+    __syncthreads();
+  }
+}
+
+// one level of the fixed tree: rows [256 c, 256 c + 256) of every column -> row c
+// (stride-halving pairwise sums over a zero-padded chunk; blockDim must be 256)
+__global__ __launch_bounds__(256) void k_tree_level(const double* in, double* out, int64_t rows, int cols) {
+  __shared__ double s[kTreeRows];
+  const int64_t chunk = blockIdx.x;
+  for (int c = blockIdx.y; c < cols; c += gridDim.y) {
+    const int64_t r = chunk * kTreeRows + threadIdx.x;
+    s[threadIdx.x] = r < rows ? in[r * cols + c] : 0.0;
+    __syncthreads();
+    for (int stride = kTreeRows / 2; stride > 0; stride >>= 1) {
+      if (threadIdx.x < stride) s[threadIdx.x] += s[threadIdx.x + stride];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[chunk * cols + c] = s[0];
+    __syncthreads();
+  }
+}
+
+// final row (6 x B sums) -> sigma[B], dsigma[B][5]
+__global__ void k_grad_out(const double* tot, int B, int64_t nev, double* sigma, double* dsigma) {
+  const int b = threadIdx.x;
+  if (b >= B) return;
+  const double iN = 1.0 / static_cast<double>(nev);
+  sigma[b] = tot[0 * B + b] * iN;
+  for (int k = 0; k < 5; ++k) dsigma[5 * b + k] = tot[(1 + k) * B + b] * iN;
+}
+
+}  // namespace vg

@@ -27,6 +27,7 @@
 #include "vegas.h"
 #include "device_common.hpp"
 #include "integrands.hpp"
+#include "adjoint.hpp"
 
 namespace vg {
 
@@ -676,6 +677,9 @@ struct vegas_state {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;  // (stage, start/stop)
   double stage_ms[4];
   int64_t stage_n[4];
+  // adjoint scratch (library-allocated on first use, grown on demand)
+  double* gbuf;
+  size_t gbuf_doubles;
 };
 
 #define VG_HIP(call)                                                  \
@@ -914,6 +918,7 @@ int vegas_destroy(vegas_handle h) {
     (void)hipEventDestroy(p.second.second);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->gbuf) (void)hipFree(h->gbuf);
   if (h->owns) {
     if (hipStreamSynchronize(h->stream) != hipSuccess) rc = VEGAS_EHIP;
     if (hipFree(h->base) != hipSuccess) rc = VEGAS_EHIP;
@@ -1095,6 +1100,72 @@ int vegas_get_weights(vegas_handle h, int64_t first, int64_t n, double* w, uint8
   if (bins)
     for (int64_t i = 0; i < n; ++i)
       for (int d = 0; d < h->D; ++d) bins[i * h->D + d] = static_cast<uint8_t>(words[(d / 4) * n + i] >> (8 * (d % 4)));
+  return VEGAS_OK;
+}
+
+int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_events, uint32_t iteration,
+               double* sigma_dev, double* dsigma_dev) {
+  if (!h || !params_dev || !sigma_dev || !dsigma_dev) return VEGAS_EINVAL;
+  if (h->cfg.process != VEGAS_DY_Z) return VEGAS_EINVAL;
+  if (B < 1 || B > kGradMaxPoints || n_events < 1 || n_events >= (int64_t(1) << 31)) return VEGAS_EINVAL;
+  const int64_t ntiles = (n_events + 63) / 64;
+  const int cols = kGradVals * B;
+  const int64_t lvl1 = (ntiles + kTreeRows - 1) / kTreeRows;
+  const size_t need = static_cast<size_t>((ntiles + lvl1) * cols);
+  if (h->gbuf_doubles < need) {
+    VG_HIP(hipStreamSynchronize(h->stream));
+    if (h->gbuf) VG_HIP(hipFree(h->gbuf));
+    h->gbuf = nullptr;
+    h->gbuf_doubles = 0;
+    if (hipMalloc(&h->gbuf, need * sizeof(double)) != hipSuccess) {
+      h->gbuf = nullptr;
+      return VEGAS_ENOMEM;
+    }
+    h->gbuf_doubles = need;
+  }
+  double* tiles = h->gbuf;
+  double* lvl = h->gbuf + ntiles * cols;
+  GradArgs ga;
+  ga.pc = h->pc;
+  ga.edges = h->b.edges;
+  ga.theta = params_dev;
+  ga.tiles = tiles;
+  ga.seed = h->cfg.seed;
+  ga.nev = n_events;
+  ga.ntiles = ntiles;
+  ga.iter = iteration;
+  ga.nbins = h->n;
+  ga.B = B;
+  {
+    const double e2 = 4.0 * kPi * h->params[VEGAS_P_ALPHA];
+    ga.e4_12 = e2 * e2 / 12.0;
+  }
+  const int lds = static_cast<int>(sizeof(double) * (3 * (h->n + 1) + 4 * 64 * 5));
+  const int64_t groups = (ntiles + 3) / 4;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&k_dy_grad), 256, lds) !=
+          hipSuccess || occ < 1)
+    occ = 1;
+  int64_t blocks = static_cast<int64_t>(h->ncu) * occ;
+  if (blocks > groups) blocks = groups;
+  hipLaunchKernelGGL(k_dy_grad, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, h->stream, ga);
+  VG_HIP(hipGetLastError());
+  // fixed tree over tiles: 256-row chunks, level by level, ping-pong between the buffers
+  const double* in = tiles;
+  double* out = lvl;
+  int64_t rows = ntiles;
+  while (rows > 1) {
+    const int64_t rout = (rows + kTreeRows - 1) / kTreeRows;
+    const int gy = cols < 64 ? cols : 64;
+    hipLaunchKernelGGL(k_tree_level, dim3(static_cast<unsigned>(rout), gy), dim3(kTreeRows), 0, h->stream, in, out,
+                       rows, cols);
+    VG_HIP(hipGetLastError());
+    rows = rout;
+    in = out;
+    out = (out == lvl) ? tiles : lvl;
+  }
+  hipLaunchKernelGGL(k_grad_out, dim3(1), dim3(64), 0, h->stream, in, B, n_events, sigma_dev, dsigma_dev);
+  VG_HIP(hipGetLastError());
   return VEGAS_OK;
 }
 

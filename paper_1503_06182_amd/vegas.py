@@ -24,7 +24,7 @@ MAX_ITER = 4096
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
-           "vegas_strerror", "vegas_set_timing", "vegas_stage_times"]
+           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad"]
 
 
 class VegasError(RuntimeError):
@@ -75,8 +75,7 @@ def load(path: str = LIB_PATH):
     L.vegas_stage_times.argtypes = [vp, vp, vp, i32]
     L.vegas_strerror.argtypes = [C.c_int]
     L.vegas_strerror.restype = C.c_char_p
-    if hasattr(L, "vegas_grad"):
-        L.vegas_grad.argtypes = [vp, vp, i32, i64, i32, vp, vp]
+    L.vegas_grad.argtypes = [vp, vp, i32, i64, C.c_uint32, vp, vp]
     _lib = L
     return L
 
@@ -206,5 +205,52 @@ class Integrator:
         names = ("event", "accumulate", "finalize", "refine")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
 
+    def grad(self, theta, n_events, iteration):
+        """sigma[B] and dsigma/dtheta[B,5] (Drell-Yan only) for theta[B,5] at the current
+        grid; theta, sigma and dsigma are float64 CUDA tensors on this handle's stream."""
+        import torch
+        theta = theta.detach().to(device="cuda", dtype=torch.float64).contiguous()
+        B = theta.shape[0]
+        sigma = torch.empty(B, dtype=torch.float64, device="cuda")
+        dsigma = torch.empty(B, 5, dtype=torch.float64, device="cuda")
+        _check(self._L.vegas_grad(self._h, C.c_void_p(theta.data_ptr()), B, n_events, iteration,
+                                  C.c_void_p(sigma.data_ptr()), C.c_void_p(dsigma.data_ptr())),
+               "vegas_grad")
+        return sigma, dsigma
+
     def set_launch(self, waves_per_block, max_blocks=0):
         _check(self._L.vegas_set_launch(self._h, waves_per_block, max_blocks), "vegas_set_launch")
+
+
+def _sigma_function():
+    import torch
+
+    class VegasSigma(torch.autograd.Function):
+        """sigma(theta) of the Drell-Yan estimator at a fixed grid and random stream;
+        backward returns grad_sigma[:, None] * dsigma/dtheta from the adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, theta, integrator, n_events, iteration):
+            sigma, dsigma = integrator.grad(theta, n_events, iteration)
+            ctx.save_for_backward(dsigma)
+            ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
+            return sigma.to(device=theta.device, dtype=theta.dtype)
+
+        @staticmethod
+        def backward(ctx, grad_sigma):
+            (dsigma,) = ctx.saved_tensors
+            g = grad_sigma.to(device=dsigma.device, dtype=dsigma.dtype)[:, None] * dsigma
+            return g.to(device=ctx.theta_device, dtype=ctx.theta_dtype), None, None, None
+
+    return VegasSigma
+
+
+def vegas_sigma(theta, integrator, n_events, iteration):
+    """Differentiable sigma(theta) for theta[B,5] (torch float64, requires_grad allowed)."""
+    global VegasSigma
+    if VegasSigma is None:
+        VegasSigma = _sigma_function()
+    return VegasSigma.apply(theta, integrator, n_events, iteration)
+
+
+VegasSigma = None
