@@ -133,8 +133,8 @@ __global__ __launch_bounds__(256) void k_dy_grad(GradArgs a) {
         const double cs = 2.0 * xx[2] - 1.0;
         P = a.pc.conv * J * jbw * jtau * 2.0 * (0.5 / m2) * (1.0 / (16.0 * kPi));
         ang = 2.0 * (1.0 + cs * cs);
-        ls = l1 + l2;
-        Ls = log(-expm1(l1)) + log(-expm1(l2));
+        ls = L;
+        Ls = log(expm1(l1) * expm1(l2));
       }
       ev[lane * 5 + 0] = P;
       ev[lane * 5 + 1] = m2;

@@ -65,11 +65,6 @@ __device__ __forceinline__ double bw_map(double r, double M2, double MG, double 
   return m2;
 }
 
-// A x^a (1-x)^b from ln x and ln(1-x)
-__device__ __forceinline__ double pdf_l(const PhysConst& c, double lnx, double ln1mx) {
-  return c.pdfA * exp(c.pdfa * lnx + c.pdfb * ln1mx);
-}
-
 // ---------------------------------------------------------------------------
 // test integrands
 // ---------------------------------------------------------------------------
@@ -145,8 +140,9 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
     l2 = L - l1;
   }
   const double jtau = -L * c.invS;
-  const double f1 = pdf_l(c, l1, log(-expm1(l1)));
-  const double f2 = pdf_l(c, l2, log(-expm1(l2)));
+  // f(x1) f(x2) = A^2 exp(a ln(x1 x2) + b ln((1-x1)(1-x2))), ln(x1 x2) = ln tau,
+  // 1 - x = -expm1(ln x)
+  const double ff = c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(expm1(l1) * expm1(l2)));
   const double cs = 2.0 * x[2] - 1.0;
   // 1 / (shat - MZ^2 + i MZ GZ)
   const double ds = m2 - c.mz2;
@@ -164,7 +160,7 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
     }
   const double me = c.e4_12 * m2 * m2 * sum * 2.0 * (1.0 + cs * cs);
   // conv * J_bw * J_tau * J_cos(2) * flux 1/(2 shat) * 2 pi / (32 pi^2)
-  return c.conv * jbw * jtau * 2.0 * (0.5 * inv_s) * (1.0 / (16.0 * kPi)) * f1 * f2 * me;
+  return c.conv * jbw * jtau * 2.0 * (0.5 * inv_s) * (1.0 / (16.0 * kPi)) * ff * me;
 }
 
 // ---------------------------------------------------------------------------
@@ -185,19 +181,19 @@ __device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
   }
   const double jtau = -L * c.invS;
   const double cs = 2.0 * x[2] - 1.0;
-  const double x1 = exp(l1), x2 = exp(l2);
+  // x = 1 + expm1(ln x): beta = (x1 - x2)/(x1 + x2) and 1 - x from the same two values
+  const double em1 = expm1(l1), em2 = expm1(l2);
   const double pt2 = 0.25 * m2 * (1.0 - cs) * (1.0 + cs);
-  const double beta = (x1 - x2) / (x1 + x2);
+  const double beta = (em1 - em2) / (2.0 + em1 + em2);
   const double num = cs + beta, dnm = 1.0 + beta * cs;
   const bool pass = (pt2 > c.ptmin2) && (num * num < c.th2 * dnm * dnm);
   if (!pass) return 0.0;
   const double ds = m2 - c.M2;
   const double den = ds * ds + c.MG * c.MG;
   const double me = c.g4v2_24 * m2 * m2 * (1.0 + cs * cs) / den;
-  const double f1 = pdf_l(c, l1, log(-expm1(l1)));
-  const double f2 = pdf_l(c, l2, log(-expm1(l2)));
+  const double ff = c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(em1 * em2));
   // conv * J_bw * J_tau * flux 1/(2 shat) * (2 * 2 pi)/(32 pi^2)
-  return c.conv * jbw * jtau * (0.5 / m2) * (1.0 / (8.0 * kPi)) * f1 * f2 * me;
+  return c.conv * jbw * jtau * (0.5 / m2) * (1.0 / (8.0 * kPi)) * ff * me;
 }
 
 // ---------------------------------------------------------------------------
@@ -271,12 +267,11 @@ __device__ __forceinline__ cx<R> mdot_r(const R a[4], const cx<R> b[4]) {
 // [ (sigma-bar.e2)(sigma.k)(sigma-bar.e1) ]_{01}; sigma-bar.e = e^0 + sigma.e,
 // sigma.k = k^0 - sigma.k (k real)
 template <typename R>
-__device__ __forceinline__ cx<R> chain01(const cx<R> e2[4], const R k[4], const cx<R> e1[4]) {
+__device__ __forceinline__ cx<R> chain01(const cx<R> e2[4], const R k[4], R B00, R B11, const cx<R> e1[4]) {
   const cx<R> A00 = cadd(e2[0], e2[3]);
   const cx<R> A01 = {e2[1].re + e2[2].im, e2[1].im - e2[2].re};  // e2^1 - i e2^2
   const cx<R> C01 = {e1[1].re + e1[2].im, e1[1].im - e1[2].re};  // e1^1 - i e1^2
   const cx<R> C11 = csub(e1[0], e1[3]);
-  const R B00 = k[0] - k[3], B11 = k[0] + k[3];
   const cx<R> B01 = {-k[1], k[2]};   // -(k1 - i k2)
   const cx<R> B10 = {-k[1], -k[2]};  // -(k1 + i k2)
   const cx<R> y0 = cadd(cscale(C01, B00), cmul(B01, C11));
@@ -284,10 +279,18 @@ __device__ __forceinline__ cx<R> chain01(const cx<R> e2[4], const R k[4], const 
   return cadd(cmul(A00, y0), cmul(A01, y1));
 }
 
+// exchange-propagator invariants: t = k^2 and k^0 -+ k^3 for k = p1 - q(W+) (u quark)
+// and k = p1 - q(W-) (d quark); given when they were formed in binary64 from the
+// mapped masses (used by the binary32 amplitude), else taken from the momenta
+template <typename R>
+struct ExchInv {
+  R tu, td, b00u, b11u, b00d, b11d;
+};
+
 // sum over q in {u, d} and quark helicity of |M|^2 (no averages)
 template <typename R>
 __device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p4[4], const R p5[4],
-                                    const R p6[4], R mp2, R mm2) {
+                                    const R p6[4], R mp2, R mm2, const ExchInv<R>* inv) {
   cx<R> a3_0, a3_1, a4_0, a4_1, a5_0, a5_1, a6_0, a6_1;
   spinor_m(p3, a3_0, a3_1);
   spinor_m(p4, a4_0, a4_1);
@@ -331,10 +334,24 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p
   const R half = rs * R(0.5);
   R ku[4] = {half - qp[0], -qp[1], -qp[2], half - qp[3]};
   R kd[4] = {half - qm[0], -qm[1], -qm[2], half - qm[3]};
-  const R tu = ku[0] * ku[0] - ku[1] * ku[1] - ku[2] * ku[2] - ku[3] * ku[3];
-  const R td = kd[0] * kd[0] - kd[1] * kd[1] - kd[2] * kd[2] - kd[3] * kd[3];
-  const cx<R> Tu = chain01(em, ku, ep);
-  const cx<R> Td = chain01(ep, kd, em);
+  R tu, td, b00u, b11u, b00d, b11d;
+  if (inv) {
+    tu = inv->tu;
+    td = inv->td;
+    b00u = inv->b00u;
+    b11u = inv->b11u;
+    b00d = inv->b00d;
+    b11d = inv->b11d;
+  } else {
+    tu = ku[0] * ku[0] - ku[1] * ku[1] - ku[2] * ku[2] - ku[3] * ku[3];
+    td = kd[0] * kd[0] - kd[1] * kd[1] - kd[2] * kd[2] - kd[3] * kd[3];
+    b00u = ku[0] - ku[3];
+    b11u = ku[0] + ku[3];
+    b00d = kd[0] - kd[3];
+    b11d = kd[0] + kd[3];
+  }
+  const cx<R> Tu = chain01(em, ku, b00u, b11u, ep);
+  const cx<R> Td = chain01(ep, kd, b00d, b11d, em);
   const R ct = static_cast<R>(c.ct);
   const R fu = -rs * ct / tu, fd = -rs * ct / td;
   const cx<R> csuL = {static_cast<R>(c.cs_re[0][0]), static_cast<R>(c.cs_im[0][0])};
@@ -345,13 +362,13 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p
 }
 
 // rest frame of Q (mass m) -> frame of Q, for k and its back-to-back partner
-__device__ __forceinline__ void boost_pair(const double Q[4], double m, const double k[4],
-                                           double a[4], double b[4]) {
-  const double qk = Q[1] * k[1] + Q[2] * k[2] + Q[3] * k[3];
-  const double im = 1.0 / m, iqm = 1.0 / (Q[0] + m);
-  const double Ea = (Q[0] * k[0] + qk) * im;
-  const double Eb = (Q[0] * k[0] - qk) * im;
-  const double fa = (k[0] + Ea) * iqm, fb = (k[0] + Eb) * iqm;
+template <typename R>
+__device__ __forceinline__ void boost_pair(const R Q[4], R m, const R k[4], R a[4], R b[4]) {
+  const R qk = Q[1] * k[1] + Q[2] * k[2] + Q[3] * k[3];
+  const R im = R(1) / m, iqm = R(1) / (Q[0] + m);
+  const R Ea = (Q[0] * k[0] + qk) * im;
+  const R Eb = (Q[0] * k[0] - qk) * im;
+  const R fa = (k[0] + Ea) * iqm, fb = (k[0] + Eb) * iqm;
   a[0] = Ea;
   b[0] = Eb;
 #pragma unroll
@@ -361,8 +378,13 @@ __device__ __forceinline__ void boost_pair(const double Q[4], double m, const do
   }
 }
 
+__device__ __forceinline__ void sincos_2pi(double x, double& s, double& c) { sincospi(2.0 * x, &s, &c); }
+__device__ __forceinline__ void sincos_2pi(float x, float& s, float& c) { sincospif(2.0f * x, &s, &c); }
+
 // WW_4L: x0 -> m+^2 (BW on [0, shat]), x1 -> m-^2 (BW on [0, (rs - m+)^2]),
 // x2, x3 -> W+ direction, x4..x7 -> lepton directions in the W rest frames.
+// Phase space (masses, momenta, lambda, Jacobian) is binary64; only the
+// amplitude (spinors, currents, diagrams) is evaluated in R.
 template <typename R>
 __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x) {
   double jp, jm;
@@ -383,36 +405,56 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x) {
   const double Ep = (sh + mp2 - mm2) * i2rs, Em = (sh - mp2 + mm2) * i2rs;
   const double ct = 2.0 * x[2] - 1.0, st = sqrt((1.0 - ct) * (1.0 + ct));
   double sf, cf;
-  sincos(2.0 * kPi * x[3], &sf, &cf);
+  sincos_2pi(x[3], sf, cf);
   const double qp[4] = {Ep, q * st * cf, q * st * sf, q * ct};
   const double qm[4] = {Em, -qp[1], -qp[2], -qp[3]};
-  double p3[4], p4[4], p5[4], p6[4];
+  double d3[4], d4[4], d5[4], d6[4];
   {
     const double c3 = 2.0 * x[4] - 1.0, s3 = sqrt((1.0 - c3) * (1.0 + c3));
     double s, cc;
-    sincos(2.0 * kPi * x[5], &s, &cc);
+    sincos_2pi(x[5], s, cc);
     const double h = 0.5 * mp;
     const double k[4] = {h, h * s3 * cc, h * s3 * s, h * c3};
-    boost_pair(qp, mp, k, p3, p4);
+    boost_pair<double>(qp, mp, k, d3, d4);
   }
   {
     const double c5 = 2.0 * x[6] - 1.0, s5 = sqrt((1.0 - c5) * (1.0 + c5));
     double s, cc;
-    sincos(2.0 * kPi * x[7], &s, &cc);
+    sincos_2pi(x[7], s, cc);
     const double h = 0.5 * mm;
     const double k[4] = {h, h * s5 * cc, h * s5 * s, h * c5};
-    boost_pair(qm, mm, k, p5, p6);
+    boost_pair<double>(qm, mm, k, d5, d6);
   }
-  R r3[4], r4[4], r5[4], r6[4];
+  R p3[4], p4[4], p5[4], p6[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    r3[i] = static_cast<R>(p3[i]);
-    r4[i] = static_cast<R>(p4[i]);
-    r5[i] = static_cast<R>(p5[i]);
-    r6[i] = static_cast<R>(p6[i]);
+    p3[i] = static_cast<R>(d3[i]);
+    p4[i] = static_cast<R>(d4[i]);
+    p5[i] = static_cast<R>(d5[i]);
+    p6[i] = static_cast<R>(d6[i]);
   }
-  const double me = static_cast<double>(
-      ww_me2<R>(c, r3, r4, r5, r6, static_cast<R>(mp2), static_cast<R>(mm2)));
+  const double two = 2.0;
+  (void)two;
+  double me;
+  if constexpr (sizeof(R) < sizeof(double)) {
+    // binary32 amplitude: the exchange invariants cancel for forward W bosons, so
+    // they are formed here in binary64 without cancellation,
+    // E -+ q cos = m^2 / (E + q) + q (1 -+ cos) for the W+ (and with cos -> -cos for the W-)
+    const double qd = sl * i2rs, Epd = (sh + mp2 - mm2) * i2rs, Emd = (sh - mp2 + mm2) * i2rs;
+    const double cd = 2.0 * x[2] - 1.0;
+    const double epm = mp2 / (Epd + qd) + qd * (1.0 - cd);  // Ep - q cos
+    const double emm = mm2 / (Emd + qd) + qd * (1.0 + cd);  // Em + q cos
+    ExchInv<R> iv;
+    iv.tu = static_cast<R>(mp2 - c.rs * epm);
+    iv.td = static_cast<R>(mm2 - c.rs * emm);
+    iv.b00u = static_cast<R>(-epm);
+    iv.b11u = static_cast<R>(c.rs - (Epd + qd * cd));
+    iv.b00d = static_cast<R>(-emm);
+    iv.b11d = static_cast<R>(c.rs - (Emd - qd * cd));
+    me = static_cast<double>(ww_me2<R>(c, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), &iv));
+  } else {
+    me = static_cast<double>(ww_me2<R>(c, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
+  }
   // dPhi_2(P) (4 pi) * dm+^2/(2 pi) * dm-^2/(2 pi) * [dPhi_2(W) (4 pi)]^2
   const double jac = sl / (8.0 * kPi * sh) * (jp / (2.0 * kPi)) * (jm / (2.0 * kPi)) *
                      (1.0 / (64.0 * kPi * kPi));

@@ -106,8 +106,14 @@ struct EventArgs {
 // ---------------------------------------------------------------------------
 // K1: events
 // ---------------------------------------------------------------------------
+// waves per SIMD the register allocation must allow with 256-thread blocks
+template <int PROC>
+constexpr int event_min_waves() {
+  return PROC == VEGAS_WW_4L ? 2 : 4;
+}
+
 template <int PROC, int PREC, int D, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_event(EventArgs a) {
+__global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) void k_event(EventArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.nbins, nd = D > 0 ? D : a.ndim;
   double* e_lds = reinterpret_cast<double*>(smem);

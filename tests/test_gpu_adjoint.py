@@ -82,7 +82,7 @@ def test_adjoint_matches_central_differences(setup):
 
 def test_autograd_function(setup):
     P, g, o, torch = setup
-    theta = torch.tensor(W.adjoint_points(64), requires_grad=True)
+    theta = torch.tensor(W.adjoint_points(64), device="cuda", requires_grad=True)
     n = 8192
     sigma = P.vegas_sigma(theta, g, n, 5)
     wts = torch.linspace(0.5, 1.5, 64, dtype=torch.float64, device="cuda")
