@@ -194,6 +194,92 @@ int vegas_grad(vegas_handle h, const double *params_dev, int32_t B, int64_t n_ev
 /* Release the handle (and the buffers the library allocated itself). */
 int vegas_destroy(vegas_handle h);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal (this library's extension; the paper's proposal is the
+ * VEGAS grid of Sec. 2.1).  A normalising flow q on the unit hypercube
+ * [0,1]^8 that the grid map is applied to: six coupling layers, each mapping
+ * four coordinates by monotone rational-quadratic splines (16 bins) whose
+ * parameters an MLP 4 -> 128 -> 128 -> 188 (ReLU) computes from the other four
+ * (Durkan et al., Neural Spline Flows, 2019).  The MLP runs in bfloat16 with
+ * binary32 accumulation on the matrix cores; splines, log-densities and the
+ * FP32 master weights are binary32.  A flow iteration draws z uniform from
+ * the same counter-based stream as a VEGAS iteration, y = F^{-1}(z), x = the
+ * grid map of y, and weights w = f(x) J(y) / q(y): an unbiased estimate of the
+ * same integral for any flow parameters.
+ *
+ * Flat parameter vector (binary32, 248424 values), per layer l = 0..5 in
+ * order: W1 [4][128], b1 [128], W2 [128][128], b2 [128], W3 [128][188],
+ * b3 [188] (input-major).  Layer l transforms the coordinates
+ * {4567},{0123},{1357},{0246},{2367},{0145} (l = 0..5) and is conditioned on
+ * the other four in increasing order; the 188 outputs are, per transformed
+ * coordinate in increasing order, 16 width logits, 16 height logits and 15
+ * interior-derivative pre-activations.
+ * ---------------------------------------------------------------------- */
+typedef struct vegas_flow_state *vegas_flow;
+
+#define VEGAS_FLOW_NPARAMS 248424
+
+/* Create a flow: He-uniform hidden layers from the counter-based generator
+ * keyed by seed, zero output layer (the identity map, q = 1).  max_batch
+ * (1 .. 2^22) bounds the batch of the density / training calls; max_sample
+ * (0 .. 2^31-1) the events of a flow iteration.  The library allocates
+ * about 3.4 KB per batch event plus 36 B per sample event plus 5 MB of
+ * device memory, freed by vegas_flow_destroy.  stream: hipStream_t or NULL.
+ * Errors: VEGAS_EINVAL, VEGAS_ENOMEM, VEGAS_EHIP. */
+int vegas_flow_create(int32_t max_batch, int64_t max_sample, uint64_t seed, void *stream, vegas_flow *out);
+int vegas_flow_destroy(vegas_flow f);
+
+/* Copy the FP32 master parameters out (device dst [VEGAS_FLOW_NPARAMS]) or in
+ * (device src; refreshes the bfloat16 copies and resets the optimiser moments
+ * and step count).  Asynchronous.  Errors: VEGAS_EINVAL, VEGAS_EHIP. */
+int vegas_flow_get_params(vegas_flow f, float *dst_dev);
+int vegas_flow_set_params(vegas_flow f, const float *src_dev);
+
+/* log q(y) for B points (device y [B][8] in [0,1], device logq [B]),
+ * 1 <= B <= max_batch.  Asynchronous.  Errors: VEGAS_EINVAL, VEGAS_EHIP. */
+int vegas_flow_density(vegas_flow f, const float *y_dev, int64_t B, float *logq_dev);
+
+/* Loss L = -sum_i w_i log q(y_i) / sum_i w_i over B weighted points (device y
+ * [B][8], device w [B], w >= 0 with a positive sum) and its gradient with
+ * respect to the parameters, written to device grad [VEGAS_FLOW_NPARAMS]
+ * (nullable).  loss (host, nullable): if given, the call waits for the stream.
+ * Errors: VEGAS_EINVAL, VEGAS_EHIP. */
+int vegas_flow_loss_grad(vegas_flow f, const float *y_dev, const double *w_dev, int64_t B, float *grad_dev,
+                         double *loss_host);
+
+/* One Adam step (beta = 0.9, 0.999, eps = 1e-8, learning rate lr) on a batch
+ * of `batch` points of a data set of n_data (1 .. 2^31-1) weighted points
+ * (device y [n_data][8], w [n_data]).  Step s takes positions [(s mod m) batch, ...) of
+ * epoch floor(s / m), m = ceil(n_data / batch), through a per-epoch
+ * permutation i -> (a i + c) mod n_data (wrapping at the end of the data).
+ * loss (host, nullable) as for vegas_flow_loss_grad.
+ * Errors: VEGAS_EINVAL, VEGAS_EHIP. */
+int vegas_flow_train_step(vegas_flow f, const float *y_dev, const double *w_dev, int64_t n_data, int32_t batch,
+                          uint64_t step, float lr, double *loss_host);
+
+/* Sampling direction: y = F^{-1}(z) and log q(y) for n points (device z, y
+ * [n][8], y may equal z; device logq [n]).  Asynchronous.
+ * Errors: VEGAS_EINVAL, VEGAS_EHIP. */
+int vegas_flow_sample(vegas_flow f, const float *z_dev, int64_t n, float *y_dev, float *logq_dev);
+
+/* Training data from the last iteration of h (a VEGAS iteration, not a flow
+ * one): events [first, first+n) as device y [n][8] (binary32 rounding of the
+ * event's uniform point, before the grid map) and device w [n] (its weight).
+ * Requires ndim = 8.  Asynchronous.
+ * Errors: VEGAS_EINVAL (range, ndim), VEGAS_ESTATE (no VEGAS iteration yet,
+ * or the last iteration used the flow). */
+int vegas_export(vegas_handle h, int64_t first, int64_t n, float *y_dev, double *w_dev);
+
+/* One iteration with the flow as proposal: z_i from the stream keyed by
+ * (seed, j, i) as in vegas_iterate, y_i = F^{-1}(z_i), then the same grid map,
+ * integrand, exact accumulation and combination as vegas_iterate, with
+ * w_i = f(x_i) J(y_i) exp(-log q(y_i)).  The grid is frozen: vegas_refine after
+ * a flow iteration returns VEGAS_ESTATE.  Requires ndim = 8 and
+ * n_events <= the flow's max_sample.  The flow's work is ordered on the
+ * handle's stream after the flow's own stream.  out as for vegas_iterate.
+ * Errors: as vegas_iterate. */
+int vegas_iterate_flow(vegas_handle h, vegas_flow f, int64_t n_events, vegas_iter_result *out);
+
 /* Message for a status code. */
 const char *vegas_strerror(int status);
 

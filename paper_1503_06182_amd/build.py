@@ -13,8 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libvegas.so")
-SOURCES = [os.path.join(HERE, "csrc", "vegas.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("device_common.hpp", "integrands.hpp")] + [
+SOURCES = [os.path.join(HERE, "csrc", "vegas.hip"), os.path.join(HERE, "csrc", "flow.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("device_common.hpp", "integrands.hpp", "adjoint.hpp", "flow.hpp")] + [
     os.path.join(ROOT, "include", "vegas.h")]
 ARCH = os.environ.get("VEGAS_OFFLOAD_ARCH", "gfx950")
 

@@ -1,0 +1,258 @@
+// flow.hpp -- learned proposal on the VEGAS y-space: a coupling-layer
+// rational-quadratic spline flow (Durkan et al., Neural Spline Flows, 2019)
+// with BF16 MFMA MLPs (FP32 accumulate) and FP32 splines, for gfx950.
+//
+// Layer l leaves its four conditioning coordinates unchanged and maps each of
+// the four others by a monotone 16-bin rational-quadratic spline on [0,1]
+// whose 47 parameters come from an MLP 4 -> 128 -> 128 -> 188 (ReLU) of the
+// conditioning coordinates.  Density direction y -> z: layers 0..5, forward
+// splines, log q(y) = sum log s'.  Sampling direction z -> y: layers 5..0,
+// inverse splines.  Base density uniform on [0,1]^8.
+//
+// One block (256 threads = 4 waves) owns a tile of 32 events: the first layer
+// of the MLP on the VALU (K = 4), the two 128-wide contractions on
+// v_mfma_f32_16x16x16_bf16 (A from LDS, B = weights from global memory,
+// stored so that each lane's four k-consecutive operands are one 8-byte load),
+// then one thread per (event, transformed coordinate) for the spline.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vg {
+
+constexpr int FL_NDIM = 8, FL_NB = 16, FL_NPAR = 47, FL_HID = 128, FL_NOUT = 188, FL_NOUTP = 192;
+constexpr int FL_NLAYER = 6, FL_TILE = 32;
+constexpr int FL_LAYER = 4 * FL_HID + FL_HID + FL_HID * FL_HID + FL_HID + FL_HID * FL_NOUT + FL_NOUT;  // 41404
+constexpr int FL_NPARAMS = FL_NLAYER * FL_LAYER;                                                   // 248424
+// offsets inside one layer of the FP32 master vector: W1 [4][128], b1, W2 [128][128], b2, W3 [128][188], b3
+constexpr int FO_W1 = 0, FO_B1 = 512, FO_W2 = 640, FO_B2 = 17024, FO_W3 = 17152, FO_B3 = 41216;
+// BF16 copies per layer: transposed (for the forward) W2t [128 out][128 in], W3t [192 out][128 in];
+// natural (for the backward) W2n [128 in][128 out], W3n [128 in][192 out]; padded columns zero
+constexpr int FB_W2T = 0, FB_W3T = 16384, FB_W2N = 16384 + 24576, FB_W3N = 2 * 16384 + 24576;
+constexpr int FB_LAYER = 2 * 16384 + 2 * 24576;  // 81920 bf16 per layer
+constexpr float FL_EPS = 1e-3f;
+constexpr int FL_LDA = FL_HID + 4;   // LDS row stride (bf16) of the activation tiles: no bank conflicts
+constexpr int FL_LDP = FL_NOUTP + 4; // LDS row stride (fp32) of the spline-parameter tile
+
+// transformed coordinates of each layer (the conditioning coordinates are the rest, in order)
+__device__ __constant__ const int kFlowX[FL_NLAYER][4] = {{4, 5, 6, 7}, {0, 1, 2, 3}, {1, 3, 5, 7},
+                                                           {0, 2, 4, 6}, {2, 3, 6, 7}, {0, 1, 4, 5}};
+__device__ __constant__ const int kFlowC[FL_NLAYER][4] = {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 2, 4, 6},
+                                                           {1, 3, 5, 7}, {0, 1, 4, 5}, {2, 3, 6, 7}};
+
+typedef short __attribute__((ext_vector_type(4))) bf16x4_t;
+typedef float __attribute__((ext_vector_type(4))) f32x4_t;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+// C(16x16 at r0, c0) = sum_k A[r][k] Bt[c][k]: A rows in LDS (stride lda, bf16), Bt rows in
+// global memory (stride ldb, bf16).  Lane l supplies A[r0 + l%16][k0 + 4(l/16) .. +3] and
+// Bt[c0 + l%16][k0 + 4(l/16) .. +3]; acc[j] = C[r0 + 4(l/16) + j][c0 + l%16].
+__device__ __forceinline__ f32x4_t mfma_rowcol(const uint16_t* A, int lda, const uint16_t* __restrict__ Bt, int ldb,
+                                               int r0, int c0, int K, int lane) {
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  const int ri = lane & 15, kq = 4 * (lane >> 4);
+  const uint16_t* ap = A + (r0 + ri) * lda + kq;
+  const uint16_t* bp = Bt + static_cast<int64_t>(c0 + ri) * ldb + kq;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(ap + k0);
+    const bf16x4_t b = *reinterpret_cast<const bf16x4_t*>(bp + k0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// rational-quadratic spline on [0,1], 16 bins, boundary derivatives 1
+// ---------------------------------------------------------------------------
+struct Knots {
+  float xk[FL_NB + 1], yk[FL_NB + 1], dk[FL_NB + 1];
+  float pw[FL_NB], ph[FL_NB];  // softmax outputs (for the backward)
+};
+
+__device__ __forceinline__ float softplusf(float z) { return z > 20.f ? z : log1pf(expf(z)); }
+
+__device__ __forceinline__ void make_knots(const float* raw, Knots& K) {
+  const float scale = 1.f - FL_NB * FL_EPS;
+  float m = raw[0];
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, raw[i]);
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    K.pw[i] = expf(raw[i] - m);
+    s += K.pw[i];
+  }
+  float is = 1.f / s, acc = 0.f;
+  K.xk[0] = 0.f;
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    K.pw[i] *= is;
+    acc += FL_EPS + scale * K.pw[i];
+    K.xk[i + 1] = acc;
+  }
+  K.xk[FL_NB] = 1.f;
+  m = raw[FL_NB];
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, raw[FL_NB + i]);
+  s = 0.f;
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    K.ph[i] = expf(raw[FL_NB + i] - m);
+    s += K.ph[i];
+  }
+  is = 1.f / s;
+  acc = 0.f;
+  K.yk[0] = 0.f;
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    K.ph[i] *= is;
+    acc += FL_EPS + scale * K.ph[i];
+    K.yk[i + 1] = acc;
+  }
+  K.yk[FL_NB] = 1.f;
+  const float shift = 0.53974242f;  // log(expm1(1 - eps)) for eps = 1e-3: raw 0 gives derivative 1
+  K.dk[0] = 1.f;
+  K.dk[FL_NB] = 1.f;
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) K.dk[i] = FL_EPS + softplusf(raw[2 * FL_NB + i - 1] + shift);
+}
+
+// bin of v among the knots t[1..15] (number of interior knots below v), clamped to [0, 15]
+__device__ __forceinline__ int knot_bin(const float* t, float v) {
+  int k = 0;
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) k += (t[i] < v) ? 1 : 0;
+  return k;
+}
+
+// the six numbers of bin k (selected with an unrolled loop so the knot arrays stay in registers)
+struct Bin {
+  float x0, x1, y0, y1, d0, d1;
+};
+
+__device__ __forceinline__ Bin pick_bin(const Knots& K, int k) {
+  Bin b{K.xk[0], K.xk[1], K.yk[0], K.yk[1], K.dk[0], K.dk[1]};
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i)
+    if (i == k) b = Bin{K.xk[i], K.xk[i + 1], K.yk[i], K.yk[i + 1], K.dk[i], K.dk[i + 1]};
+  return b;
+}
+
+__device__ __forceinline__ float rqs_fwd(const Knots& K, float x, float& ld) {
+  const Bin q = pick_bin(K, knot_bin(K.xk, x));
+  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
+  const float s = h / w;
+  const float xi = (x - q.x0) / w, t = xi * (1.f - xi);
+  const float den = s + (q.d1 + q.d0 - 2.f * s) * t;
+  const float y = q.y0 + h * (s * xi * xi + q.d0 * t) / den;
+  const float P = q.d1 * xi * xi + 2.f * s * t + q.d0 * (1.f - xi) * (1.f - xi);
+  ld = logf(s * s * P / (den * den));
+  return y;
+}
+
+__device__ __forceinline__ float rqs_inv(const Knots& K, float y, float& ld) {
+  const Bin q = pick_bin(K, knot_bin(K.yk, y));
+  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
+  const float s = h / w;
+  const float dy = y - q.y0;
+  const float g = q.d1 + q.d0 - 2.f * s;
+  const float a = h * (s - q.d0) + dy * g;
+  const float b = h * q.d0 - dy * g;
+  const float c = -s * dy;
+  const float disc = fmaxf(b * b - 4.f * a * c, 0.f);
+  float xi = 2.f * c / (-b - sqrtf(disc));
+  xi = fminf(fmaxf(xi, 0.f), 1.f);
+  const float x = q.x0 + xi * w;
+  const float t = xi * (1.f - xi);
+  const float den = s + g * t;
+  const float P = q.d1 * xi * xi + 2.f * s * t + q.d0 * (1.f - xi) * (1.f - xi);
+  ld = logf(s * s * P / (den * den));
+  return x;
+}
+
+// reverse sweep of (y, log s') = spline(x; raw): given ybar and ldbar, returns xbar and
+// writes rawbar[47]
+__device__ __forceinline__ float rqs_bwd(const float* raw, const Knots& K, float x, float ybar, float ldbar,
+                                         float* rawbar) {
+  const int k = knot_bin(K.xk, x);
+  const Bin q = pick_bin(K, k);
+  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
+  const float s = h / w, d0 = q.d0, d1 = q.d1;
+  const float xi = (x - q.x0) / w, t = xi * (1.f - xi);
+  const float g = d1 + d0 - 2.f * s;
+  const float den = s + g * t;
+  const float num = s * xi * xi + d0 * t;
+  const float omx = 1.f - xi;
+  const float P = d1 * xi * xi + 2.f * s * t + d0 * omx * omx;
+  float sb = 0.f, tb = 0.f, xib = 0.f, d0b = 0.f, d1b = 0.f, denb = 0.f, hb = 0.f, wb = 0.f, ykb = 0.f, xkb = 0.f;
+  // ld = 2 log s + log P - 2 log den
+  sb += ldbar * 2.f / s;
+  const float Pb = ldbar / P;
+  denb += -2.f * ldbar / den;
+  d1b += Pb * xi * xi;
+  sb += Pb * 2.f * t;
+  tb += Pb * 2.f * s;
+  d0b += Pb * omx * omx;
+  xib += Pb * (2.f * d1 * xi - 2.f * d0 * omx);
+  // y = y_k + h num / den
+  ykb += ybar;
+  hb += ybar * num / den;
+  const float numb = ybar * h / den;
+  denb += -ybar * h * num / (den * den);
+  sb += numb * xi * xi;
+  xib += numb * 2.f * s * xi;
+  d0b += numb * t;
+  tb += numb * d0;
+  // den = s + (d1 + d0 - 2 s) t
+  sb += denb * (1.f - 2.f * t);
+  d1b += denb * t;
+  d0b += denb * t;
+  tb += denb * g;
+  // t = xi (1 - xi)
+  xib += tb * (1.f - 2.f * xi);
+  // xi = (x - x_k) / w
+  const float xbar = xib / w;
+  xkb += -xib / w;
+  wb += -xib * xi / w;
+  // s = h / w
+  hb += sb / w;
+  wb += -sb * h / (w * w);
+  // w = x_{k+1} - x_k, h = y_{k+1} - y_k; x_j = sum_{i<j} width_i for j <= 15 (x_16 = 1 fixed)
+  const float xk1b = (k + 1 < FL_NB) ? wb : 0.f, yk1b = (k + 1 < FL_NB) ? hb : 0.f;
+  xkb -= wb;
+  ykb -= hb;
+  // widths_i = eps + (1 - 16 eps) softmax_i: raw bar_j = p_j (pbar_j - sum_i p_i pbar_i)
+  const float scale = 1.f - FL_NB * FL_EPS;
+  float wib[FL_NB], hib[FL_NB];
+  float dotw = 0.f, doth = 0.f;
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    wib[i] = scale * ((i < k ? xkb : 0.f) + (i < k + 1 ? xk1b : 0.f));
+    hib[i] = scale * ((i < k ? ykb : 0.f) + (i < k + 1 ? yk1b : 0.f));
+    dotw += K.pw[i] * wib[i];
+    doth += K.ph[i] * hib[i];
+  }
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    rawbar[i] = K.pw[i] * (wib[i] - dotw);
+    rawbar[FL_NB + i] = K.ph[i] * (hib[i] - doth);
+  }
+  // interior derivatives d_j = eps + softplus(raw_{32 + j - 1} + shift), j = 1..15
+  const float shift = 0.53974242f;
+#pragma unroll
+  for (int j = 1; j < FL_NB; ++j) {
+    const float z = raw[2 * FL_NB + j - 1] + shift;
+    const float sig = 1.f / (1.f + expf(-z));
+    const float db = (j == k ? d0b : 0.f) + (j == k + 1 ? d1b : 0.f);
+    rawbar[2 * FL_NB + j - 1] = db * sig;
+  }
+  return xbar;
+}
+
+}  // namespace vg

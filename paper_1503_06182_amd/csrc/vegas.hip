@@ -18,6 +18,7 @@
 // Sec. 2.2, made structural).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -101,18 +102,24 @@ struct EventArgs {
   int64_t stride_rec;  // maxN (record plane stride)
   uint32_t iter;
   int ndim, nbins;
+  const float* ext_y;   // learned proposal: points y [nev][8] and log q(y) [nev] (EXT kernels only)
+  const float* ext_lq;
 };
 
 // ---------------------------------------------------------------------------
 // K1: events
 // ---------------------------------------------------------------------------
 // waves per SIMD the register allocation must allow with 256-thread blocks
+constexpr double kExtLo = 0x1p-40, kExtHi = 1.0 - 0x1p-40;
+
 template <int PROC>
 constexpr int event_min_waves() {
   return PROC == VEGAS_WW_4L ? 2 : 4;
 }
 
-template <int PROC, int PREC, int D, int MAXT>
+// EXT: the point is the learned proposal's y (binary32, kept inside the open unit
+// cube) instead of the event's uniforms, and the weight is divided by q(y)
+template <int PROC, int PREC, int D, int MAXT, bool EXT = false>
 __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) void k_event(EventArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.nbins, nd = D > 0 ? D : a.ndim;
@@ -133,10 +140,20 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
     double u[D > 0 ? D : VEGAS_MAX_DIM], x[D > 0 ? D : VEGAS_MAX_DIM];
     int bins[D > 0 ? D : VEGAS_MAX_DIM];
-    event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
+    if constexpr (EXT) {
+#pragma unroll
+      for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
+        if (d >= nd) break;
+        const double v = static_cast<double>(a.ext_y[i * nd + d]);
+        u[d] = fmin(fmax(v, kExtLo), kExtHi);
+      }
+    } else {
+      event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
+    }
     const double J = grid_map<D>(e_lds, n, nd, u, x, bins);
     const double f = integrand<PROC, PREC, D>(a.pc, x);
     double w = J * f;
+    if constexpr (EXT) w *= exp(-static_cast<double>(a.ext_lq[i]));
     double w2 = w * w;
     if (!isfinite(w2)) {
       ++nnf;
@@ -461,6 +478,20 @@ __global__ void k_result(DevBufs b, int n_iter) {
   b.result[3] = n_iter;
 }
 
+// training data for the learned proposal: the uniform points (binary32) and weights
+// of events [first, first+n) of iteration iter (8 dimensions)
+__global__ void k_export(const double* __restrict__ rec_w, uint64_t seed, uint32_t iter, int64_t first, int64_t n,
+                         float* y, double* w) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double u[8];
+    event_uniforms<8>(seed, iter, static_cast<uint64_t>(first + i), 8, u);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) y[i * 8 + d] = static_cast<float>(u[d]);
+    w[i] = rec_w[first + i];
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -673,6 +704,7 @@ struct vegas_state {
   uint32_t iter;      // next iteration index
   bool have_hist;     // an iteration ran since init / the last refine
   bool any_iter;
+  bool last_flow;     // the last iteration used the learned proposal
   int64_t last_n;
   int wpb, max_blocks;
   int event_lds, acc_lds;
@@ -781,6 +813,33 @@ hipError_t launch_event(const vegas_state* h, const EventArgs& a, int blocks, in
       return launch_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(a, blocks, threads, lds, s);
   }
   return hipErrorInvalidValue;
+}
+
+// learned-proposal variants (8-dimensional integrands only, 256-thread blocks)
+hipError_t launch_event_ext(const vegas_state* h, const EventArgs& a, int blocks) {
+  const int lds = h->event_lds;
+  hipStream_t s = h->stream;
+  switch (h->cfg.process) {
+    case VEGAS_GAUSS:
+      hipLaunchKernelGGL((k_event<VEGAS_GAUSS, VEGAS_FP64, 0, 256, true>), dim3(blocks), dim3(256), lds, s, a);
+      break;
+    case VEGAS_GENZ:
+      hipLaunchKernelGGL((k_event<VEGAS_GENZ, VEGAS_FP64, 0, 256, true>), dim3(blocks), dim3(256), lds, s, a);
+      break;
+    case VEGAS_WW_4L:
+      if (h->cfg.precision == VEGAS_FP32_ME)
+        hipLaunchKernelGGL((k_event<VEGAS_WW_4L, VEGAS_FP32_ME, 8, 256, true>), dim3(blocks), dim3(256), lds, s, a);
+      else
+        hipLaunchKernelGGL((k_event<VEGAS_WW_4L, VEGAS_FP64, 8, 256, true>), dim3(blocks), dim3(256), lds, s, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool ext_supported(const vegas_state* h) {
+  const int p = h->cfg.process;
+  return h->D == 8 && (p == VEGAS_GAUSS || p == VEGAS_GENZ || p == VEGAS_WW_4L);
 }
 
 template <int PROC, int PREC, int D>
@@ -964,11 +1023,25 @@ int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks
   return VEGAS_OK;
 }
 
-int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
-  if (!h) return VEGAS_EINVAL;
-  if (n_events < 2 || n_events > h->maxN) return VEGAS_EINVAL;
-  if (h->iter >= VEGAS_MAX_ITER) return VEGAS_ESTATE;
-  const int threads = pick_threads(h);
+}  // extern "C"
+
+namespace vg {
+int flow_sample_events(vegas_flow f, hipStream_t s, uint64_t seed, uint32_t iter, int64_t n, const float** y,
+                       const float** lq);
+int flow_sample_finish(vegas_flow f, hipStream_t s);
+
+void record_hip_error(const char* what, hipError_t e) {
+  g_last_hip_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+}  // namespace vg
+
+namespace {
+
+// one iteration: events (from the counter stream, or from the learned proposal's
+// points when ext_y is given), then the exact accumulation and the combination
+int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const float* ext_lq,
+                  vegas_iter_result* out) {
+  const int threads = ext_y ? 256 : pick_threads(h);
   const int nslot = h->D * h->n;
   EventArgs ea;
   ea.pc = h->pc;
@@ -979,9 +1052,14 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
   ea.iter = h->iter;
   ea.ndim = h->D;
   ea.nbins = h->n;
+  ea.ext_y = ext_y;
+  ea.ext_lq = ext_lq;
   const int ev_blocks = pick_blocks(h, n_events, threads, h->occ_event, kMaxRowsEvent);
   hipEvent_t t0 = stage_begin(h);
-  VG_HIP(launch_event(h, ea, ev_blocks, threads));
+  if (ext_y)
+    VG_HIP(launch_event_ext(h, ea, ev_blocks));
+  else
+    VG_HIP(launch_event(h, ea, ev_blocks, threads));
   stage_end(h, 0, t0);
   t0 = stage_begin(h);
   hipLaunchKernelGGL(k_binmax, dim3((nslot + kColTile - 1) / kColTile, (ev_blocks + kRowTile - 1) / kRowTile),
@@ -1007,7 +1085,8 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
   stage_end(h, 2, t0);
   const uint32_t j = h->iter;
   h->iter++;
-  h->have_hist = true;
+  h->have_hist = ext_y == nullptr;  // the grid stays frozen under the learned proposal
+  h->last_flow = ext_y != nullptr;
   h->any_iter = true;
   h->last_n = n_events;
   if (out) {
@@ -1021,6 +1100,40 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
     out->n_events = n_events;
     out->iteration = j;
   }
+  return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
+  if (!h) return VEGAS_EINVAL;
+  if (n_events < 2 || n_events > h->maxN) return VEGAS_EINVAL;
+  if (h->iter >= VEGAS_MAX_ITER) return VEGAS_ESTATE;
+  return run_iteration(h, n_events, nullptr, nullptr, out);
+}
+
+int vegas_iterate_flow(vegas_handle h, vegas_flow f, int64_t n_events, vegas_iter_result* out) {
+  if (!h || !f) return VEGAS_EINVAL;
+  if (!ext_supported(h) || n_events < 2 || n_events > h->maxN) return VEGAS_EINVAL;
+  if (h->iter >= VEGAS_MAX_ITER) return VEGAS_ESTATE;
+  const float *y = nullptr, *lq = nullptr;
+  int rc = flow_sample_events(f, h->stream, h->cfg.seed, h->iter, n_events, &y, &lq);
+  if (rc != VEGAS_OK) return rc;
+  rc = run_iteration(h, n_events, y, lq, out);
+  const int rc2 = flow_sample_finish(f, h->stream);
+  return rc != VEGAS_OK ? rc : rc2;
+}
+
+int vegas_export(vegas_handle h, int64_t first, int64_t n, float* y_dev, double* w_dev) {
+  if (!h || !y_dev || !w_dev || h->D != 8) return VEGAS_EINVAL;
+  if (!h->any_iter || h->last_flow) return VEGAS_ESTATE;
+  if (first < 0 || n < 1 || first + n > h->last_n) return VEGAS_EINVAL;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_export, dim3(blocks), dim3(256), 0, h->stream, h->b.rec_w, h->cfg.seed, h->iter - 1, first, n,
+                     y_dev, w_dev);
+  VG_HIP(hipGetLastError());
   return VEGAS_OK;
 }
 

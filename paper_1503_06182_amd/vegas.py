@@ -24,7 +24,10 @@ MAX_ITER = 4096
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
-           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad"]
+           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad",
+           "vegas_export", "vegas_iterate_flow", "vegas_flow_create", "vegas_flow_destroy",
+           "vegas_flow_get_params", "vegas_flow_set_params", "vegas_flow_density",
+           "vegas_flow_loss_grad", "vegas_flow_train_step", "vegas_flow_sample"]
 
 
 class VegasError(RuntimeError):
@@ -76,6 +79,16 @@ def load(path: str = LIB_PATH):
     L.vegas_strerror.argtypes = [C.c_int]
     L.vegas_strerror.restype = C.c_char_p
     L.vegas_grad.argtypes = [vp, vp, i32, i64, C.c_uint32, vp, vp]
+    L.vegas_export.argtypes = [vp, i64, i64, vp, vp]
+    L.vegas_iterate_flow.argtypes = [vp, vp, i64, C.POINTER(IterResult)]
+    L.vegas_flow_create.argtypes = [i32, i64, C.c_uint64, vp, C.POINTER(vp)]
+    L.vegas_flow_destroy.argtypes = [vp]
+    L.vegas_flow_get_params.argtypes = [vp, vp]
+    L.vegas_flow_set_params.argtypes = [vp, vp]
+    L.vegas_flow_density.argtypes = [vp, vp, i64, vp]
+    L.vegas_flow_loss_grad.argtypes = [vp, vp, vp, i64, vp, dp]
+    L.vegas_flow_train_step.argtypes = [vp, vp, vp, i64, i32, C.c_uint64, C.c_float, dp]
+    L.vegas_flow_sample.argtypes = [vp, vp, i64, vp, vp]
     _lib = L
     return L
 
@@ -148,6 +161,23 @@ class Integrator:
         _check(self._L.vegas_iterate(self._h, n, C.byref(r)), "vegas_iterate")
         return {"I": r.integral, "var": r.variance, "n_events": r.n_events,
                 "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration}
+
+    def iterate_flow(self, flow, n):
+        """One iteration with the learned proposal `flow` (grid frozen)."""
+        r = IterResult()
+        _check(self._L.vegas_iterate_flow(self._h, flow._f, n, C.byref(r)), "vegas_iterate_flow")
+        return {"I": r.integral, "var": r.variance, "n_events": r.n_events,
+                "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration}
+
+    def export(self, first, n):
+        """Training data of the last (VEGAS) iteration: y [n,8] float32 and w [n] float64
+        CUDA tensors."""
+        import torch
+        y = torch.empty(n, 8, dtype=torch.float32, device="cuda")
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(self._L.vegas_export(self._h, first, n, C.c_void_p(y.data_ptr()), C.c_void_p(w.data_ptr())),
+               "vegas_export")
+        return y, w
 
     def refine(self):
         _check(self._L.vegas_refine(self._h), "vegas_refine")
