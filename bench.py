@@ -23,13 +23,39 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per event of the event kernel, FP64 FLOPs (add, mul, and
-# fma counted as 2; transcendental calls as the FP64 VALU operations their
-# library expansion issues), from the rocprofv3 FP64 instruction counters of
-# one launch divided by the events of that launch.
-FLOP_PER_EVENT = {"w_plus": None, "dy_z": None, "ww_4l": None}
+# Work per event of the event kernel (the dominant kernel): FP64 and FP32 VALU
+# FLOPs (add, mul = 1, fma = 2, transcendental instructions = 1) from the
+# rocprofv3 instruction counters of its launches x 64 lanes / events, and the
+# HBM bytes one launch moves at the workload's default event count (FETCH_SIZE
+# x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
+# Measured on the kernels as built; the counter summaries are under profiles/.
+EVENT_KERNEL_WORK = {
+    ("w_plus", "fp64"): None,
+    ("ww_4l", "fp64"): None,
+    ("ww_4l", "fp32me"): None,
+}
 PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+
+def roofline(workload, precision, n_events, avg_launch_s):
+    """The event kernel against the VALU peaks: achieved = FLOPs per launch / average
+    launch time; for a mixed FP64/FP32 kernel frac is the sum of the two pipes'
+    fractions of their own peaks."""
+    work = EVENT_KERNEL_WORK.get((workload, precision))
+    roof = {"kernel": "k_event", "bound": "alu", "achieved": None, "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_ms": avg_launch_s * 1e3}
+    if work is None or avg_launch_s <= 0:
+        return roof
+    f64 = work["f64"] * n_events / avg_launch_s / 1e12
+    f32 = work["f32"] * n_events / avg_launch_s / 1e12
+    roof.update(achieved=f64 + f32, frac=f64 / PEAK_FP64_VALU_TFLOPS + f32 / PEAK_FP32_VALU_TFLOPS,
+                flop_per_event={"f64": work["f64"], "f32": work["f32"]},
+                achieved_f64=f64, achieved_f32=f32)
+    if work.get("events") == n_events:
+        roof["traffic"] = work["traffic"]
+    return roof
 
 
 def parse_args():
@@ -67,7 +93,7 @@ def combine(history):
 
 
 def history_from_state(blob, ndim, nbins):
-    head = struct.calcsize("<Q4iQ")
+    head = struct.calcsize("<Q4iQ4i")
     _magic, _proc, _nd, _nb, it, _seed = struct.unpack_from("<Q3iIQ", blob, 0)
     off = head + 8 * ndim * (nbins + 1)
     vals = struct.unpack_from(f"<{2 * it}d", blob, off)
@@ -149,40 +175,34 @@ def main():
         g.iterate(N, sync=False)
         g.refine()
     torch.cuda.synchronize()
-    g.set_timing(True)
-    g.stage_times(reset=True)
+    # throughput: K steps with nothing between the kernels
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.iterate(N, sync=False)
         g.refine()
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    st = g.stage_times()
     hist = history_from_state(g.get_state(), cfg["ndim"], cfg["nbins"])
-    timed = hist[args.warmup:]
+    timed = hist[args.warmup:args.warmup + args.steps]
+    # kernel durations: K more steps with HIP start/stop events bound to each kernel's
+    # dispatch on the library's stream (the events cost host time per launch, so this
+    # pass is kept apart from the throughput pass)
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    for _ in range(args.steps):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    st = g.stage_times()
+    g.set_timing(False)
     I, sig = combine(timed)
     eps = sig / abs(I)
     events_per_s = args.steps * N / T
     eff = 1.0 / (eps * eps * T)
 
     ms_ev, n_ev = st["event"]
-    ms_acc, n_acc = st["accumulate"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
-    avg_acc = ms_acc / max(n_acc, 1) * 1e-3
-    flop = FLOP_PER_EVENT.get(args.workload)
-    # record bytes per event: w (8) + packed bin words (4 per 4 dimensions), written
-    # by the event kernel and read back by the accumulation kernel
-    rec_bytes = 8 + 4 * ((cfg["ndim"] + 3) // 4)
-    if flop is not None:
-        achieved = flop * N / avg_ev / 1e12
-        roof = {"kernel": "k_event", "bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
-                "avg_launch_ms": avg_ev * 1e3, "flop_per_event": flop}
-    else:
-        roof = {"kernel": "k_event", "bound": "alu", "achieved": None,
-                "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "avg_launch_ms": avg_ev * 1e3}
+    roof = roofline(args.workload, args.precision, N, avg_ev)
     line = {
         "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
         "value": events_per_s,
@@ -202,8 +222,7 @@ def main():
         "time_to_1e-3_s": 1e6 / eff,
         "integral_pb": I,
         "rel_error": eps,
-        "stage_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in st.items()},
-        "accumulate_hbm_gbs": rec_bytes * N / avg_acc / 1e9,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

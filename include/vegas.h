@@ -95,6 +95,15 @@ typedef struct {
   int64_t n_nonzero;    /* events with w != 0                              */
   int64_t n_nonfinite;  /* events whose w or w^2 was not finite (dropped)  */
   uint32_t iteration;   /* index j of this iteration (keys the random stream) */
+  int32_t fold;         /* how the exact sums were folded: 0 = from the records at
+                           this iteration's own scale (first iteration, or the
+                           digits do not fit one block's LDS); 1 = inside the
+                           event kernel at the scale fixed by the previous
+                           iteration (2^16 above its max |w|); 2 = like 1, but
+                           this iteration's max |w| left [2^-40, 1) of that scale,
+                           so the sums were re-folded from the records at the
+                           iteration's own scale.  Any fold gives the same
+                           integers for every launch configuration. */
 } vegas_iter_result;
 
 typedef struct vegas_state *vegas_handle;
@@ -166,12 +175,14 @@ int vegas_set_state(vegas_handle h, const void *buf, size_t bytes);
 /* Change the launch configuration (must not change any result). */
 int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks);
 
-/* Per-stage kernel timing (off by default).  When on, every launch is
- * bracketed by HIP events recorded on the handle's stream.  vegas_stage_times
- * waits for the stream and returns, for the stages {events, accumulation,
- * finalisation, refinement}, the summed kernel milliseconds ms[4] and launch
- * counts launches[4] (host arrays, either nullable) since the last reset;
- * reset != 0 clears them. */
+/* Per-stage kernel timing (off by default).  When on, every kernel is
+ * launched with a start and a stop HIP event bound to its own dispatch
+ * (hipExtLaunchKernel), so timing adds no work between kernels.
+ * vegas_stage_times waits for the stream and returns, for the stages
+ * {events, accumulation, finalisation, refinement}, the summed kernel
+ * milliseconds ms[4] and kernel counts launches[4] (host arrays, either
+ * nullable) since the last reset; reset != 0 clears them.  One iteration
+ * launches one kernel in each of the first two stages and two in the third. */
 int vegas_set_timing(vegas_handle h, int32_t enable);
 int vegas_stage_times(vegas_handle h, double *ms, int64_t *launches, int32_t reset);
 

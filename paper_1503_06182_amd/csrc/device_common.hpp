@@ -85,7 +85,10 @@ __device__ __forceinline__ void fx_digits(double v, int E, long long& d0, long l
   }
   const int s = e2 + FX_BITS - E;  // X = m * 2^s
   uint64_t lo, hi;
-  if (s >= 64) {
+  if (s >= 128) {  // outside the frame (only at a scale the caller then discards)
+    lo = 0;
+    hi = 0;
+  } else if (s >= 64) {
     lo = 0;
     hi = m << (s - 64);
   } else if (s > 0) {

@@ -5,17 +5,19 @@
 // One iteration is four launches on the handle's stream:
 //   k_event     one event per lane (grid-stride): Philox point -> grid map ->
 //               phase space -> PDFs x |M|^2 -> weight; writes the event record
-//               (w, packed bin indices) and the exact maxima that fix the
-//               fixed-point scales (max |w|, and max w^2 per grid bin).
+//               (w, packed bin indices) and the exact max |w| that fixes the
+//               iteration's fixed-point scales.
 //   k_accum     reads the records and accumulates S1 = sum w, S2 = sum w^2 and
-//               d[dim][bin] = sum w^2 as exact integer digits (LDS atomics,
-//               then one global atomic per non-zero digit per block).
-//   k_finalize  one block: digits -> doubles, I_j, var_j, clears the digits.
+//               d[dim][bin] = sum w^2 as exact integer digits (per-lane and LDS
+//               sums, one row of per-block partials).
+//   k_accsum,   column sums of the partials (integer atomics), then one block:
+//   k_finalize  digits -> doubles, I_j, var_j.
 //   k_refine    (vegas_refine) one block, one wave per dimension: smoothing,
 //               damping, equal-importance rebinning.
 // Integer accumulation is associative, so every launch configuration gives
 // byte-identical results (the paper's independence from the thread count,
 // Sec. 2.2, made structural).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,25 +36,23 @@ namespace vg {
 
 constexpr int kWave = 64;
 
-constexpr int kMaxRowsEvent = 2048;  // cap on event-kernel blocks (rows of the per-bin max partials)
-constexpr int kMaxRowsAcc = 1024;    // cap on accumulation blocks (rows of the digit partials)
+constexpr int kMaxRowsEvent = 1 << 16;  // cap on event-kernel blocks
+constexpr int kMaxRowsAcc = 1024;       // cap on accumulation blocks (rows of the digit partials)
+constexpr int kFusedLdsMax = 48 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
 
 struct DevBufs {
   double* edges;                 // [D][n+1]
   double* rec_w;                 // [maxN]
   uint32_t* rec_bins;            // [ceil(D/4)][maxN], 4 bins of 8 bits per word
-  unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max, cleared by k_binmax)
-  unsigned long long* cnt;       // [2] n_nonzero, n_nonfinite (atomic, cleared by k_binmax)
-  unsigned long long* it_scal;   // [4] this iteration's max |w| bits, n_nonzero, n_nonfinite
-  unsigned long long* part_max;  // [rows][D*n] per-block max of w^2 per bin (bits)
-  unsigned long long* binmax;    // [D*n] max of w^2 per bin (bits)
+  unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max, cleared by k_finalize)
+  unsigned long long* cnt;       // [2] n_nonzero, n_nonfinite (atomic, cleared by k_finalize)
+  int* fxs;                      // [4] valid, E1, E2 of the fused fold (set by k_finalize for the next iteration)
   long long* part_acc;           // [rows][3*(2+D*n)] per-block digit sums: S1, S2, d[...]
   long long* acc_tot;            // [3*(2+D*n)] digit sums over all blocks
   double* hist;                  // [D*n + 2] d, S1, S2 of the last iteration
   double* history;               // [VEGAS_MAX_ITER][2] I_j, var_j
   double* iter_out;              // [8] I_j, var_j, nz, nnf, N
   double* result;                // [4] I, sigma, chi2/dof, n_iter
-  int* scale;                    // [D*n + 2] fixed-point exponents of the last iteration
 };
 
 // ---------------------------------------------------------------------------
@@ -94,6 +94,53 @@ __device__ __forceinline__ double integrand(const PhysConst& c, const double* x)
   else return f_ww<double>(c, x);
 }
 
+// ---------------------------------------------------------------------------
+// exact accumulation of one event: S1 = sum w and S2 = sum w^2 in per-lane
+// registers, d[dim][bin] = sum w^2 in LDS (3 integer digits per slot); the
+// digits are taken at scales fixed for the whole iteration, so every partition
+// of the events gives the same integer totals
+// ---------------------------------------------------------------------------
+struct LaneSums {
+  long long v[6];
+};
+
+__device__ __forceinline__ void lane_sums_zero(LaneSums& ls) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ls.v[k] = 0;
+}
+
+// S1, S2 digits of w; returns the digits of w^2 for the histogram
+__device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls, long long& h0, long long& h1,
+                                         long long& h2) {
+  long long d0, d1, d2;
+  fx_digits(w, E1, d0, d1, d2);
+  ls.v[0] += d0;
+  ls.v[1] += d1;
+  ls.v[2] += d2;
+  fx_digits(w * w, E2, h0, h1, h2);
+  ls.v[3] += h0;
+  ls.v[4] += h1;
+  ls.v[5] += h2;
+}
+
+__device__ __forceinline__ void acc_hist(long long* acc, int col, long long h0, long long h1, long long h2) {
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + col);
+  if (h0) atomicAdd(p + 0, static_cast<unsigned long long>(h0));
+  if (h1) atomicAdd(p + 1, static_cast<unsigned long long>(h1));
+  if (h2) atomicAdd(p + 2, static_cast<unsigned long long>(h2));
+}
+
+// per-lane S1, S2 -> wave butterfly -> LDS columns 0..5 (call with the whole block)
+__device__ __forceinline__ void acc_sums_to_lds(LaneSums& ls, long long* acc) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ls.v[k] = wave_sum_i64(ls.v[k]);
+  if ((threadIdx.x & 63) == 0) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(acc);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) atomicAdd(p + k, static_cast<unsigned long long>(ls.v[k]));
+  }
+}
+
 struct EventArgs {
   PhysConst pc;
   DevBufs b;
@@ -118,23 +165,34 @@ constexpr int event_min_waves() {
 }
 
 // EXT: the point is the learned proposal's y (binary32, kept inside the open unit
-// cube) instead of the event's uniforms, and the weight is divided by q(y)
-template <int PROC, int PREC, int D, int MAXT, bool EXT = false>
+// cube) instead of the event's uniforms, and the weight is divided by q(y).
+// FUSED: the event also adds its exact digits at the scales fixed by the
+// previous iteration (b.fxs) and the block writes one row of partials; the
+// finalisation re-folds from the records if the scales turn out not to fit.
+template <int PROC, int PREC, int D, int MAXT, bool EXT = false, bool FUSED = false>
 __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) void k_event(EventArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.nbins, nd = D > 0 ? D : a.ndim;
+  const int ncol = 3 * (2 + nd * n);
   double* e_lds = reinterpret_cast<double*>(smem);
-  unsigned long long* bmax = reinterpret_cast<unsigned long long*>(e_lds + nd * (n + 1));
+  long long* acc = reinterpret_cast<long long*>(e_lds + nd * (n + 1));  // FUSED: [ncol]
   for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x) e_lds[i] = a.b.edges[i];
-  for (int i = threadIdx.x; i < nd * n; i += blockDim.x) bmax[i] = 0ull;
+  if constexpr (FUSED)
+    for (int i = threadIdx.x; i < ncol; i += blockDim.x) acc[i] = 0;
   if (blockIdx.x == 0) {
-    // clear the device-wide reduction targets of this iteration (the previous
-    // iteration's values were consumed by its finalisation, earlier on the stream)
-    for (int i = threadIdx.x; i < nd * n; i += blockDim.x) a.b.binmax[i] = 0ull;
-    for (int i = threadIdx.x; i < 3 * (2 + nd * n); i += blockDim.x) a.b.acc_tot[i] = 0;
+    // clear this iteration's digit totals (the previous iteration's were consumed
+    // by its finalisation, earlier on the stream)
+    for (int i = threadIdx.x; i < ncol; i += blockDim.x) a.b.acc_tot[i] = 0;
+  }
+  int E1 = 0, E2 = 0;
+  if constexpr (FUSED) {
+    E1 = a.b.fxs[1];
+    E2 = a.b.fxs[2];
   }
   __syncthreads();
 
+  LaneSums ls;
+  lane_sums_zero(ls);
   unsigned long long wmax = 0ull, nz = 0ull, nnf = 0ull;
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
@@ -154,11 +212,9 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     const double f = integrand<PROC, PREC, D>(a.pc, x);
     double w = J * f;
     if constexpr (EXT) w *= exp(-static_cast<double>(a.ext_lq[i]));
-    double w2 = w * w;
-    if (!isfinite(w2)) {
+    if (!isfinite(w * w)) {
       ++nnf;
       w = 0.0;
-      w2 = 0.0;
     } else if (w != 0.0) {
       ++nz;
     }
@@ -174,12 +230,15 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     }
     const unsigned long long wb = static_cast<unsigned long long>(__double_as_longlong(fabs(w)));
     wmax = wb > wmax ? wb : wmax;
-    if (w2 != 0.0) {
-      const unsigned long long b2 = static_cast<unsigned long long>(__double_as_longlong(w2));
+    if constexpr (FUSED) {
+      if (w != 0.0) {
+        long long h0, h1, h2;
+        acc_sums(w, E1, E2, ls, h0, h1, h2);
 #pragma unroll
-      for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
-        if (d >= nd) break;
-        atomicMax(&bmax[d * n + bins[d]], b2);
+        for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
+          if (d >= nd) break;
+          acc_hist(acc, 3 * (2 + d * n + bins[d]), h0, h1, h2);
+        }
       }
     }
   }
@@ -195,50 +254,25 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     atomicAdd(&blk[1], static_cast<unsigned long long>(snz));
     atomicAdd(&blk[2], static_cast<unsigned long long>(snf));
   }
+  if constexpr (FUSED) acc_sums_to_lds(ls, acc);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (blk[0]) atomicMax(&a.b.maxw[0], blk[0]);
     if (blk[1]) atomicAdd(&a.b.cnt[0], blk[1]);
     if (blk[2]) atomicAdd(&a.b.cnt[1], blk[2]);
   }
-  unsigned long long* row = a.b.part_max + static_cast<int64_t>(blockIdx.x) * nd * n;
-  for (int i = threadIdx.x; i < nd * n; i += blockDim.x) row[i] = bmax[i];
+  if constexpr (FUSED) {
+    long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * ncol;
+    for (int i = threadIdx.x; i < ncol; i += blockDim.x) row[i] = acc[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
-// column reductions of the per-block partials: block (x, y) covers 32 columns and
+// column reduction of the per-block partials: block (x, y) covers 32 columns and
 // rows [32 y, 32 y + 32) with 8 row groups, then one device-wide integer atomic
 // per column (max and sum are exact and order-free)
 // ---------------------------------------------------------------------------
 constexpr int kColTile = 32, kRowTile = 32;
-
-// per-bin maxima over the event kernel's blocks; block (0,0) also latches and
-// clears this iteration's device-wide max |w| and counters
-__global__ void k_binmax(DevBufs b, int nslot, int rows) {
-  __shared__ unsigned long long red[8][kColTile];
-  const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
-  const int col = blockIdx.x * kColTile + c;
-  unsigned long long m = 0ull;
-  if (col < nslot)
-    for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8) {
-      const unsigned long long v = b.part_max[static_cast<int64_t>(r) * nslot + col];
-      m = v > m ? v : m;
-    }
-  red[rg][c] = m;
-  __syncthreads();
-  if (rg == 0 && col < nslot) {
-    for (int g = 1; g < 8; ++g) m = red[g][c] > m ? red[g][c] : m;
-    if (m) atomicMax(&b.binmax[col], m);
-  }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    b.it_scal[0] = b.maxw[0];
-    b.it_scal[1] = b.cnt[0];
-    b.it_scal[2] = b.cnt[1];
-    b.maxw[0] = 0ull;
-    b.cnt[0] = 0ull;
-    b.cnt[1] = 0ull;
-  }
-}
 
 // digit sums over the accumulation kernel's blocks
 __global__ void k_accsum(DevBufs b, int ncol, int rows) {
@@ -258,108 +292,142 @@ __global__ void k_accsum(DevBufs b, int ncol, int rows) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: exact accumulation of S1, S2 and d from the records
+// K2 (two-pass fold): exact accumulation of S1, S2 and d from the records at the
+// scales of this iteration's own max |w|.  Block (x, y) holds the histogram of
+// dimensions [y dpg, (y + 1) dpg) in LDS (and S1, S2 when y == 0) and writes its
+// part of row x of the partials.
 // ---------------------------------------------------------------------------
 struct AccArgs {
   DevBufs b;
   int64_t nev;
   int64_t stride_rec;
   int ndim, nbins;
+  int dims_per_group;
 };
 
 __global__ void k_accum(AccArgs a) {
   extern __shared__ unsigned char smem[];
-  const int n = a.nbins, nd = a.ndim, nslot = nd * n, ncol = 3 * (2 + nslot);
-  long long* acc = reinterpret_cast<long long*>(smem);  // [2 + nslot][3]: S1, S2, d
-  int* esc = reinterpret_cast<int*>(acc + ncol);         // [nslot]
-  for (int i = threadIdx.x; i < ncol; i += blockDim.x) acc[i] = 0;
-  for (int i = threadIdx.x; i < nslot; i += blockDim.x)
-    esc[i] = fx_exponent(__longlong_as_double(static_cast<long long>(a.b.binmax[i])));
-  const double wmax = __longlong_as_double(static_cast<long long>(a.b.it_scal[0]));
+  const int n = a.nbins, nd = a.ndim, ncol = 3 * (2 + nd * n);
+  const int dlo = blockIdx.y * a.dims_per_group;
+  const int dhi = min(nd, dlo + a.dims_per_group);
+  const int lcol = 3 * (2 + (dhi - dlo) * n);
+  long long* acc = reinterpret_cast<long long*>(smem);  // [lcol]: S1, S2, d of the group's dimensions
+  for (int i = threadIdx.x; i < lcol; i += blockDim.x) acc[i] = 0;
+  // one scale per quantity: 2^(94 - E) with |w| < 2^E1 and w^2 < 2^E2 for every event
+  const double wmax = __longlong_as_double(static_cast<long long>(a.b.maxw[0]));
   const int E1 = fx_exponent(wmax);
   const int E2 = fx_exponent(wmax * wmax);
   __syncthreads();
 
-  long long s1_0 = 0, s1_1 = 0, s1_2 = 0, s2_0 = 0, s2_1 = 0, s2_2 = 0;
+  LaneSums ls;
+  lane_sums_zero(ls);
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
     const double w = a.b.rec_w[i];
     if (w == 0.0) continue;
-    const double w2 = w * w;
-    long long d0, d1, d2;
-    fx_digits(w, E1, d0, d1, d2);
-    s1_0 += d0;
-    s1_1 += d1;
-    s1_2 += d2;
-    fx_digits(w2, E2, d0, d1, d2);
-    s2_0 += d0;
-    s2_1 += d1;
-    s2_2 += d2;
-    for (int g = 0; 4 * g < nd; ++g) {
-      const uint32_t word = a.b.rec_bins[g * a.stride_rec + i];
-      for (int j = 0; j < 4 && 4 * g + j < nd; ++j) {
-        const int d = 4 * g + j;
-        const int slot = d * n + static_cast<int>((word >> (8 * j)) & 0xffu);
-        fx_digits(w2, esc[slot], d0, d1, d2);
-        unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + 3 * (2 + slot));
-        if (d0) atomicAdd(p + 0, static_cast<unsigned long long>(d0));
-        if (d1) atomicAdd(p + 1, static_cast<unsigned long long>(d1));
-        if (d2) atomicAdd(p + 2, static_cast<unsigned long long>(d2));
-      }
+    long long h0, h1, h2;
+    acc_sums(w, E1, E2, ls, h0, h1, h2);
+    // the same digits of w^2 go to the event's bin in every dimension
+    for (int d = dlo; d < dhi; ++d) {
+      const uint32_t word = a.b.rec_bins[(d >> 2) * a.stride_rec + i];
+      const int bin = static_cast<int>((word >> (8 * (d & 3))) & 0xffu);
+      acc_hist(acc, 3 * (2 + (d - dlo) * n + bin), h0, h1, h2);
     }
   }
-  // S1, S2: per-lane registers -> wave butterfly -> LDS
-  s1_0 = wave_sum_i64(s1_0);
-  s1_1 = wave_sum_i64(s1_1);
-  s1_2 = wave_sum_i64(s1_2);
-  s2_0 = wave_sum_i64(s2_0);
-  s2_1 = wave_sum_i64(s2_1);
-  s2_2 = wave_sum_i64(s2_2);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    unsigned long long* p = reinterpret_cast<unsigned long long*>(acc);
-    atomicAdd(p + 0, static_cast<unsigned long long>(s1_0));
-    atomicAdd(p + 1, static_cast<unsigned long long>(s1_1));
-    atomicAdd(p + 2, static_cast<unsigned long long>(s1_2));
-    atomicAdd(p + 3, static_cast<unsigned long long>(s2_0));
-    atomicAdd(p + 4, static_cast<unsigned long long>(s2_1));
-    atomicAdd(p + 5, static_cast<unsigned long long>(s2_2));
-  }
+  acc_sums_to_lds(ls, acc);
   __syncthreads();
   long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * ncol;
-  for (int i = threadIdx.x; i < ncol; i += blockDim.x) row[i] = acc[i];
+  if (blockIdx.y == 0)
+    for (int i = threadIdx.x; i < 6; i += blockDim.x) row[i] = acc[i];
+  for (int i = threadIdx.x; i < lcol - 6; i += blockDim.x) row[3 * (2 + dlo * n) + i] = acc[6 + i];
 }
 
 // ---------------------------------------------------------------------------
-// K3: digit totals -> doubles (d, S1, S2), then I_j and var_j
+// K3: digit totals -> doubles (d, S1, S2), then I_j and var_j.  One block.
+// After a fused fold, the scales of the previous iteration are kept only while
+// this iteration's max |w| lies in [2^(E1 - kFxLow), 2^E1); otherwise the block
+// re-folds every record at this iteration's own scales (same totals as the
+// two-pass fold).  It then fixes the next iteration's scales and clears the
+// iteration's max |w| and counters.
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(DevBufs b, int nslot, int64_t nev, uint32_t iter) {
+constexpr int kFxHead = 16;  // next scale: 2^16 above this iteration's max |w|
+constexpr int kFxLow = 40;   // the fused scale is kept down to 2^-40 of itself (>= 54 bits per event)
+
+struct FinArgs {
+  DevBufs b;
+  int64_t nev, stride_rec;
+  int ndim, nbins;
+  uint32_t iter;
+  int fused;
+};
+
+__global__ void k_finalize(FinArgs f) {
+  extern __shared__ unsigned char smem[];  // fused: [3 (2 + D n)] for a re-fold
   __shared__ double s12[2];
-  const double wmax = __longlong_as_double(static_cast<long long>(b.it_scal[0]));
+  const DevBufs& b = f.b;
+  const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol = 3 * (2 + nslot);
+  const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
+  const unsigned long long nz = b.cnt[0], nnf = b.cnt[1];
+  const int Ec1 = fx_exponent(wmax), Ec2 = fx_exponent(wmax * wmax);
+  int E1 = Ec1, E2 = Ec2, fold = 0;
+  if (f.fused) {
+    const int Ef = b.fxs[1];
+    if (Ec1 > Ef || Ec1 < Ef - kFxLow) {
+      fold = 2;
+    } else {
+      fold = 1;
+      E1 = Ef;
+      E2 = b.fxs[2];
+    }
+  }
+  const long long* tot = b.acc_tot;
+  if (fold == 2) {  // block-uniform
+    long long* acc = reinterpret_cast<long long*>(smem);
+    for (int i = threadIdx.x; i < ncol; i += blockDim.x) acc[i] = 0;
+    __syncthreads();
+    LaneSums ls;
+    lane_sums_zero(ls);
+    for (int64_t i = threadIdx.x; i < f.nev; i += blockDim.x) {
+      const double w = b.rec_w[i];
+      if (w == 0.0) continue;
+      long long h0, h1, h2;
+      acc_sums(w, E1, E2, ls, h0, h1, h2);
+      for (int d = 0; d < nd; ++d) {
+        const uint32_t word = b.rec_bins[(d >> 2) * f.stride_rec + i];
+        acc_hist(acc, 3 * (2 + d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), h0, h1, h2);
+      }
+    }
+    acc_sums_to_lds(ls, acc);
+    __syncthreads();
+    tot = acc;
+  }
   for (int slot = threadIdx.x; slot < nslot + 2; slot += blockDim.x) {
-    int E;
-    if (slot == 0) E = fx_exponent(wmax);
-    else if (slot == 1) E = fx_exponent(wmax * wmax);
-    else E = fx_exponent(__longlong_as_double(static_cast<long long>(b.binmax[slot - 2])));
-    const long long* t = b.acc_tot + 3 * slot;
-    const double v = fx_value(t[0], t[1], t[2], E);
+    const long long* t = tot + 3 * slot;
+    const double v = fx_value(t[0], t[1], t[2], slot == 0 ? E1 : E2);
     const int h = slot < 2 ? nslot + slot : slot - 2;
     b.hist[h] = v;
-    b.scale[h] = E;
     if (slot < 2) s12[slot] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const double S1 = s12[0], S2 = s12[1];
-    const double N = static_cast<double>(nev);
+    const double N = static_cast<double>(f.nev);
     const double I = S1 / N;
     const double var = fma(-I, I, S2 / N) / (N - 1.0);
-    b.history[2 * iter] = I;
-    b.history[2 * iter + 1] = var;
+    b.history[2 * f.iter] = I;
+    b.history[2 * f.iter + 1] = var;
     b.iter_out[0] = I;
     b.iter_out[1] = var;
-    b.iter_out[2] = static_cast<double>(b.it_scal[1]);
-    b.iter_out[3] = static_cast<double>(b.it_scal[2]);
+    b.iter_out[2] = static_cast<double>(nz);
+    b.iter_out[3] = static_cast<double>(nnf);
     b.iter_out[4] = N;
+    b.iter_out[5] = static_cast<double>(fold);
+    b.fxs[0] = 1;
+    b.fxs[1] = Ec1 + kFxHead;
+    b.fxs[2] = 2 * (Ec1 + kFxHead);
+    b.maxw[0] = 0ull;
+    b.cnt[0] = 0ull;
+    b.cnt[1] = 0ull;
   }
 }
 
@@ -517,8 +585,7 @@ namespace {
 thread_local std::string g_last_hip_error;
 
 struct Layout {
-  size_t edges, rec_w, rec_bins, maxw, cnt, it_scal, part_max, binmax, part_acc, acc_tot, hist, history,
-      iter_out, result, scale, total;
+  size_t edges, rec_w, rec_bins, maxw, cnt, fxs, part_acc, acc_tot, hist, history, iter_out, result, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -537,16 +604,13 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.rec_bins = take(sizeof(uint32_t) * words * maxN);
   L.maxw = take(sizeof(unsigned long long) * 2);
   L.cnt = take(sizeof(unsigned long long) * 2);
-  L.it_scal = take(sizeof(unsigned long long) * 4);
-  L.part_max = take(sizeof(unsigned long long) * kMaxRowsEvent * D * n);
-  L.binmax = take(sizeof(unsigned long long) * D * n);
+  L.fxs = take(sizeof(int) * 4);
   L.part_acc = take(sizeof(long long) * kMaxRowsAcc * 3 * (2 + D * n));
   L.acc_tot = take(sizeof(long long) * 3 * (2 + D * n));
   L.hist = take(sizeof(double) * (D * n + 2));
   L.history = take(sizeof(double) * 2 * VEGAS_MAX_ITER);
   L.iter_out = take(sizeof(double) * 8);
   L.result = take(sizeof(double) * 4);
-  L.scale = take(sizeof(int) * (D * n + 2));
   L.total = off;
   return L;
 }
@@ -707,8 +771,11 @@ struct vegas_state {
   bool last_flow;     // the last iteration used the learned proposal
   int64_t last_n;
   int wpb, max_blocks;
-  int event_lds, acc_lds;
-  int ncu, occ_event, occ_acc;  // CUs, and resident 256-thread blocks per CU of each kernel
+  int event_lds, acc_lds, fused_lds, fin_lds;
+  int acc_dpg, acc_groups;      // histogram dimensions per k_accum block, and blocks along y
+  bool fused_ok;                // the fused fold fits in LDS for this configuration
+  bool scale_valid;             // the device holds scales from a previous iteration (b.fxs)
+  int ncu, occ_event, occ_event_fused, occ_acc;  // CUs, and resident 256-thread blocks per CU
   // optional per-stage kernel timing with HIP events on the handle's stream
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -759,21 +826,34 @@ hipEvent_t pool_event(vegas_state* h) {
   return e;
 }
 
-// record a start event before a stage's launch (no-op unless timing is on)
-hipEvent_t stage_begin(vegas_state* h) {
-  if (!h->timing) return nullptr;
-  hipEvent_t e = pool_event(h);
-  if (e) (void)hipEventRecord(e, h->stream);
-  return e;
-}
-
-void stage_end(vegas_state* h, int stage, hipEvent_t start) {
-  if (!h->timing || !start) return;
-  hipEvent_t e = pool_event(h);
-  if (!e) return;
-  (void)hipEventRecord(e, h->stream);
-  h->ev_pending.push_back({stage, {start, e}});
-}
+// launch on the handle's stream; with timing on, the start and stop events are
+// bound to the kernel's own dispatch (no marker packets between kernels)
+struct TimedLaunch {
+  vegas_state* h;
+  int stage;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimedLaunch(vegas_state* hh, int st) : h(hh), stage(st) {
+    if (!h->timing) return;
+    e0 = pool_event(h);
+    e1 = e0 ? pool_event(h) : nullptr;
+    if (e0 && !e1) {
+      h->ev_pool.push_back(e0);
+      e0 = nullptr;
+    }
+  }
+  hipError_t done() {
+    const hipError_t err = hipGetLastError();
+    if (e0 && e1) {
+      if (err == hipSuccess) {
+        h->ev_pending.push_back({stage, {e0, e1}});
+      } else {
+        h->ev_pool.push_back(e0);
+        h->ev_pool.push_back(e1);
+      }
+    }
+    return err;
+  }
+};
 
 // fold finished event pairs into the per-stage totals (the stream must be idle)
 void stage_collect(vegas_state* h) {
@@ -789,52 +869,51 @@ void stage_collect(vegas_state* h) {
   h->ev_pending.clear();
 }
 
-template <int PROC, int PREC, int D>
-hipError_t launch_event_t(const EventArgs& a, int blocks, int threads, int lds, hipStream_t s) {
-  if (threads <= 256)
-    hipLaunchKernelGGL((k_event<PROC, PREC, D, 256>), dim3(blocks), dim3(threads), lds, s, a);
+template <int PROC, int PREC, int D, bool EXT, bool FUSED>
+hipError_t launch_event_tf(vegas_state* h, const EventArgs& a, int blocks, int threads) {
+  TimedLaunch t(h, 0);
+  const int lds = FUSED ? h->fused_lds : h->event_lds;
+  if (EXT || threads <= 256)
+    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 256, EXT, FUSED>), dim3(blocks), dim3(EXT ? 256 : threads), lds,
+                          h->stream, t.e0, t.e1, 0, a);
   else
-    hipLaunchKernelGGL((k_event<PROC, PREC, D, 1024>), dim3(blocks), dim3(threads), lds, s, a);
-  return hipGetLastError();
+    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 1024, false, FUSED>), dim3(blocks), dim3(threads), lds, h->stream,
+                          t.e0, t.e1, 0, a);
+  return t.done();
 }
 
-hipError_t launch_event(const vegas_state* h, const EventArgs& a, int blocks, int threads) {
-  const int lds = h->event_lds;
-  hipStream_t s = h->stream;
+template <int PROC, int PREC, int D, bool EXT = false>
+hipError_t launch_event_t(vegas_state* h, const EventArgs& a, int blocks, int threads, bool fused) {
+  return fused ? launch_event_tf<PROC, PREC, D, EXT, true>(h, a, blocks, threads)
+               : launch_event_tf<PROC, PREC, D, EXT, false>(h, a, blocks, threads);
+}
+
+hipError_t launch_event(vegas_state* h, const EventArgs& a, int blocks, int threads, bool fused) {
   switch (h->cfg.process) {
-    case VEGAS_GAUSS: return launch_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(a, blocks, threads, lds, s);
-    case VEGAS_GENZ: return launch_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(a, blocks, threads, lds, s);
-    case VEGAS_EEMUMU: return launch_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(a, blocks, threads, lds, s);
-    case VEGAS_DY_Z: return launch_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(a, blocks, threads, lds, s);
-    case VEGAS_W_PLUS: return launch_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(a, blocks, threads, lds, s);
+    case VEGAS_GAUSS: return launch_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(h, a, blocks, threads, fused);
+    case VEGAS_GENZ: return launch_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(h, a, blocks, threads, fused);
+    case VEGAS_EEMUMU: return launch_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(h, a, blocks, threads, fused);
+    case VEGAS_DY_Z: return launch_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(h, a, blocks, threads, fused);
+    case VEGAS_W_PLUS: return launch_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(h, a, blocks, threads, fused);
     case VEGAS_WW_4L:
       if (h->cfg.precision == VEGAS_FP32_ME)
-        return launch_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(a, blocks, threads, lds, s);
-      return launch_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(a, blocks, threads, lds, s);
+        return launch_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(h, a, blocks, threads, fused);
+      return launch_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(h, a, blocks, threads, fused);
   }
   return hipErrorInvalidValue;
 }
 
 // learned-proposal variants (8-dimensional integrands only, 256-thread blocks)
-hipError_t launch_event_ext(const vegas_state* h, const EventArgs& a, int blocks) {
-  const int lds = h->event_lds;
-  hipStream_t s = h->stream;
+hipError_t launch_event_ext(vegas_state* h, const EventArgs& a, int blocks, bool fused) {
   switch (h->cfg.process) {
-    case VEGAS_GAUSS:
-      hipLaunchKernelGGL((k_event<VEGAS_GAUSS, VEGAS_FP64, 0, 256, true>), dim3(blocks), dim3(256), lds, s, a);
-      break;
-    case VEGAS_GENZ:
-      hipLaunchKernelGGL((k_event<VEGAS_GENZ, VEGAS_FP64, 0, 256, true>), dim3(blocks), dim3(256), lds, s, a);
-      break;
+    case VEGAS_GAUSS: return launch_event_t<VEGAS_GAUSS, VEGAS_FP64, 0, true>(h, a, blocks, 256, fused);
+    case VEGAS_GENZ: return launch_event_t<VEGAS_GENZ, VEGAS_FP64, 0, true>(h, a, blocks, 256, fused);
     case VEGAS_WW_4L:
       if (h->cfg.precision == VEGAS_FP32_ME)
-        hipLaunchKernelGGL((k_event<VEGAS_WW_4L, VEGAS_FP32_ME, 8, 256, true>), dim3(blocks), dim3(256), lds, s, a);
-      else
-        hipLaunchKernelGGL((k_event<VEGAS_WW_4L, VEGAS_FP64, 8, 256, true>), dim3(blocks), dim3(256), lds, s, a);
-      break;
+        return launch_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8, true>(h, a, blocks, 256, fused);
+      return launch_event_t<VEGAS_WW_4L, VEGAS_FP64, 8, true>(h, a, blocks, 256, fused);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 bool ext_supported(const vegas_state* h) {
@@ -843,25 +922,26 @@ bool ext_supported(const vegas_state* h) {
 }
 
 template <int PROC, int PREC, int D>
-int occupancy_event_t(int lds) {
+int occupancy_event_t(int lds, bool fused) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256>),
-                                                    256, lds) != hipSuccess)
+  const void* k = fused ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, true>)
+                        : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-int occupancy_event(const vegas_state* h) {
-  const int lds = h->event_lds;
+int occupancy_event(const vegas_state* h, bool fused) {
+  const int lds = fused ? h->fused_lds : h->event_lds;
   switch (h->cfg.process) {
-    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds);
-    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds);
-    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds);
-    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds);
-    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds);
+    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds, fused);
+    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds, fused);
+    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds, fused);
+    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds, fused);
+    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds, fused);
     case VEGAS_WW_4L:
-      if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds);
-      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds);
+      if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds, fused);
+      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds, fused);
   }
   return 1;
 }
@@ -912,7 +992,7 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   h->L = L;
   h->wpb = cfg->waves_per_block;
   h->max_blocks = cfg->max_blocks;
-  h->event_lds = static_cast<int>(sizeof(double) * D * (n + 1) + sizeof(unsigned long long) * D * n);
+  h->event_lds = static_cast<int>(sizeof(double) * D * (n + 1));
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return VEGAS_EHIP;
@@ -933,23 +1013,34 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   h->b.rec_bins = reinterpret_cast<uint32_t*>(B + L.rec_bins);
   h->b.maxw = reinterpret_cast<unsigned long long*>(B + L.maxw);
   h->b.cnt = reinterpret_cast<unsigned long long*>(B + L.cnt);
-  h->b.it_scal = reinterpret_cast<unsigned long long*>(B + L.it_scal);
-  h->b.part_max = reinterpret_cast<unsigned long long*>(B + L.part_max);
-  h->b.binmax = reinterpret_cast<unsigned long long*>(B + L.binmax);
+  h->b.fxs = reinterpret_cast<int*>(B + L.fxs);
   h->b.part_acc = reinterpret_cast<long long*>(B + L.part_acc);
   h->b.acc_tot = reinterpret_cast<long long*>(B + L.acc_tot);
   h->b.hist = reinterpret_cast<double*>(B + L.hist);
   h->b.history = reinterpret_cast<double*>(B + L.history);
   h->b.iter_out = reinterpret_cast<double*>(B + L.iter_out);
   h->b.result = reinterpret_cast<double*>(B + L.result);
-  h->b.scale = reinterpret_cast<int*>(B + L.scale);
   h->pc = make_consts(&h->cfg, h->params);
-  h->acc_lds = static_cast<int>(sizeof(long long) * 3 * (2 + D * n) + sizeof(int) * D * n);
   {
     hipDeviceProp_t prop;
-    h->ncu = hipGetDeviceProperties(&prop, h->device) == hipSuccess ? prop.multiProcessorCount : 256;
+    const bool have_prop = hipGetDeviceProperties(&prop, h->device) == hipSuccess;
+    h->ncu = have_prop ? prop.multiProcessorCount : 256;
     if (h->ncu < 1) h->ncu = 1;
-    h->occ_event = occupancy_event(h);
+    // histogram dimensions per k_accum block: as many as fit in the block's LDS
+    size_t smem = have_prop ? prop.sharedMemPerBlock : 65536;
+    if (smem > 65536) smem = 65536;
+    const size_t per_dim = sizeof(long long) * 3 * n;
+    int dpg = static_cast<int>((smem - sizeof(long long) * 6) / per_dim);
+    dpg = dpg < 1 ? 1 : (dpg > D ? D : dpg);
+    h->acc_dpg = dpg;
+    h->acc_groups = (D + dpg - 1) / dpg;
+    h->acc_lds = static_cast<int>(sizeof(long long) * (6 + 3 * dpg * n));
+    const int full = static_cast<int>(sizeof(long long) * 3 * (2 + D * n));
+    h->fused_lds = h->event_lds + full;
+    h->fused_ok = h->fused_lds <= kFusedLdsMax;
+    h->fin_lds = h->fused_ok ? full : 0;
+    h->occ_event = occupancy_event(h, false);
+    h->occ_event_fused = h->fused_ok ? occupancy_event(h, true) : 1;
     int nb = 0;
     h->occ_acc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_accum), 256,
                                                               h->acc_lds) == hipSuccess && nb > 0
@@ -959,7 +1050,7 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   // zero the device-wide atomics and every buffer after the partials with a fill kernel
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, h->stream,
                      reinterpret_cast<unsigned long long*>(B + L.maxw),
-                     static_cast<int64_t>((L.part_max - L.maxw) / 8));
+                     static_cast<int64_t>((L.part_acc - L.maxw) / 8));
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, h->stream,
                      reinterpret_cast<unsigned long long*>(B + L.hist),
                      static_cast<int64_t>((L.total - L.hist) / 8));
@@ -1054,35 +1145,53 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   ea.nbins = h->n;
   ea.ext_y = ext_y;
   ea.ext_lq = ext_lq;
-  const int ev_blocks = pick_blocks(h, n_events, threads, h->occ_event, kMaxRowsEvent);
-  hipEvent_t t0 = stage_begin(h);
+  // fused fold (digits added by the event kernel at the previous iteration's scales)
+  // whenever such scales exist and the digits fit in LDS; the choice depends on
+  // the history and the configuration only, never on the launch shape
+  const bool fused = h->fused_ok && h->scale_valid;
+  const int ev_blocks = fused ? pick_blocks(h, n_events, threads, h->occ_event_fused, kMaxRowsAcc)
+                              : pick_blocks(h, n_events, threads, h->occ_event, kMaxRowsEvent);
   if (ext_y)
-    VG_HIP(launch_event_ext(h, ea, ev_blocks));
+    VG_HIP(launch_event_ext(h, ea, ev_blocks, fused));
   else
-    VG_HIP(launch_event(h, ea, ev_blocks, threads));
-  stage_end(h, 0, t0);
-  t0 = stage_begin(h);
-  hipLaunchKernelGGL(k_binmax, dim3((nslot + kColTile - 1) / kColTile, (ev_blocks + kRowTile - 1) / kRowTile),
-                     dim3(256), 0, h->stream, h->b, nslot, ev_blocks);
-  VG_HIP(hipGetLastError());
-  AccArgs aa;
-  aa.b = h->b;
-  aa.nev = n_events;
-  aa.stride_rec = h->maxN;
-  aa.ndim = h->D;
-  aa.nbins = h->n;
-  const int acc_blocks = pick_blocks(h, n_events, threads, h->occ_acc, kMaxRowsAcc);
-  hipLaunchKernelGGL(k_accum, dim3(acc_blocks), dim3(threads), h->acc_lds, h->stream, aa);
-  VG_HIP(hipGetLastError());
-  stage_end(h, 1, t0);
-  t0 = stage_begin(h);
+    VG_HIP(launch_event(h, ea, ev_blocks, threads, fused));
+  int rows = ev_blocks;
+  if (!fused) {
+    AccArgs aa;
+    aa.b = h->b;
+    aa.nev = n_events;
+    aa.stride_rec = h->maxN;
+    aa.ndim = h->D;
+    aa.nbins = h->n;
+    aa.dims_per_group = h->acc_dpg;
+    rows = pick_blocks(h, n_events, threads, h->occ_acc, kMaxRowsAcc);
+    TimedLaunch t(h, 1);
+    hipExtLaunchKernelGGL(k_accum, dim3(rows, h->acc_groups), dim3(threads), h->acc_lds, h->stream, t.e0, t.e1, 0,
+                          aa);
+    VG_HIP(t.done());
+  }
   const int ncol = 3 * (2 + nslot);
-  hipLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (acc_blocks + kRowTile - 1) / kRowTile),
-                     dim3(256), 0, h->stream, h->b, ncol, acc_blocks);
-  VG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->b, nslot, n_events, h->iter);
-  VG_HIP(hipGetLastError());
-  stage_end(h, 2, t0);
+  {
+    TimedLaunch t(h, 2);
+    hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
+                          dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
+    VG_HIP(t.done());
+  }
+  {
+    FinArgs fa;
+    fa.b = h->b;
+    fa.nev = n_events;
+    fa.stride_rec = h->maxN;
+    fa.ndim = h->D;
+    fa.nbins = h->n;
+    fa.iter = h->iter;
+    fa.fused = fused ? 1 : 0;
+    TimedLaunch t(h, 2);
+    hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused ? 1024 : 256), fused ? h->fin_lds : 0, h->stream, t.e0,
+                          t.e1, 0, fa);
+    VG_HIP(t.done());
+  }
+  h->scale_valid = true;
   const uint32_t j = h->iter;
   h->iter++;
   h->have_hist = ext_y == nullptr;  // the grid stays frozen under the learned proposal
@@ -1090,7 +1199,7 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   h->any_iter = true;
   h->last_n = n_events;
   if (out) {
-    double o[5];
+    double o[6];
     VG_HIP(hipMemcpyAsync(o, h->b.iter_out, sizeof(o), hipMemcpyDeviceToHost, h->stream));
     VG_HIP(hipStreamSynchronize(h->stream));
     out->integral = o[0];
@@ -1099,6 +1208,7 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     out->n_nonfinite = static_cast<int64_t>(o[3]);
     out->n_events = n_events;
     out->iteration = j;
+    out->fold = static_cast<int32_t>(o[5]);
   }
   return VEGAS_OK;
 }
@@ -1140,10 +1250,9 @@ int vegas_export(vegas_handle h, int64_t first, int64_t n, float* y_dev, double*
 int vegas_refine(vegas_handle h) {
   if (!h) return VEGAS_EINVAL;
   if (!h->have_hist) return VEGAS_ESTATE;
-  hipEvent_t t0 = stage_begin(h);
-  hipLaunchKernelGGL(k_refine, dim3(h->D), dim3(kWave), 0, h->stream, h->b, h->n, h->cfg.alpha);
-  VG_HIP(hipGetLastError());
-  stage_end(h, 3, t0);
+  TimedLaunch t(h, 3);
+  hipExtLaunchKernelGGL(k_refine, dim3(h->D), dim3(kWave), 0, h->stream, t.e0, t.e1, 0, h->b, h->n, h->cfg.alpha);
+  VG_HIP(t.done());
   h->have_hist = false;
   return VEGAS_OK;
 }
@@ -1295,8 +1404,9 @@ struct CkptHeader {
   int32_t process, ndim, nbins;
   uint32_t iter;
   uint64_t seed;
+  int32_t fxs[4];  // fused-fold scales for the next iteration (valid, E1, E2, unused)
 };
-constexpr uint64_t kMagic = 0x5645474153434b31ull;  // "VEGASCK1"
+constexpr uint64_t kMagic = 0x5645474153434b32ull;  // "VEGASCK2"
 }  // namespace
 
 int vegas_get_state(vegas_handle h, void* buf, size_t* bytes) {
@@ -1308,13 +1418,14 @@ int vegas_get_state(vegas_handle h, void* buf, size_t* bytes) {
     return VEGAS_OK;
   }
   if (*bytes < need) return VEGAS_EINVAL;
-  CkptHeader hd{kMagic, h->cfg.process, h->D, h->n, h->iter, h->cfg.seed};
+  CkptHeader hd{kMagic, h->cfg.process, h->D, h->n, h->iter, h->cfg.seed, {0, 0, 0, 0}};
   char* p = static_cast<char*>(buf);
-  std::memcpy(p, &hd, sizeof(hd));
   double* e = reinterpret_cast<double*>(p + sizeof(hd));
+  VG_HIP(hipMemcpyAsync(hd.fxs, h->b.fxs, sizeof(hd.fxs), hipMemcpyDeviceToHost, h->stream));
   VG_HIP(hipMemcpyAsync(e, h->b.edges, sizeof(double) * ne, hipMemcpyDeviceToHost, h->stream));
   if (nh) VG_HIP(hipMemcpyAsync(e + ne, h->b.history, sizeof(double) * nh, hipMemcpyDeviceToHost, h->stream));
   VG_HIP(hipStreamSynchronize(h->stream));
+  std::memcpy(p, &hd, sizeof(hd));
   *bytes = need;
   return VEGAS_OK;
 }
@@ -1329,9 +1440,12 @@ int vegas_set_state(vegas_handle h, const void* buf, size_t bytes) {
   const size_t ne = static_cast<size_t>(h->D) * (h->n + 1), nh = 2 * static_cast<size_t>(hd.iter);
   if (bytes != sizeof(CkptHeader) + sizeof(double) * (ne + nh)) return VEGAS_EINVAL;
   const double* e = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(hd));
+  if (hd.fxs[0] != 0 && hd.fxs[0] != 1) return VEGAS_EINVAL;
   VG_HIP(hipMemcpyAsync(h->b.edges, e, sizeof(double) * ne, hipMemcpyHostToDevice, h->stream));
   if (nh) VG_HIP(hipMemcpyAsync(h->b.history, e + ne, sizeof(double) * nh, hipMemcpyHostToDevice, h->stream));
+  VG_HIP(hipMemcpyAsync(h->b.fxs, hd.fxs, sizeof(hd.fxs), hipMemcpyHostToDevice, h->stream));
   VG_HIP(hipStreamSynchronize(h->stream));
+  h->scale_valid = hd.fxs[0] == 1;
   h->iter = hd.iter;
   h->any_iter = hd.iter > 0;
   h->have_hist = false;

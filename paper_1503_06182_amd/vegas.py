@@ -46,7 +46,8 @@ class Config(C.Structure):
 
 class IterResult(C.Structure):
     _fields_ = [("integral", C.c_double), ("variance", C.c_double), ("n_events", C.c_int64),
-                ("n_nonzero", C.c_int64), ("n_nonfinite", C.c_int64), ("iteration", C.c_uint32)]
+                ("n_nonzero", C.c_int64), ("n_nonfinite", C.c_int64), ("iteration", C.c_uint32),
+                ("fold", C.c_int32)]
 
 
 _lib = None
@@ -160,14 +161,16 @@ class Integrator:
         r = IterResult()
         _check(self._L.vegas_iterate(self._h, n, C.byref(r)), "vegas_iterate")
         return {"I": r.integral, "var": r.variance, "n_events": r.n_events,
-                "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration}
+                "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration,
+                "fold": r.fold}
 
     def iterate_flow(self, flow, n):
         """One iteration with the learned proposal `flow` (grid frozen)."""
         r = IterResult()
         _check(self._L.vegas_iterate_flow(self._h, flow._f, n, C.byref(r)), "vegas_iterate_flow")
         return {"I": r.integral, "var": r.variance, "n_events": r.n_events,
-                "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration}
+                "n_nonzero": r.n_nonzero, "n_nonfinite": r.n_nonfinite, "iteration": r.iteration,
+                "fold": r.fold}
 
     def export(self, first, n):
         """Training data of the last (VEGAS) iteration: y [n,8] float32 and w [n] float64

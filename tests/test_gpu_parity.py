@@ -7,6 +7,8 @@ decisions identical (flips counted, none allowed); byte-identical results for
 every launch configuration (the GPU form of the paper's thread-count
 independence, Sec. 2.2).
 """
+import struct
+
 import numpy as np
 import pytest
 
@@ -164,6 +166,50 @@ def test_checkpoint_resume_is_bit_identical(P):
     rb = b.result()
     assert ra == rb
     assert np.array_equal(a.get_grid(), b.get_grid())
+
+
+def _with_scale(blob, valid, e1):
+    """The checkpoint with its stored fused-fold scale replaced (header: magic,
+    process, ndim, nbins, iteration, seed, then valid, E1, E2, unused)."""
+    off = struct.calcsize("<Q3iIQ")
+    return blob[:off] + struct.pack("<4i", valid, e1, 2 * e1, 0) + blob[off + 16:]
+
+
+def test_fold_modes(P):
+    """The first iteration folds the sums from the records at its own scale (fold 0);
+    later ones fold inside the event kernel at the scale the previous iteration fixed
+    (fold 1).  A stored scale that this iteration's max |w| overflows, or one 2^100
+    above it, forces the re-fold (fold 2): the same integers as a two-pass fold of the
+    iteration, so bit-identical estimates and histogram.  The fused fold differs from
+    them only in the truncation of each event's digits (below 2^-54 of it)."""
+    cfg = W.config("w_plus")
+    n = 50_000
+    mk = lambda: P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+    a = mk()
+    assert a.iterate(n)["fold"] == 0
+    a.refine()
+    blob = a.get_state()
+    valid, e1 = struct.unpack_from("<2i", blob, struct.calcsize("<Q3iIQ"))
+    assert valid == 1
+    r1 = a.iterate(n)
+    d1, s1 = a.get_hist()
+    assert r1["fold"] == 1
+    runs = {}
+    for tag, v, e in (("two-pass", 0, 0), ("overflow", 1, e1 - 30), ("far above", 1, e1 + 100)):
+        b = mk()
+        b.set_state(_with_scale(blob, v, e))
+        r = b.iterate(n)
+        assert r["fold"] == (0 if v == 0 else 2), tag
+        assert r["iteration"] == 1
+        runs[tag] = (r, b.get_hist())
+    r0, (d0, s0) = runs["two-pass"]
+    for tag in ("overflow", "far above"):
+        r, (d, s) = runs[tag]
+        assert r["I"] == r0["I"] and r["var"] == r0["var"], tag
+        assert np.array_equal(d, d0) and np.array_equal(s, s0), tag
+    assert abs(r1["I"] / r0["I"] - 1) < 1e-15 and abs(r1["var"] / r0["var"] - 1) < 1e-14
+    m = d0 > 0
+    assert np.max(np.abs(d1[m] / d0[m] - 1)) < 1e-13
 
 
 def test_histogram_sums_and_zero_weight_edge_cases(P):
