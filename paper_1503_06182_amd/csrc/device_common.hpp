@@ -72,39 +72,22 @@ __host__ __device__ __forceinline__ int fx_exponent(double vmax) {
   return ex - 1022;           // v < 2^(ex-1023+1)
 }
 
+// digits of v at scale 2^(94 - E) (|v| < 2^E): X = |v| 2^(94-E) is exact (a change
+// of exponent), then X = d2 2^64 + d1 2^32 + d0 with every step exact in binary64
+// (trunc, and fma of a product that is exactly representable); the magnitude's
+// digits carry the sign of v.  Equal, digit for digit, to shifting the integer
+// mantissa (and truncating the bits below 2^0).  Values at or above 2^E only occur
+// at a scale the caller discards; X is clamped so the conversions stay defined.
 __device__ __forceinline__ void fx_digits(double v, int E, long long& d0, long long& d1, long long& d2) {
-  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
-  const int ex = static_cast<int>((b >> 52) & 0x7ff);
-  uint64_t m = b & 0x000FFFFFFFFFFFFFull;
-  int e2;
-  if (ex == 0) {
-    e2 = -1074;
-  } else {
-    m |= 0x0010000000000000ull;
-    e2 = ex - 1075;
-  }
-  const int s = e2 + FX_BITS - E;  // X = m * 2^s
-  uint64_t lo, hi;
-  if (s >= 128) {  // outside the frame (only at a scale the caller then discards)
-    lo = 0;
-    hi = 0;
-  } else if (s >= 64) {
-    lo = 0;
-    hi = m << (s - 64);
-  } else if (s > 0) {
-    lo = m << s;
-    hi = m >> (64 - s);
-  } else if (s > -64) {
-    lo = m >> (-s);
-    hi = 0;
-  } else {
-    lo = 0;
-    hi = 0;
-  }
-  long long a0 = static_cast<long long>(lo & 0xFFFFFFFFull);
-  long long a1 = static_cast<long long>(lo >> 32);
-  long long a2 = static_cast<long long>(hi);
-  if (b >> 63) {
+  const double X = fmin(ldexp(fabs(v), FX_BITS - E), 0x1p95);
+  const double h = trunc(X * 0x1p-64);
+  const double r = __fma_rn(-h, 0x1p64, X);
+  const double m = trunc(r * 0x1p-32);
+  const double l = trunc(__fma_rn(-m, 0x1p32, r));
+  long long a2 = static_cast<long long>(static_cast<uint32_t>(h));
+  long long a1 = static_cast<long long>(static_cast<uint32_t>(m));
+  long long a0 = static_cast<long long>(static_cast<uint32_t>(l));
+  if (signbit(v)) {
     a0 = -a0;
     a1 = -a1;
     a2 = -a2;

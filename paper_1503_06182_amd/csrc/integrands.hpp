@@ -20,7 +20,7 @@ struct PhysConst {
   int process, ndim, nbins, family;
   double conv;                // (hbar c)^2 in pb GeV^2
   // Breit-Wigner mapping of the first resonance: m^2 = M2 + MG tan(rho_lo + x rho_rng)
-  double M2, MG, rho_lo, rho_rng, m2lo, tlo;
+  double M2, MG, invMG, rho_lo, rho_rng, m2lo, tlo;
   double invS;                // 1 / S (hadronic)
   double pdfA, pdfa, pdfb;
   // Drell-Yan: Q_q Q_l and chiral Z couplings g[q][h] * g_l[h'] products
@@ -47,21 +47,18 @@ struct PhysConst {
 // ---------------------------------------------------------------------------
 // mappings (rounding kept as in their plain definitions: no contraction)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double bw_map(double r, double M2, double MG, double m2lo, double tlo,
+__device__ __forceinline__ double bw_map(double r, double M2, double MG, double invMG, double m2lo, double tlo,
                                          double rlo, double rrng, double& jac) {
 #pragma clang fp contract(off)
   const double rho = rlo + r * rrng;
-  double m2;
-  if (rho < 0.0) {
-    // below the pole: measured from the window's lower edge (tangent addition
-    // theorem), free of the cancellation in M^2 + M G tan(rho) as m^2 -> m2lo
-    const double td = tan(r * rrng);
-    m2 = m2lo + MG * (1.0 + tlo * tlo) * td / (1.0 - tlo * td);
-  } else {
-    m2 = M2 + MG * tan(rho);
-  }
+  // below the pole the mass is measured from the window's lower edge (tangent
+  // addition theorem), free of the cancellation in M^2 + M G tan(rho) as m^2 -> m2lo;
+  // one tangent per event either way (no divergent second call)
+  const bool below = rho < 0.0;
+  const double t = tan(below ? r * rrng : rho);
+  const double m2 = below ? m2lo + MG * (1.0 + tlo * tlo) * t / (1.0 - tlo * t) : M2 + MG * t;
   const double dm = m2 - M2;
-  jac = rrng * (dm * dm + MG * MG) / MG;
+  jac = rrng * (dm * dm + MG * MG) * invMG;
   return m2;
 }
 
@@ -131,7 +128,7 @@ __device__ __forceinline__ double f_eemumu(const PhysConst& c, const double* x) 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
   double jbw;
-  const double m2 = bw_map(x[0], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  const double m2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
   double L, l1, l2;
   {
 #pragma clang fp contract(off)
@@ -171,7 +168,7 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
   double jbw;
-  const double m2 = bw_map(x[0], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  const double m2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
   double L, l1, l2;
   {
 #pragma clang fp contract(off)
@@ -190,10 +187,11 @@ __device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
   if (!pass) return 0.0;
   const double ds = m2 - c.M2;
   const double den = ds * ds + c.MG * c.MG;
-  const double me = c.g4v2_24 * m2 * m2 * (1.0 + cs * cs) / den;
+  // |M|^2 / (2 shat) = g^4 |V|^2 / 24 * shat^2 (1 + cos^2) / den / (2 shat): one division
+  const double me_flux = c.g4v2_24 * (0.5 * m2) * (1.0 + cs * cs) / den;
   const double ff = c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(em1 * em2));
-  // conv * J_bw * J_tau * flux 1/(2 shat) * (2 * 2 pi)/(32 pi^2)
-  return c.conv * jbw * jtau * (0.5 / m2) * (1.0 / (8.0 * kPi)) * ff * me;
+  // conv * J_bw * J_tau * |M|^2 / (2 shat) * (2 * 2 pi)/(32 pi^2)
+  return c.conv * jbw * jtau * (1.0 / (8.0 * kPi)) * ff * me_flux;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,12 +386,12 @@ __device__ __forceinline__ void sincos_2pi(float x, float& s, float& c) { sincos
 template <typename R>
 __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x) {
   double jp, jm;
-  const double mp2 = bw_map(x[0], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jp);
+  const double mp2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jp);
   if (!(mp2 > 0.0)) return 0.0;
   const double mp = sqrt(mp2);
   const double up = (c.rs - mp) * (c.rs - mp);
   const double rrng2 = atan((up - c.M2) / c.MG) - c.rho_lo;
-  const double mm2 = bw_map(x[1], c.M2, c.MG, c.m2lo, c.tlo, c.rho_lo, rrng2, jm);
+  const double mm2 = bw_map(x[1], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rrng2, jm);
   if (!(mm2 > 0.0)) return 0.0;
   const double mm = sqrt(mm2);
   const double sh = c.shat;

@@ -2,17 +2,20 @@
 // VEGAS iteration (Campbell, Ellis, Giele, "A Multi-Threaded Version of MCFM",
 // Sec. 2.1-2.2).
 //
-// One iteration is four launches on the handle's stream:
+// One iteration is three or four launches on the handle's stream:
 //   k_event     one event per lane (grid-stride): Philox point -> grid map ->
 //               phase space -> PDFs x |M|^2 -> weight; writes the event record
-//               (w, packed bin indices) and the exact max |w| that fixes the
-//               iteration's fixed-point scales.
-//   k_accum     reads the records and accumulates S1 = sum w, S2 = sum w^2 and
-//               d[dim][bin] = sum w^2 as exact integer digits (per-lane and LDS
-//               sums, one row of per-block partials).
-//   k_accsum,   column sums of the partials (integer atomics), then one block:
-//   k_finalize  digits -> doubles, I_j, var_j.
-//   k_refine    (vegas_refine) one block, one wave per dimension: smoothing,
+//               (w, packed bin indices) and the exact max |w|.  From the second
+//               iteration on it also adds each event's exact digits of w, w^2
+//               (S1, S2 per lane; d[dim][bin] in LDS) at the scales the previous
+//               iteration fixed, one row of partials per block.
+//   k_accum     first iteration only (or digits too large for LDS): the same
+//               digits from the records, at this iteration's own scales.
+//   k_accsum    column sums of the partial rows (integer atomics).
+//   k_finalize  one block: totals -> d, S1, S2 as doubles, I_j and var_j; re-folds
+//               from the records if this iteration's max |w| left the window of
+//               the previous scale, and fixes the next iteration's scales.
+//   k_refine    (vegas_refine) one 64-lane block per dimension: smoothing,
 //               damping, equal-importance rebinning.
 // Integer accumulation is associative, so every launch configuration gives
 // byte-identical results (the paper's independence from the thread count,
@@ -161,7 +164,7 @@ constexpr double kExtLo = 0x1p-40, kExtHi = 1.0 - 0x1p-40;
 
 template <int PROC>
 constexpr int event_min_waves() {
-  return PROC == VEGAS_WW_4L ? 2 : 4;
+  return PROC == VEGAS_WW_4L ? 2 : (PROC == VEGAS_W_PLUS ? 3 : 4);
 }
 
 // EXT: the point is the learned proposal's y (binary32, kept inside the open unit
@@ -274,23 +277,6 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
 // ---------------------------------------------------------------------------
 constexpr int kColTile = 32, kRowTile = 32;
 
-// digit sums over the accumulation kernel's blocks
-__global__ void k_accsum(DevBufs b, int ncol, int rows) {
-  __shared__ long long red[8][kColTile];
-  const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
-  const int col = blockIdx.x * kColTile + c;
-  long long sum = 0;
-  if (col < ncol)
-    for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8)
-      sum += b.part_acc[static_cast<int64_t>(r) * ncol + col];
-  red[rg][c] = sum;
-  __syncthreads();
-  if (rg == 0 && col < ncol) {
-    for (int g = 1; g < 8; ++g) sum += red[g][c];
-    if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc_tot[col]), static_cast<unsigned long long>(sum));
-  }
-}
-
 // ---------------------------------------------------------------------------
 // K2 (two-pass fold): exact accumulation of S1, S2 and d from the records at the
 // scales of this iteration's own max |w|.  Block (x, y) holds the histogram of
@@ -361,8 +347,7 @@ struct FinArgs {
   int fused;
 };
 
-__global__ void k_finalize(FinArgs f) {
-  extern __shared__ unsigned char smem[];  // fused: [3 (2 + D n)] for a re-fold
+__device__ void finalize_block(const FinArgs& f, unsigned char* smem) {
   __shared__ double s12[2];
   const DevBufs& b = f.b;
   const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol = 3 * (2 + nslot);
@@ -429,6 +414,32 @@ __global__ void k_finalize(FinArgs f) {
     b.cnt[0] = 0ull;
     b.cnt[1] = 0ull;
   }
+}
+
+// column sums of the per-block partial rows: block (x, y) covers 32 columns and rows
+// [32 y, 32 y + 32) with 8 row groups, then one device-wide integer atomic per
+// column (sums of integers: exact and order-free)
+__global__ void k_accsum(DevBufs b, int ncol, int rows) {
+  __shared__ long long red[8][kColTile];
+  const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  const int col = blockIdx.x * kColTile + c;
+  long long sum = 0;
+  if (col < ncol)
+    for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8)
+      sum += b.part_acc[static_cast<int64_t>(r) * ncol + col];
+  red[rg][c] = sum;
+  __syncthreads();
+  if (rg == 0 && col < ncol) {
+    for (int g = 1; g < 8; ++g) sum += red[g][c];
+    if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc_tot[col]), static_cast<unsigned long long>(sum));
+  }
+}
+
+// one block (a separate launch: a grid-wide "last block" hand-off would need a
+// device-scope fence in every block, which costs far more than the launch)
+__global__ void k_finalize(FinArgs f) {
+  extern __shared__ unsigned char smem[];  // fused: [3 (2 + D n)] for a re-fold
+  finalize_block(f, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -695,6 +706,7 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
     k.MG = MZ * GZ;
     const double lo = p[VEGAS_P_MLO], hi = p[VEGAS_P_MHI] > 0 ? p[VEGAS_P_MHI] : rs;
     k.m2lo = lo * lo;
+    k.invMG = 1.0 / k.MG;
     k.tlo = (k.m2lo - MZ * MZ) / k.MG;
     k.rho_lo = std::atan(k.tlo);
     k.rho_rng = std::atan((hi * hi - MZ * MZ) / k.MG) - k.rho_lo;
@@ -714,6 +726,7 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
     k.MG = MW * GW;
     const double lo = p[VEGAS_P_MLO], hi = p[VEGAS_P_MHI] > 0 ? p[VEGAS_P_MHI] : rs;
     k.m2lo = lo * lo;
+    k.invMG = 1.0 / k.MG;
     k.tlo = (k.m2lo - MW * MW) / k.MG;
     k.rho_lo = std::atan(k.tlo);
     k.rho_rng = std::atan((hi * hi - MW * MW) / k.MG) - k.rho_lo;
@@ -728,6 +741,7 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
     k.rs = rs;
     k.shat = rs * rs;
     k.m2lo = 0.0;
+    k.invMG = 1.0 / k.MG;
     k.tlo = (0.0 - MW * MW) / k.MG;
     k.rho_lo = std::atan(k.tlo);
     k.rho_rng = std::atan((k.shat - MW * MW) / k.MG) - k.rho_lo;
@@ -1172,12 +1186,6 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   }
   const int ncol = 3 * (2 + nslot);
   {
-    TimedLaunch t(h, 2);
-    hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
-                          dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
-    VG_HIP(t.done());
-  }
-  {
     FinArgs fa;
     fa.b = h->b;
     fa.nev = n_events;
@@ -1186,6 +1194,12 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     fa.nbins = h->n;
     fa.iter = h->iter;
     fa.fused = fused ? 1 : 0;
+    {
+      TimedLaunch t(h, 2);
+      hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
+                            dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
+      VG_HIP(t.done());
+    }
     TimedLaunch t(h, 2);
     hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused ? 1024 : 256), fused ? h->fin_lds : 0, h->stream, t.e0,
                           t.e1, 0, fa);
