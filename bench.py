@@ -30,9 +30,9 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): None,
-    ("ww_4l", "fp64"): None,
-    ("ww_4l", "fp32me"): None,
+    ("w_plus", "fp64"): {"f64": 466.0, "f32": 0.0, "traffic": 19_724_698, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1495.5, "f32": 0.0, "traffic": 171_619_942, "events": 10_000_000},
+    ("ww_4l", "fp32me"): {"f64": 835.5, "f32": 606.0, "traffic": 170_322_330, "events": 10_000_000},
 }
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 157.3
@@ -63,7 +63,9 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "adjoint"])
+    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "adjoint", "flow"])
+    ap.add_argument("--train-events", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--events", type=int, default=0, help="events per iteration (0: workload's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32me"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -147,19 +149,85 @@ def bench_adjoint(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_flow(args):
+    """Learned proposal on the W+W- integrand: the VEGAS grid converged (10 x 1e7),
+    the flow trained on 1e6 events of one more VEGAS iteration (Adam, lr 1e-3, batch
+    4096, 20 epochs), then K iterations of 1e7 events with the flow and K with plain
+    VEGAS on the same frozen grid.  One step = one flow iteration."""
+    import torch
+
+    import paper_1503_06182_amd as P
+    import workloads as W
+    torch.cuda.set_device(0)
+    cfg = W.config("ww_4l")
+    N = args.events or cfg["n_events"]
+    g = P.Integrator(cfg["process"], 8, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"], max_events=N)
+    for _ in range(cfg["n_iter"]):
+        g.iterate(N, sync=False)
+        g.refine()
+    g.iterate(args.train_events)
+    y, w = g.export(0, args.train_events)
+    f = P.Flow(max_batch=4096, max_sample=N, seed=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = P.train(f, y, w, epochs=args.epochs, batch=4096, lr=1e-3, log_every=1000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps_train = f.steps
+
+    def run(kind, k):
+        rs = []
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            rs.append(g.iterate_flow(f, N) if kind == "flow" else g.iterate(N))
+        torch.cuda.synchronize()
+        return rs, time.perf_counter() - t
+
+    for _ in range(args.warmup):
+        g.iterate_flow(f, N)
+        g.iterate(N)
+    rf, tf = run("flow", args.steps)
+    rv, tv = run("vegas", args.steps)
+    If, sf = combine([(r["I"], r["var"]) for r in rf])
+    Iv, sv = combine([(r["I"], r["var"]) for r in rv])
+    eff_f = 1.0 / ((sf / If) ** 2 * tf)
+    eff_v = 1.0 / ((sv / Iv) ** 2 * tv)
+    relvar_f = sum(r["var"] * N / r["I"] ** 2 for r in rf) / len(rf)
+    relvar_v = sum(r["var"] * N / r["I"] ** 2 for r in rv) / len(rv)
+    line = {"metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
+            "value": args.steps * N / tf, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": tf / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mlp/f32-spline/f64-weight",
+            "data": "synthetic (counter-based Philox stream, seed 1; parametric PDFs)",
+            "config": {"workload": "flow", "integrand": "ww_4l", "events_per_iteration": N,
+                       "train_events": args.train_events, "epochs": args.epochs, "batch": 4096},
+            "effective_events_per_s": eff_f, "vegas_events_per_s": args.steps * N / tv,
+            "vegas_effective_events_per_s": eff_v, "effective_gain_vs_vegas": eff_f / eff_v,
+            "per_event_rel_variance": {"flow": relvar_f, "vegas": relvar_v},
+            "flow_uses": "flow" if eff_f > eff_v else "vegas (fallback)",
+            "integral_pb": {"flow": If, "flow_sigma": sf, "vegas": Iv, "vegas_sigma": sv},
+            "training": {"seconds": t_train, "steps": steps_train, "loss_first": losses[0][1],
+                         "loss_last": losses[-1][1]}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: there is no multi-GPU path in this library "
+              "(how it would shard is described in the design notes); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
     if args.workload == "adjoint":
         bench_adjoint(args)
+        return
+    if args.workload == "flow":
+        bench_flow(args)
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
-              file=sys.stderr)
-        sys.exit(2)
     import torch
 
     import paper_1503_06182_amd as P
