@@ -77,15 +77,22 @@ def bf16(x):
     return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
 
 
+def half(x):
+    """Round to binary16 (round to nearest even), back to float64."""
+    return x.to(torch.float16).to(torch.float64)
+
+
 def mlp(cond, theta, l, bf16_emulation=False):
-    """Spline parameters of layer l.  bf16_emulation rounds the operands of the two
-    128-wide products (h1, W2, h2, W3) to bfloat16, as the library's matrix-core
-    path does; the first layer (4 inputs) and the biases stay unrounded."""
+    """Spline parameters of layer l.  bf16_emulation rounds as the library's
+    matrix-core path does: the operands of the two 128-wide products (h1, W2, h2,
+    W3) to bfloat16 and the resulting spline parameters to binary16; the first
+    layer (4 inputs) and the biases stay unrounded."""
     W1, b1, W2, b2, W3, b3 = unpack(theta, l)
     r = bf16 if bf16_emulation else (lambda t: t)
     h1 = torch.relu(cond @ W1 + b1)
     h2 = torch.relu(r(h1) @ r(W2) + b2)
-    return r(h2) @ r(W3) + b3
+    out = r(h2) @ r(W3) + b3
+    return half(out) if bf16_emulation else out
 
 
 def spline_knots(raw):

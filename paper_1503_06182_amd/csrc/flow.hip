@@ -63,18 +63,15 @@ __global__ void k_flow_init(float* master, uint64_t seed) {
 }
 
 // ---------------------------------------------------------------------------
-// MLP of one tile: cond (LDS [32][4]) -> h1, h2 (LDS bf16) -> spline parameters (LDS fp32)
+// MLP of one 32-event tile for the backward: cond (LDS [32][4]) -> h1, h2 (LDS bf16)
+// -> spline parameters (LDS, binary32 holding the binary16-rounded values).  B comes
+// from global memory; the MFMA sequence per output tile is the forward kernel's, so
+// every value equals the forward's bit for bit.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void mlp_tile(const float* __restrict__ m, const uint16_t* __restrict__ w,
-                                         const float (*cond)[4], uint16_t* h1, uint16_t* h2, float* par) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < FL_TILE * FL_HID; i += blockDim.x) {
-    const int e = i / FL_HID, j = i % FL_HID;
-    float a = m[FO_B1 + j];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) a += cond[e][c] * m[FO_W1 + c * FL_HID + j];
-    h1[e * FL_LDA + j] = f2bf(fmaxf(a, 0.f));
-  }
+__device__ __forceinline__ void mlp_tile32(const float* __restrict__ m, const uint16_t* __restrict__ w,
+                                           const float (*cond)[4], uint16_t* h1, uint16_t* h2, float* par) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  mlp_h1(m, cond, h1, FL_TILE);
   __syncthreads();
   // h2: 2 row blocks x 8 column blocks; wave w owns column blocks 2w, 2w+1
   for (int rb = 0; rb < 2; ++rb)
@@ -100,7 +97,7 @@ __device__ __forceinline__ void mlp_tile(const float* __restrict__ m, const uint
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = rb * 16 + 4 * (lane >> 4) + j;
-        par[row * FL_LDP + col] = acc[j] + bias;
+        par[row * FL_LDP + col] = round_h(acc[j] + bias);
       }
     }
   __syncthreads();
@@ -108,34 +105,85 @@ __device__ __forceinline__ void mlp_tile(const float* __restrict__ m, const uint
 
 // one coupling layer over a batch; SAMPLE: inverse splines (z -> y), else forward (y -> z).
 // vout may alias vin.  logq[i] += sum of log s' of the four transformed coordinates.
+// Tiles of 64 events; each wave keeps the B operands of its output columns (W2: 2
+// column blocks, W3: 3) for all eight k-steps in registers for the whole launch.
 template <bool SAMPLE>
-__global__ __launch_bounds__(256) void k_flow_layer(const float* __restrict__ master, const uint16_t* __restrict__ wb,
-                                                     int l, const float* vin, float* vout, float* logq, int64_t B) {
-  __shared__ float cond[FL_TILE][4];
-  __shared__ __align__(16) uint16_t h1[FL_TILE * FL_LDA];
-  __shared__ __align__(16) uint16_t h2[FL_TILE * FL_LDA];
-  __shared__ __align__(16) float par[FL_TILE * FL_LDP];
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__ master,
+                                                        const uint16_t* __restrict__ wb, int l, const float* vin,
+                                                        float* vout, float* logq, int64_t B) {
+  __shared__ float cond[FL_TILE_F][4];
+  __shared__ __align__(16) uint16_t h1[FL_TILE_F * FL_LDA];
+  __shared__ __align__(16) uint16_t h2[FL_TILE_F * FL_LDA];
+  __shared__ __align__(16) _Float16 par[FL_TILE_F * FL_LDH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float* m = master + l * FL_LAYER;
   const uint16_t* w = wb + static_cast<int64_t>(l) * FB_LAYER;
-  for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE; e0 < B; e0 += static_cast<int64_t>(gridDim.x) * FL_TILE) {
-    if (tid < FL_TILE * 4) {
+  bf16x4_t b2[2][FL_HID / 16], b3[3][FL_HID / 16];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int ks = 0; ks < FL_HID / 16; ++ks) b2[cc][ks] = load_bfrag(w + FB_W2T, FL_HID, (2 * wave + cc) * 16, ks * 16, lane);
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int ks = 0; ks < FL_HID / 16; ++ks) b3[cc][ks] = load_bfrag(w + FB_W3T, FL_HID, (3 * wave + cc) * 16, ks * 16, lane);
+  float bias2[2], bias3[3];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc) bias2[cc] = m[FO_B2 + (2 * wave + cc) * 16 + (lane & 15)];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const int col = (3 * wave + cc) * 16 + (lane & 15);
+    bias3[cc] = col < FL_NOUT ? m[FO_B3 + col] : 0.f;
+  }
+  const int ri = lane & 15, kq = 4 * (lane >> 4);
+  for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE_F; e0 < B;
+       e0 += static_cast<int64_t>(gridDim.x) * FL_TILE_F) {
+    {
       const int e = tid >> 2, c = tid & 3;
       const int64_t ev = e0 + e;
       cond[e][c] = ev < B ? vin[ev * FL_NDIM + kFlowC[l][c]] : 0.5f;
     }
     __syncthreads();
-    mlp_tile(m, w, cond, h1, h2, par);
-    if (tid < FL_TILE * 4) {
+    mlp_h1(m, cond, h1, FL_TILE_F);
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < FL_HID / 16; ++ks) {
+          const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(h1 + (rb * 16 + ri) * FL_LDA + ks * 16 + kq);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b2[cc][ks], acc, 0, 0, 0);
+        }
+        const int col = (2 * wave + cc) * 16 + ri;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) h2[(rb * 16 + kq + j) * FL_LDA + col] = f2bf(fmaxf(acc[j] + bias2[cc], 0.f));
+      }
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < FL_HID / 16; ++ks) {
+          const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(h2 + (rb * 16 + ri) * FL_LDA + ks * 16 + kq);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b3[cc][ks], acc, 0, 0, 0);
+        }
+        const int col = (3 * wave + cc) * 16 + ri;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) par[(rb * 16 + kq + j) * FL_LDH + col] = static_cast<_Float16>(acc[j] + bias3[cc]);
+      }
+    __syncthreads();
+    {
       const int e = tid >> 2, j = tid & 3;
       const int64_t ev = e0 + e;
       float ld = 0.f;
       if (ev < B) {
-        Knots K;
-        make_knots(&par[e * FL_LDP + j * FL_NPAR], K);
         const int d = kFlowX[l][j];
         const float v = vin[ev * FL_NDIM + d];
-        const float o = SAMPLE ? rqs_inv(K, v, ld) : rqs_fwd(K, v, ld);
+        const float o = spline_eval<SAMPLE>(par + e * FL_LDH + j * FL_NPAR, v, ld);
         vout[ev * FL_NDIM + d] = o;
         if (vout != vin) vout[ev * FL_NDIM + kFlowC[l][j]] = cond[e][j];
       }
@@ -179,7 +227,7 @@ __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict_
       if (ev < B) s.COND[ev * 4 + c] = v;
     }
     __syncthreads();
-    mlp_tile(m, w, cond, h1, h2, par);
+    mlp_tile32(m, w, cond, h1, h2, par);
     // activations of the tile for the weight gradients
     for (int i = tid; i < FL_TILE * FL_HID; i += blockDim.x) {
       const int e = i / FL_HID, j = i % FL_HID;
@@ -288,78 +336,92 @@ __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// weight gradients of one layer (overwrites its slice of grad):
-//   dW3 = H2^T DR, dW2 = H1^T DH2 on MFMA (contraction over the batch, 16 events per step);
+// weight gradients of one layer, split over the batch (split-K): split sp sums the
+// events [sp kc, (sp + 1) kc) into its own partial row; a second kernel adds the
+// rows in split order (deterministic) and writes the layer's slice of grad.
+//   dW3 = H2^T DR, dW2 = H1^T DH2 on MFMA (16 events per step);
 //   dW1 = COND^T DH1, db1..db3 = column sums, on the VALU
 // ---------------------------------------------------------------------------
+constexpr int kWgTiles = 96 + 64;                  // 16x16 output tiles: dW3 (8 x 12), dW2 (8 x 8)
+constexpr int kWgValu = 512 + 128 + 128 + FL_NOUT;  // dW1, db1, db2, db3
+constexpr int kWgPart = kWgTiles * 256 + kWgValu;   // floats per split
+constexpr int kWgMaxSplit = 64;
+constexpr int kWgBlocksX = (kWgTiles + (kWgValu + 63) / 64 + 3) / 4;
+
 __device__ __forceinline__ f32x4_t mfma_tn(const uint16_t* __restrict__ H, int ldh, const uint16_t* __restrict__ D,
-                                           int ldd, int m0, int n0, int64_t K, int lane) {
+                                           int ldd, int m0, int n0, int64_t k_lo, int64_t k_hi, int lane) {
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
   const int ri = lane & 15, kq = 4 * (lane >> 4);
-  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll 4
+  for (int64_t k0 = k_lo; k0 < k_hi; k0 += 16) {
     bf16x4_t a, b;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t kk = k0 + kq + j;
-      a[j] = kk < K ? static_cast<short>(H[kk * ldh + m0 + ri]) : static_cast<short>(0);
-      b[j] = kk < K ? static_cast<short>(D[kk * ldd + n0 + ri]) : static_cast<short>(0);
+      a[j] = kk < k_hi ? static_cast<short>(H[kk * ldh + m0 + ri]) : static_cast<short>(0);
+      b[j] = kk < k_hi ? static_cast<short>(D[kk * ldd + n0 + ri]) : static_cast<short>(0);
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_flow_wgrad(int l, int64_t B, FlowBwdBufs s, float* grad) {
-  float* g = grad + l * FL_LAYER;
+__global__ __launch_bounds__(256) void k_flow_wgrad_part(int64_t B, int kc, FlowBwdBufs s, float* part) {
   const int lane = threadIdx.x & 63;
   const int wave_g = blockIdx.x * 4 + (threadIdx.x >> 6);
-  // MFMA tiles: 96 of dW3 (8 x 12) then 64 of dW2 (8 x 8)
+  const int64_t k_lo = static_cast<int64_t>(blockIdx.y) * kc;
+  const int64_t k_hi = k_lo + kc < B ? k_lo + kc : B;
+  float* out = part + static_cast<int64_t>(blockIdx.y) * kWgPart;
   if (wave_g < 96) {
     const int mb = wave_g / 12, nb = wave_g % 12;
-    const f32x4_t acc = mfma_tn(s.H2, FL_HID, s.DRb, FL_NOUTP, mb * 16, nb * 16, B, lane);
-    const int col = nb * 16 + (lane & 15);
+    const f32x4_t acc = mfma_tn(s.H2, FL_HID, s.DRb, FL_NOUTP, mb * 16, nb * 16, k_lo, k_hi, lane);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = mb * 16 + 4 * (lane >> 4) + j;
-      if (col < FL_NOUT) g[FO_W3 + row * FL_NOUT + col] = acc[j];
-    }
-  } else if (wave_g < 160) {
+    for (int j = 0; j < 4; ++j) out[wave_g * 256 + lane * 4 + j] = acc[j];
+  } else if (wave_g < kWgTiles) {
     const int t = wave_g - 96, mb = t / 8, nb = t % 8;
-    const f32x4_t acc = mfma_tn(s.H1, FL_HID, s.DH2b, FL_HID, mb * 16, nb * 16, B, lane);
-    const int col = nb * 16 + (lane & 15);
+    const f32x4_t acc = mfma_tn(s.H1, FL_HID, s.DH2b, FL_HID, mb * 16, nb * 16, k_lo, k_hi, lane);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = mb * 16 + 4 * (lane >> 4) + j;
-      g[FO_W2 + row * FL_HID + col] = acc[j];
-    }
+    for (int j = 0; j < 4; ++j) out[wave_g * 256 + lane * 4 + j] = acc[j];
   } else {
-    // VALU part: thread index over 512 (dW1) + 128 (db1) + 128 (db2) + 188 (db3)
-    const int t = (wave_g - 160) * 64 + lane;
+    const int t = (wave_g - kWgTiles) * 64 + lane;
+    float a = 0.f;
     if (t < 512) {
       const int c = t / FL_HID, n = t % FL_HID;
-      float a = 0.f;
-      for (int64_t b = 0; b < B; ++b) a += s.COND[b * 4 + c] * s.DH1f[b * FL_HID + n];
-      g[FO_W1 + c * FL_HID + n] = a;
+      for (int64_t b = k_lo; b < k_hi; ++b) a += s.COND[b * 4 + c] * s.DH1f[b * FL_HID + n];
     } else if (t < 640) {
-      const int n = t - 512;
-      float a = 0.f;
-      for (int64_t b = 0; b < B; ++b) a += s.DH1f[b * FL_HID + n];
-      g[FO_B1 + n] = a;
+      for (int64_t b = k_lo; b < k_hi; ++b) a += s.DH1f[b * FL_HID + (t - 512)];
     } else if (t < 768) {
-      const int n = t - 640;
-      float a = 0.f;
-      for (int64_t b = 0; b < B; ++b) a += s.DH2f[b * FL_HID + n];
-      g[FO_B2 + n] = a;
-    } else if (t < 956) {
-      const int n = t - 768;
-      float a = 0.f;
-      for (int64_t b = 0; b < B; ++b) a += s.DRf[b * FL_NOUTP + n];
-      g[FO_B3 + n] = a;
+      for (int64_t b = k_lo; b < k_hi; ++b) a += s.DH2f[b * FL_HID + (t - 640)];
+    } else if (t < kWgValu) {
+      for (int64_t b = k_lo; b < k_hi; ++b) a += s.DRf[b * FL_NOUTP + (t - 768)];
     }
+    if (t < kWgValu) out[kWgTiles * 256 + t] = a;
   }
 }
 
-constexpr int kWgradBlocks = (160 + 15 + 3) / 4;  // 160 MFMA waves + 15 VALU waves (956 threads): 44 blocks
+__global__ void k_flow_wgrad_sum(int nsplit, const float* __restrict__ part, float* grad_layer) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kWgPart) return;
+  float a = 0.f;
+  for (int sp = 0; sp < nsplit; ++sp) a += part[static_cast<int64_t>(sp) * kWgPart + idx];
+  if (idx < kWgTiles * 256) {
+    const int tile = idx / 256, r = idx % 256, lane = r / 4, j = r % 4;
+    const int row16 = 4 * (lane >> 4) + j, col16 = lane & 15;
+    if (tile < 96) {
+      const int row = (tile / 12) * 16 + row16, col = (tile % 12) * 16 + col16;
+      if (col < FL_NOUT) grad_layer[FO_W3 + row * FL_NOUT + col] = a;
+    } else {
+      const int t = tile - 96;
+      grad_layer[FO_W2 + ((t / 8) * 16 + row16) * FL_HID + (t % 8) * 16 + col16] = a;
+    }
+  } else {
+    const int t = idx - kWgTiles * 256;
+    if (t < 512) grad_layer[FO_W1 + t] = a;  // [c][n] with c = t / 128
+    else if (t < 640) grad_layer[FO_B1 + t - 512] = a;
+    else if (t < 768) grad_layer[FO_B2 + t - 640] = a;
+    else grad_layer[FO_B3 + t - 768] = a;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // loss terms: W = sum w (one block, fixed order), glq_i = -w_i / W; loss = -sum w log q / W
@@ -462,6 +524,7 @@ struct vegas_flow_state {
   double *scal; // [4] sum w, loss
   FlowBwdBufs bw;
   float *zs, *lqs;  // sampling buffers [max_sample][8], [max_sample]
+  float* wpart;     // [kWgMaxSplit][kWgPart] split-K partials of the weight gradients
   uint64_t adam_t;
   hipEvent_t ev_ready, ev_used;  // cross-stream ordering with a VEGAS handle's stream
 };
@@ -485,6 +548,10 @@ int flow_prep(vegas_flow_state* f) {
   return VEGAS_OK;
 }
 
+// forward-kernel blocks: two resident per CU (LDS 60 KB, 256 VGPRs); more tiles per block
+// amortise the per-launch load of the weights into registers
+constexpr int kFwdBlocks = 2 * 256;
+
 int64_t grid_for(int64_t n, int per_block, int cap) {
   int64_t g = (n + per_block - 1) / per_block;
   if (g > cap) g = cap;
@@ -498,7 +565,7 @@ int flow_forward(vegas_flow_state* f, const float* y, int64_t B) {
   VF_HIP(hipGetLastError());
   const int64_t stride = static_cast<int64_t>(f->max_batch) * FL_NDIM;
   for (int l = 0; l < FL_NLAYER; ++l) {
-    hipLaunchKernelGGL(k_flow_layer<false>, dim3(grid_for(B, FL_TILE, 4096)), dim3(256), 0, f->stream, f->master,
+    hipLaunchKernelGGL(k_flow_layer<false>, dim3(grid_for(B, FL_TILE_F, kFwdBlocks)), dim3(256), 0, f->stream, f->master,
                        f->wb, l, f->V + l * stride, f->V + (l + 1) * stride, f->logq, B);
     VF_HIP(hipGetLastError());
   }
@@ -521,7 +588,13 @@ int flow_backward(vegas_flow_state* f, const double* w, int64_t B, double* loss_
     hipLaunchKernelGGL(k_flow_layer_bwd, dim3(grid_for(B, FL_TILE, 4096)), dim3(256), 0, f->stream, f->master, f->wb,
                        l, f->V + l * stride, gout, gin, f->glq, B, f->bw);
     VF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_flow_wgrad, dim3(kWgradBlocks), dim3(256), 0, f->stream, l, B, f->bw, f->grad);
+    int kc = 256;
+    if ((B + kc - 1) / kc > kWgMaxSplit) kc = static_cast<int>(((B + kWgMaxSplit - 1) / kWgMaxSplit + 15) / 16 * 16);
+    const int nsplit = static_cast<int>((B + kc - 1) / kc);
+    hipLaunchKernelGGL(k_flow_wgrad_part, dim3(kWgBlocksX, nsplit), dim3(256), 0, f->stream, B, kc, f->bw, f->wpart);
+    VF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_flow_wgrad_sum, dim3((kWgPart + 255) / 256), dim3(256), 0, f->stream, nsplit, f->wpart,
+                       f->grad + l * FL_LAYER);
     VF_HIP(hipGetLastError());
     float* t = gout;
     gout = gin;
@@ -565,6 +638,7 @@ int vegas_flow_create(int32_t max_batch, int64_t max_sample, uint64_t seed, void
   const size_t o_DH2b = take(2 * Bm * FL_HID), o_DRf = take(4 * Bm * FL_NOUTP), o_DH2f = take(4 * Bm * FL_HID);
   const size_t o_DH1f = take(4 * Bm * FL_HID), o_COND = take(4 * Bm * 4);
   const size_t o_zs = take(4 * S * FL_NDIM), o_lqs = take(4 * S);
+  const size_t o_wpart = take(4 * static_cast<size_t>(kWgMaxSplit) * kWgPart);
   if (hipMalloc(&f->mem, off) != hipSuccess) {
     delete f;
     return VEGAS_ENOMEM;
@@ -592,6 +666,7 @@ int vegas_flow_create(int32_t max_batch, int64_t max_sample, uint64_t seed, void
   f->bw.COND = reinterpret_cast<float*>(b + o_COND);
   f->zs = reinterpret_cast<float*>(b + o_zs);
   f->lqs = reinterpret_cast<float*>(b + o_lqs);
+  f->wpart = reinterpret_cast<float*>(b + o_wpart);
   if (hipEventCreateWithFlags(&f->ev_ready, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&f->ev_used, hipEventDisableTiming) != hipSuccess) {
     (void)hipFree(f->mem);
@@ -713,7 +788,7 @@ int vegas_flow_sample(vegas_flow f, const float* z_dev, int64_t n, float* y_dev,
   hipLaunchKernelGGL(k_flow_zero, dim3(grid_for(n, 256, 1024)), dim3(256), 0, f->stream, logq_dev, n);
   VF_HIP(hipGetLastError());
   for (int l = FL_NLAYER - 1; l >= 0; --l) {
-    hipLaunchKernelGGL(k_flow_layer<true>, dim3(grid_for(n, FL_TILE, 8192)), dim3(256), 0, f->stream, f->master,
+    hipLaunchKernelGGL(k_flow_layer<true>, dim3(grid_for(n, FL_TILE_F, kFwdBlocks)), dim3(256), 0, f->stream, f->master,
                        f->wb, l, y_dev, y_dev, logq_dev, n);
     VF_HIP(hipGetLastError());
   }
@@ -737,7 +812,7 @@ int flow_sample_events(vegas_flow f, hipStream_t s, uint64_t seed, uint32_t iter
   hipLaunchKernelGGL(k_flow_zinit, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, seed, iter, n, f->zs, f->lqs);
   VF_HIP(hipGetLastError());
   for (int l = FL_NLAYER - 1; l >= 0; --l) {
-    hipLaunchKernelGGL(k_flow_layer<true>, dim3(grid_for(n, FL_TILE, 8192)), dim3(256), 0, s, f->master, f->wb, l,
+    hipLaunchKernelGGL(k_flow_layer<true>, dim3(grid_for(n, FL_TILE_F, kFwdBlocks)), dim3(256), 0, s, f->master, f->wb, l,
                        f->zs, f->zs, f->lqs, n);
     VF_HIP(hipGetLastError());
   }

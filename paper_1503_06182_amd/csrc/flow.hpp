@@ -9,11 +9,13 @@
 // splines, log q(y) = sum log s'.  Sampling direction z -> y: layers 5..0,
 // inverse splines.  Base density uniform on [0,1]^8.
 //
-// One block (256 threads = 4 waves) owns a tile of 32 events: the first layer
-// of the MLP on the VALU (K = 4), the two 128-wide contractions on
-// v_mfma_f32_16x16x16_bf16 (A from LDS, B = weights from global memory,
-// stored so that each lane's four k-consecutive operands are one 8-byte load),
-// then one thread per (event, transformed coordinate) for the spline.
+// The forward kernels give each block (256 threads = 4 waves) tiles of 64
+// events: the first layer of the MLP on the VALU (K = 4), the two 128-wide
+// contractions on v_mfma_f32_16x16x16_bf16 (A from LDS; B, the layer's weights,
+// held in each wave's registers for the whole launch), the spline parameters
+// rounded to binary16 in LDS, then one thread per (event, transformed
+// coordinate) for the spline.  The backward kernel recomputes the same MLP
+// (tiles of 32, B from global memory, the same MFMA sequence, so the same bits).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,7 +34,10 @@ constexpr int FB_W2T = 0, FB_W3T = 16384, FB_W2N = 16384 + 24576, FB_W3N = 2 * 1
 constexpr int FB_LAYER = 2 * 16384 + 2 * 24576;  // 81920 bf16 per layer
 constexpr float FL_EPS = 1e-3f;
 constexpr int FL_LDA = FL_HID + 4;   // LDS row stride (bf16) of the activation tiles: no bank conflicts
-constexpr int FL_LDP = FL_NOUTP + 4; // LDS row stride (fp32) of the spline-parameter tile
+constexpr int FL_LDP = FL_NOUTP + 4; // LDS row stride (fp32) of the spline-parameter tile (backward)
+constexpr int FL_LDH = FL_NOUTP + 8; // LDS row stride (binary16) of the spline-parameter tile (forward)
+constexpr int FL_TILE_F = 64;        // events per tile of the forward kernels
+constexpr float FL_DSHIFT = 0.53974242f;  // log(expm1(1 - eps)) for eps = 1e-3: raw 0 gives derivative 1
 
 // transformed coordinates of each layer (the conditioning coordinates are the rest, in order)
 __device__ __constant__ const int kFlowX[FL_NLAYER][4] = {{4, 5, 6, 7}, {0, 1, 2, 3}, {1, 3, 5, 7},
@@ -49,6 +54,25 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
   return static_cast<uint16_t>(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+// spline parameters are rounded to binary16 (round to nearest even) in both directions
+__device__ __forceinline__ float round_h(float x) { return static_cast<float>(static_cast<_Float16>(x)); }
+
+// first MLP layer of `rows` events (cond [rows][4] in LDS) -> h1 (bf16, LDS, stride
+// FL_LDA), by the whole block; explicit fma order so every kernel gets the same bits
+__device__ __forceinline__ void mlp_h1(const float* __restrict__ m, const float (*cond)[4], uint16_t* h1, int rows) {
+  for (int i = threadIdx.x; i < rows * FL_HID; i += blockDim.x) {
+    const int e = i / FL_HID, j = i % FL_HID;
+    float a = m[FO_B1 + j];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a = __fmaf_rn(cond[e][c], m[FO_W1 + c * FL_HID + j], a);
+    h1[e * FL_LDA + j] = f2bf(fmaxf(a, 0.f));
+  }
+}
+
+// B operand of one 16x16x16 step: lane l supplies Bt[c0 + l%16][k0 + 4(l/16) .. +3]
+__device__ __forceinline__ bf16x4_t load_bfrag(const uint16_t* __restrict__ Bt, int ldb, int c0, int k0, int lane) {
+  return *reinterpret_cast<const bf16x4_t*>(Bt + static_cast<int64_t>(c0 + (lane & 15)) * ldb + k0 + 4 * (lane >> 4));
+}
 
 // C(16x16 at r0, c0) = sum_k A[r][k] Bt[c][k]: A rows in LDS (stride lda, bf16), Bt rows in
 // global memory (stride ldb, bf16).  Lane l supplies A[r0 + l%16][k0 + 4(l/16) .. +3] and
@@ -68,62 +92,132 @@ __device__ __forceinline__ f32x4_t mfma_rowcol(const uint16_t* A, int lda, const
 }
 
 // ---------------------------------------------------------------------------
-// rational-quadratic spline on [0,1], 16 bins, boundary derivatives 1
+// rational-quadratic spline on [0,1], 16 bins, boundary derivatives 1.
+// Fast single-precision exp / log / reciprocal throughout; the forward and
+// inverse evaluations and the knot construction of the backward use the same
+// operations in the same order, so the backward differentiates exactly the
+// function the forward evaluated.
 // ---------------------------------------------------------------------------
-struct Knots {
-  float xk[FL_NB + 1], yk[FL_NB + 1], dk[FL_NB + 1];
-  float pw[FL_NB], ph[FL_NB];  // softmax outputs (for the backward)
+__device__ __forceinline__ float fexp(float x) { return __expf(x); }
+__device__ __forceinline__ float flog(float x) { return __logf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float softplus_f(float z) { return z > 20.f ? z : flog(1.f + fexp(z)); }
+__device__ __forceinline__ float knot_step(float e, float inv) {  // eps + (1 - 16 eps) softmax
+  return __fmaf_rn(1.f - FL_NB * FL_EPS, e * inv, FL_EPS);
+}
+
+// the four numbers of the rational-quadratic map on one bin, and its evaluation
+struct Bin {
+  float x0, x1, y0, y1, d0, d1;
 };
 
-__device__ __forceinline__ float softplusf(float z) { return z > 20.f ? z : log1pf(expf(z)); }
+__device__ __forceinline__ float rq_forward(const Bin& q, float x, float& ld) {
+  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
+  const float iw = frcp(w);
+  const float s = h * iw;
+  const float xi = (x - q.x0) * iw, t = xi * (1.f - xi);
+  const float den = s + (q.d1 + q.d0 - 2.f * s) * t;
+  const float iden = frcp(den);
+  const float y = q.y0 + h * (s * xi * xi + q.d0 * t) * iden;
+  const float P = q.d1 * xi * xi + 2.f * s * t + q.d0 * (1.f - xi) * (1.f - xi);
+  ld = flog(s * s * P * iden * iden);
+  return y;
+}
 
-__device__ __forceinline__ void make_knots(const float* raw, Knots& K) {
-  const float scale = 1.f - FL_NB * FL_EPS;
-  float m = raw[0];
+__device__ __forceinline__ float rq_inverse(const Bin& q, float y, float& ld) {
+  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
+  const float s = h * frcp(w);
+  const float dy = y - q.y0;
+  const float g = q.d1 + q.d0 - 2.f * s;
+  const float a = h * (s - q.d0) + dy * g;
+  const float b = h * q.d0 - dy * g;
+  const float c = -s * dy;
+  const float disc = fmaxf(b * b - 4.f * a * c, 0.f);
+  float xi = 2.f * c * frcp(-b - sqrtf(disc));
+  xi = fminf(fmaxf(xi, 0.f), 1.f);
+  const float x = q.x0 + xi * w;
+  const float t = xi * (1.f - xi);
+  const float iden = frcp(s + g * t);
+  const float P = q.d1 * xi * xi + 2.f * s * t + q.d0 * (1.f - xi) * (1.f - xi);
+  ld = flog(s * s * P * iden * iden);
+  return x;
+}
+
+// softmax numerators e_i = exp(r_i - max r) of 16 logits and 1 / sum
+template <typename T>
+__device__ __forceinline__ float softmax16(const T* r, float* e) {
+  float m = static_cast<float>(r[0]);
 #pragma unroll
-  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, raw[i]);
+  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, static_cast<float>(r[i]));
   float s = 0.f;
 #pragma unroll
   for (int i = 0; i < FL_NB; ++i) {
-    K.pw[i] = expf(raw[i] - m);
-    s += K.pw[i];
+    e[i] = fexp(static_cast<float>(r[i]) - m);
+    s += e[i];
   }
-  float is = 1.f / s, acc = 0.f;
+  return frcp(s);
+}
+
+// spline of one coordinate from its 47 parameters (forward: x -> y; INV: y -> x) and
+// log s' of the forward map; the bin is the number of interior knots below v (of the
+// x knots forward, of the y knots inverse)
+template <bool INV, typename T>
+__device__ __forceinline__ float spline_eval(const T* p, float v, float& ld) {
+  float ew[FL_NB], eh[FL_NB];
+  const float iw = softmax16(p, ew), ih = softmax16(p + FL_NB, eh);
+  Bin q{0.f, 1.f, 0.f, 1.f, 1.f, 1.f};
+  int k = FL_NB - 1;
+  bool found = false;
+  float cx = 0.f, cy = 0.f;
+#pragma unroll
+  for (int i = 0; i < FL_NB; ++i) {
+    const float nx = i == FL_NB - 1 ? 1.f : cx + knot_step(ew[i], iw);
+    const float ny = i == FL_NB - 1 ? 1.f : cy + knot_step(eh[i], ih);
+    const bool here = !found && (i == FL_NB - 1 || !((INV ? ny : nx) < v));
+    if (here) {
+      q.x0 = cx;
+      q.x1 = nx;
+      q.y0 = cy;
+      q.y1 = ny;
+      k = i;
+      found = true;
+    }
+    cx = nx;
+    cy = ny;
+  }
+  q.d0 = k == 0 ? 1.f : FL_EPS + softplus_f(static_cast<float>(p[2 * FL_NB + k - 1]) + FL_DSHIFT);
+  q.d1 = k == FL_NB - 1 ? 1.f : FL_EPS + softplus_f(static_cast<float>(p[2 * FL_NB + k]) + FL_DSHIFT);
+  return INV ? rq_inverse(q, v, ld) : rq_forward(q, v, ld);
+}
+
+// knots of the backward (all 17 of each kind and the softmax outputs)
+struct Knots {
+  float xk[FL_NB + 1], yk[FL_NB + 1], dk[FL_NB + 1];
+  float pw[FL_NB], ph[FL_NB];  // softmax outputs
+};
+
+__device__ __forceinline__ void make_knots(const float* raw, Knots& K) {
+  float ew[FL_NB], eh[FL_NB];
+  const float iw = softmax16(raw, ew), ih = softmax16(raw + FL_NB, eh);
+  float cx = 0.f, cy = 0.f;
   K.xk[0] = 0.f;
-#pragma unroll
-  for (int i = 0; i < FL_NB; ++i) {
-    K.pw[i] *= is;
-    acc += FL_EPS + scale * K.pw[i];
-    K.xk[i + 1] = acc;
-  }
-  K.xk[FL_NB] = 1.f;
-  m = raw[FL_NB];
-#pragma unroll
-  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, raw[FL_NB + i]);
-  s = 0.f;
-#pragma unroll
-  for (int i = 0; i < FL_NB; ++i) {
-    K.ph[i] = expf(raw[FL_NB + i] - m);
-    s += K.ph[i];
-  }
-  is = 1.f / s;
-  acc = 0.f;
   K.yk[0] = 0.f;
 #pragma unroll
   for (int i = 0; i < FL_NB; ++i) {
-    K.ph[i] *= is;
-    acc += FL_EPS + scale * K.ph[i];
-    K.yk[i + 1] = acc;
+    K.pw[i] = ew[i] * iw;
+    K.ph[i] = eh[i] * ih;
+    cx = i == FL_NB - 1 ? 1.f : cx + knot_step(ew[i], iw);
+    cy = i == FL_NB - 1 ? 1.f : cy + knot_step(eh[i], ih);
+    K.xk[i + 1] = cx;
+    K.yk[i + 1] = cy;
   }
-  K.yk[FL_NB] = 1.f;
-  const float shift = 0.53974242f;  // log(expm1(1 - eps)) for eps = 1e-3: raw 0 gives derivative 1
   K.dk[0] = 1.f;
   K.dk[FL_NB] = 1.f;
 #pragma unroll
-  for (int i = 1; i < FL_NB; ++i) K.dk[i] = FL_EPS + softplusf(raw[2 * FL_NB + i - 1] + shift);
+  for (int i = 1; i < FL_NB; ++i) K.dk[i] = FL_EPS + softplus_f(raw[2 * FL_NB + i - 1] + FL_DSHIFT);
 }
 
-// bin of v among the knots t[1..15] (number of interior knots below v), clamped to [0, 15]
+// bin of x among the x knots 1..15 (number of them below x), and its numbers
 __device__ __forceinline__ int knot_bin(const float* t, float v) {
   int k = 0;
 #pragma unroll
@@ -131,49 +225,12 @@ __device__ __forceinline__ int knot_bin(const float* t, float v) {
   return k;
 }
 
-// the six numbers of bin k (selected with an unrolled loop so the knot arrays stay in registers)
-struct Bin {
-  float x0, x1, y0, y1, d0, d1;
-};
-
 __device__ __forceinline__ Bin pick_bin(const Knots& K, int k) {
   Bin b{K.xk[0], K.xk[1], K.yk[0], K.yk[1], K.dk[0], K.dk[1]};
 #pragma unroll
   for (int i = 1; i < FL_NB; ++i)
     if (i == k) b = Bin{K.xk[i], K.xk[i + 1], K.yk[i], K.yk[i + 1], K.dk[i], K.dk[i + 1]};
   return b;
-}
-
-__device__ __forceinline__ float rqs_fwd(const Knots& K, float x, float& ld) {
-  const Bin q = pick_bin(K, knot_bin(K.xk, x));
-  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
-  const float s = h / w;
-  const float xi = (x - q.x0) / w, t = xi * (1.f - xi);
-  const float den = s + (q.d1 + q.d0 - 2.f * s) * t;
-  const float y = q.y0 + h * (s * xi * xi + q.d0 * t) / den;
-  const float P = q.d1 * xi * xi + 2.f * s * t + q.d0 * (1.f - xi) * (1.f - xi);
-  ld = logf(s * s * P / (den * den));
-  return y;
-}
-
-__device__ __forceinline__ float rqs_inv(const Knots& K, float y, float& ld) {
-  const Bin q = pick_bin(K, knot_bin(K.yk, y));
-  const float w = q.x1 - q.x0, h = q.y1 - q.y0;
-  const float s = h / w;
-  const float dy = y - q.y0;
-  const float g = q.d1 + q.d0 - 2.f * s;
-  const float a = h * (s - q.d0) + dy * g;
-  const float b = h * q.d0 - dy * g;
-  const float c = -s * dy;
-  const float disc = fmaxf(b * b - 4.f * a * c, 0.f);
-  float xi = 2.f * c / (-b - sqrtf(disc));
-  xi = fminf(fmaxf(xi, 0.f), 1.f);
-  const float x = q.x0 + xi * w;
-  const float t = xi * (1.f - xi);
-  const float den = s + g * t;
-  const float P = q.d1 * xi * xi + 2.f * s * t + q.d0 * (1.f - xi) * (1.f - xi);
-  ld = logf(s * s * P / (den * den));
-  return x;
 }
 
 // reverse sweep of (y, log s') = spline(x; raw): given ybar and ldbar, returns xbar and
@@ -244,11 +301,10 @@ __device__ __forceinline__ float rqs_bwd(const float* raw, const Knots& K, float
     rawbar[FL_NB + i] = K.ph[i] * (hib[i] - doth);
   }
   // interior derivatives d_j = eps + softplus(raw_{32 + j - 1} + shift), j = 1..15
-  const float shift = 0.53974242f;
 #pragma unroll
   for (int j = 1; j < FL_NB; ++j) {
-    const float z = raw[2 * FL_NB + j - 1] + shift;
-    const float sig = 1.f / (1.f + expf(-z));
+    const float z = raw[2 * FL_NB + j - 1] + FL_DSHIFT;
+    const float sig = z > 20.f ? 1.f : frcp(1.f + fexp(-z));  // d softplus / dz (softplus_f is z above 20)
     const float db = (j == k ? d0b : 0.f) + (j == k + 1 ? d1b : 0.f);
     rawbar[2 * FL_NB + j - 1] = db * sig;
   }

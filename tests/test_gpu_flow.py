@@ -44,16 +44,18 @@ def points(torch, n, seed):
 
 
 def assert_rounding_noise(d, what):
-    """Bars for |library - bf16-emulating oracle| on log q or y.  The library
-    accumulates in binary32 (relative error ~1e-6 on each pre-activation), which
-    now and then sends an operand to the other bfloat16 neighbour (2^-8 relative)
-    and so moves the output by far more than the accumulation error itself.
-    Pushing relative noise of 1e-6 through the emulating oracle with the test's
-    parameters (output scale 0.3) gives median 6e-6, 90th percentile 3e-5, mean
-    1e-4 and maximum 1.3e-2 over 1000 points; the bars leave room above those.
-    A wrong operand layout or index moves the median to O(1)."""
+    """Bars for |library - emulating oracle| on log q or y.  The library accumulates
+    in binary32 (relative error ~1e-6 on each pre-activation), which now and then
+    sends a value to the other neighbour when it is rounded (bfloat16 activations,
+    2^-8 relative; binary16 spline parameters, 2^-11) and so moves the output by far
+    more than the accumulation error itself.  Pushing relative noise of 1e-6 through
+    the emulating oracle with the test's parameters (output scale 0.3) gives median
+    1.1e-5 to 1.4e-5, 90th percentile 5e-4 to 7e-4, mean 3e-4 and maximum 1.4e-2
+    over 1000 points; the bars leave room above those (and for the fast
+    single-precision exp and log of the splines).  A wrong operand layout or index
+    moves the median to O(1)."""
     q50, q90 = np.quantile(d, [0.5, 0.9])
-    assert q50 <= 2e-5 and q90 <= 1e-4 and d.mean() <= 5e-4 and d.max() <= 5e-2, \
+    assert q50 <= 5e-5 and q90 <= 2e-3 and d.mean() <= 1e-3 and d.max() <= 5e-2, \
         (what, q50, q90, d.mean(), d.max())
 
 
