@@ -71,7 +71,7 @@ __global__ void k_flow_init(float* master, uint64_t seed) {
 __device__ __forceinline__ void mlp_tile32(const float* __restrict__ m, const uint16_t* __restrict__ w,
                                            const float (*cond)[4], uint16_t* h1, uint16_t* h2, float* par) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  mlp_h1(m, cond, h1, FL_TILE);
+  mlp_h1(load_h1_unit(m), cond, h1, FL_TILE);
   __syncthreads();
   // h2: 2 row blocks x 8 column blocks; wave w owns column blocks 2w, 2w+1
   for (int rb = 0; rb < 2; ++rb)
@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__
     const int col = (3 * wave + cc) * 16 + (lane & 15);
     bias3[cc] = col < FL_NOUT ? m[FO_B3 + col] : 0.f;
   }
+  const H1Unit u1 = load_h1_unit(m);
   const int ri = lane & 15, kq = 4 * (lane >> 4);
   for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE_F; e0 < B;
        e0 += static_cast<int64_t>(gridDim.x) * FL_TILE_F) {
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__
       cond[e][c] = ev < B ? vin[ev * FL_NDIM + kFlowC[l][c]] : 0.5f;
     }
     __syncthreads();
-    mlp_h1(m, cond, h1, FL_TILE_F);
+    mlp_h1(u1, cond, h1, FL_TILE_F);
     __syncthreads();
 #pragma unroll
     for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
@@ -198,11 +199,15 @@ __global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__
 // ---------------------------------------------------------------------------
 // backward of one layer over a batch (one 32-event tile per block iteration)
 //   gout = dL/d(layer output) [B][8], glq = dL/d log q [B]  ->  gin = dL/d(layer input);
-//   stores H1, H2, DR (bf16 and fp32), DH2 (bf16 and fp32), DH1 (fp32), COND for the weight gradients
+//   stores H1, H2, DR (bf16 and fp32), DH2 (bf16 and fp32), DH1 (fp32), COND for the weight
+//   gradients, feature-major ([feature][ld], ld = the batch capacity rounded up to 32) so
+//   the contractions over events read contiguous runs; every row of the last tile is
+//   written, and the rows past the batch carry zero gradients
 // ---------------------------------------------------------------------------
 struct FlowBwdBufs {
   uint16_t *H1, *H2, *DRb, *DH2b;
   float *DRf, *DH2f, *DH1f, *COND;
+  int64_t ld;
 };
 
 __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict__ master,
@@ -224,18 +229,15 @@ __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict_
       const int64_t ev = e0 + e;
       const float v = ev < B ? vin[ev * FL_NDIM + kFlowC[l][c]] : 0.5f;
       cond[e][c] = v;
-      if (ev < B) s.COND[ev * 4 + c] = v;
+      s.COND[c * s.ld + ev] = v;
     }
     __syncthreads();
     mlp_tile32(m, w, cond, h1, h2, par);
     // activations of the tile for the weight gradients
     for (int i = tid; i < FL_TILE * FL_HID; i += blockDim.x) {
-      const int e = i / FL_HID, j = i % FL_HID;
-      const int64_t ev = e0 + e;
-      if (ev < B) {
-        s.H1[ev * FL_HID + j] = h1[e * FL_LDA + j];
-        s.H2[ev * FL_HID + j] = h2[e * FL_LDA + j];
-      }
+      const int e = i % FL_TILE, j = i / FL_TILE;
+      s.H1[j * s.ld + e0 + e] = h1[e * FL_LDA + j];
+      s.H2[j * s.ld + e0 + e] = h2[e * FL_LDA + j];
     }
     // spline reverse sweep: thread (event, transformed coordinate)
     if (tid < FL_TILE * 4) {
@@ -264,14 +266,11 @@ __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict_
     }
     __syncthreads();
     for (int i = tid; i < FL_TILE * FL_NOUTP; i += blockDim.x) {
-      const int e = i / FL_NOUTP, c = i % FL_NOUTP;
-      const int64_t ev = e0 + e;
+      const int e = i % FL_TILE, c = i / FL_TILE;
       const float g = par[e * FL_LDP + c];
       dpb[e * FL_LDP + c] = f2bf(g);
-      if (ev < B) {
-        s.DRb[ev * FL_NOUTP + c] = f2bf(g);
-        s.DRf[ev * FL_NOUTP + c] = g;
-      }
+      s.DRb[c * s.ld + e0 + e] = f2bf(g);
+      s.DRf[c * s.ld + e0 + e] = g;
     }
     __syncthreads();
     // dh2 = dp W3^T (mask h2 > 0): A = dpb [32][192], Bt = W3n [128 in][192 out]
@@ -296,11 +295,8 @@ __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict_
           const int row = rb * 16 + 4 * (lane >> 4) + j;
           const float g = dh2v[rb][cc][j];
           dpb[row * FL_LDA + col] = f2bf(g);
-          const int64_t ev = e0 + row;
-          if (ev < B) {
-            s.DH2b[ev * FL_HID + col] = f2bf(g);
-            s.DH2f[ev * FL_HID + col] = g;
-          }
+          s.DH2b[col * s.ld + e0 + row] = f2bf(g);
+          s.DH2f[col * s.ld + e0 + row] = g;
         }
       }
     __syncthreads();
@@ -315,8 +311,7 @@ __global__ __launch_bounds__(256) void k_flow_layer_bwd(const float* __restrict_
           const int row = rb * 16 + 4 * (lane >> 4) + j;
           const float g = bf2f(h1[row * FL_LDA + col]) > 0.f ? acc[j] : 0.f;
           par[row * FL_LDP + col] = g;
-          const int64_t ev = e0 + row;
-          if (ev < B) s.DH1f[ev * FL_HID + col] = g;
+          s.DH1f[col * s.ld + e0 + row] = g;
         }
       }
     __syncthreads();
@@ -348,53 +343,64 @@ constexpr int kWgPart = kWgTiles * 256 + kWgValu;   // floats per split
 constexpr int kWgMaxSplit = 64;
 constexpr int kWgBlocksX = (kWgTiles + (kWgValu + 63) / 64 + 3) / 4;
 
-__device__ __forceinline__ f32x4_t mfma_tn(const uint16_t* __restrict__ H, int ldh, const uint16_t* __restrict__ D,
-                                           int ldd, int m0, int n0, int64_t k_lo, int64_t k_hi, int lane) {
+// C(16x16 at m0, n0) = sum_k A[m][k] B[k][n] with A = Ht (feature-major [m][ld]) and
+// B = Dt ([n][ld]): lane l supplies Ht[m0 + l%16][k0 + 4(l/16) .. +3] and
+// Dt[n0 + l%16][k0 + 4(l/16) .. +3], one 8-byte load each
+__device__ __forceinline__ f32x4_t mfma_tn(const uint16_t* __restrict__ Ht, const uint16_t* __restrict__ Dt,
+                                           int64_t ld, int m0, int n0, int64_t k_lo, int64_t k_hi, int lane) {
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  const int ri = lane & 15, kq = 4 * (lane >> 4);
+  const uint16_t* ap = Ht + (m0 + (lane & 15)) * ld + 4 * (lane >> 4);
+  const uint16_t* bp = Dt + (n0 + (lane & 15)) * ld + 4 * (lane >> 4);
 #pragma unroll 4
   for (int64_t k0 = k_lo; k0 < k_hi; k0 += 16) {
-    bf16x4_t a, b;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t kk = k0 + kq + j;
-      a[j] = kk < k_hi ? static_cast<short>(H[kk * ldh + m0 + ri]) : static_cast<short>(0);
-      b[j] = kk < k_hi ? static_cast<short>(D[kk * ldd + n0 + ri]) : static_cast<short>(0);
-    }
+    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(ap + k0);
+    const bf16x4_t b = *reinterpret_cast<const bf16x4_t*>(bp + k0);
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_flow_wgrad_part(int64_t B, int kc, FlowBwdBufs s, float* part) {
+// sum over k in [k_lo, k_hi) (multiples of 4) of x[k] (y == nullptr) or x[k] y[k]
+__device__ __forceinline__ float dot_run(const float* __restrict__ x, const float* __restrict__ y, int64_t k_lo,
+                                         int64_t k_hi) {
+  float a = 0.f;
+#pragma unroll 4
+  for (int64_t k = k_lo; k < k_hi; k += 4) {
+    const float4 u = *reinterpret_cast<const float4*>(x + k);
+    if (y) {
+      const float4 v = *reinterpret_cast<const float4*>(y + k);
+      a += u.x * v.x + u.y * v.y + u.z * v.z + u.w * v.w;
+    } else {
+      a += u.x + u.y + u.z + u.w;
+    }
+  }
+  return a;
+}
+
+// k_hi is the batch rounded up to 16 (the padded rows hold zero gradients)
+__global__ __launch_bounds__(256) void k_flow_wgrad_part(int64_t Bp, int kc, FlowBwdBufs s, float* part) {
   const int lane = threadIdx.x & 63;
   const int wave_g = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t k_lo = static_cast<int64_t>(blockIdx.y) * kc;
-  const int64_t k_hi = k_lo + kc < B ? k_lo + kc : B;
+  const int64_t k_hi = k_lo + kc < Bp ? k_lo + kc : Bp;
   float* out = part + static_cast<int64_t>(blockIdx.y) * kWgPart;
   if (wave_g < 96) {
     const int mb = wave_g / 12, nb = wave_g % 12;
-    const f32x4_t acc = mfma_tn(s.H2, FL_HID, s.DRb, FL_NOUTP, mb * 16, nb * 16, k_lo, k_hi, lane);
+    const f32x4_t acc = mfma_tn(s.H2, s.DRb, s.ld, mb * 16, nb * 16, k_lo, k_hi, lane);
 #pragma unroll
     for (int j = 0; j < 4; ++j) out[wave_g * 256 + lane * 4 + j] = acc[j];
   } else if (wave_g < kWgTiles) {
     const int t = wave_g - 96, mb = t / 8, nb = t % 8;
-    const f32x4_t acc = mfma_tn(s.H1, FL_HID, s.DH2b, FL_HID, mb * 16, nb * 16, k_lo, k_hi, lane);
+    const f32x4_t acc = mfma_tn(s.H1, s.DH2b, s.ld, mb * 16, nb * 16, k_lo, k_hi, lane);
 #pragma unroll
     for (int j = 0; j < 4; ++j) out[wave_g * 256 + lane * 4 + j] = acc[j];
   } else {
     const int t = (wave_g - kWgTiles) * 64 + lane;
     float a = 0.f;
-    if (t < 512) {
-      const int c = t / FL_HID, n = t % FL_HID;
-      for (int64_t b = k_lo; b < k_hi; ++b) a += s.COND[b * 4 + c] * s.DH1f[b * FL_HID + n];
-    } else if (t < 640) {
-      for (int64_t b = k_lo; b < k_hi; ++b) a += s.DH1f[b * FL_HID + (t - 512)];
-    } else if (t < 768) {
-      for (int64_t b = k_lo; b < k_hi; ++b) a += s.DH2f[b * FL_HID + (t - 640)];
-    } else if (t < kWgValu) {
-      for (int64_t b = k_lo; b < k_hi; ++b) a += s.DRf[b * FL_NOUTP + (t - 768)];
-    }
+    if (t < 512) a = dot_run(s.COND + (t / FL_HID) * s.ld, s.DH1f + (t % FL_HID) * s.ld, k_lo, k_hi);
+    else if (t < 640) a = dot_run(s.DH1f + (t - 512) * s.ld, nullptr, k_lo, k_hi);
+    else if (t < 768) a = dot_run(s.DH2f + (t - 640) * s.ld, nullptr, k_lo, k_hi);
+    else if (t < kWgValu) a = dot_run(s.DRf + (t - 768) * s.ld, nullptr, k_lo, k_hi);
     if (t < kWgValu) out[kWgTiles * 256 + t] = a;
   }
 }
@@ -588,10 +594,11 @@ int flow_backward(vegas_flow_state* f, const double* w, int64_t B, double* loss_
     hipLaunchKernelGGL(k_flow_layer_bwd, dim3(grid_for(B, FL_TILE, 4096)), dim3(256), 0, f->stream, f->master, f->wb,
                        l, f->V + l * stride, gout, gin, f->glq, B, f->bw);
     VF_HIP(hipGetLastError());
+    const int64_t Bp = (B + 15) / 16 * 16;  // rows past B (written by the backward) hold zero gradients
     int kc = 256;
-    if ((B + kc - 1) / kc > kWgMaxSplit) kc = static_cast<int>(((B + kWgMaxSplit - 1) / kWgMaxSplit + 15) / 16 * 16);
-    const int nsplit = static_cast<int>((B + kc - 1) / kc);
-    hipLaunchKernelGGL(k_flow_wgrad_part, dim3(kWgBlocksX, nsplit), dim3(256), 0, f->stream, B, kc, f->bw, f->wpart);
+    if ((Bp + kc - 1) / kc > kWgMaxSplit) kc = static_cast<int>(((Bp + kWgMaxSplit - 1) / kWgMaxSplit + 15) / 16 * 16);
+    const int nsplit = static_cast<int>((Bp + kc - 1) / kc);
+    hipLaunchKernelGGL(k_flow_wgrad_part, dim3(kWgBlocksX, nsplit), dim3(256), 0, f->stream, Bp, kc, f->bw, f->wpart);
     VF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_flow_wgrad_sum, dim3((kWgPart + 255) / 256), dim3(256), 0, f->stream, nsplit, f->wpart,
                        f->grad + l * FL_LAYER);
@@ -634,9 +641,10 @@ int vegas_flow_create(int32_t max_batch, int64_t max_sample, uint64_t seed, void
   const size_t o_V = take(4 * 7 * Bm * FL_NDIM), o_G = take(4 * 2 * Bm * FL_NDIM);
   const size_t o_logq = take(4 * Bm), o_glq = take(4 * Bm), o_yb = take(4 * Bm * FL_NDIM), o_wbat = take(8 * Bm);
   const size_t o_scal = take(8 * 4);
-  const size_t o_H1 = take(2 * Bm * FL_HID), o_H2 = take(2 * Bm * FL_HID), o_DRb = take(2 * Bm * FL_NOUTP);
-  const size_t o_DH2b = take(2 * Bm * FL_HID), o_DRf = take(4 * Bm * FL_NOUTP), o_DH2f = take(4 * Bm * FL_HID);
-  const size_t o_DH1f = take(4 * Bm * FL_HID), o_COND = take(4 * Bm * 4);
+  const size_t Bl = (Bm + FL_TILE - 1) / FL_TILE * FL_TILE;  // row stride of the feature-major buffers
+  const size_t o_H1 = take(2 * Bl * FL_HID), o_H2 = take(2 * Bl * FL_HID), o_DRb = take(2 * Bl * FL_NOUTP);
+  const size_t o_DH2b = take(2 * Bl * FL_HID), o_DRf = take(4 * Bl * FL_NOUTP), o_DH2f = take(4 * Bl * FL_HID);
+  const size_t o_DH1f = take(4 * Bl * FL_HID), o_COND = take(4 * Bl * 4);
   const size_t o_zs = take(4 * S * FL_NDIM), o_lqs = take(4 * S);
   const size_t o_wpart = take(4 * static_cast<size_t>(kWgMaxSplit) * kWgPart);
   if (hipMalloc(&f->mem, off) != hipSuccess) {
@@ -664,6 +672,7 @@ int vegas_flow_create(int32_t max_batch, int64_t max_sample, uint64_t seed, void
   f->bw.DH2f = reinterpret_cast<float*>(b + o_DH2f);
   f->bw.DH1f = reinterpret_cast<float*>(b + o_DH1f);
   f->bw.COND = reinterpret_cast<float*>(b + o_COND);
+  f->bw.ld = static_cast<int64_t>(Bl);
   f->zs = reinterpret_cast<float*>(b + o_zs);
   f->lqs = reinterpret_cast<float*>(b + o_lqs);
   f->wpart = reinterpret_cast<float*>(b + o_wpart);

@@ -57,14 +57,25 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(stati
 // spline parameters are rounded to binary16 (round to nearest even) in both directions
 __device__ __forceinline__ float round_h(float x) { return static_cast<float>(static_cast<_Float16>(x)); }
 
-// first MLP layer of `rows` events (cond [rows][4] in LDS) -> h1 (bf16, LDS, stride
-// FL_LDA), by the whole block; explicit fma order so every kernel gets the same bits
-__device__ __forceinline__ void mlp_h1(const float* __restrict__ m, const float (*cond)[4], uint16_t* h1, int rows) {
-  for (int i = threadIdx.x; i < rows * FL_HID; i += blockDim.x) {
-    const int e = i / FL_HID, j = i % FL_HID;
-    float a = m[FO_B1 + j];
+// first MLP layer: thread t of a block (blockDim a multiple of 128) owns hidden unit
+// j = t % 128, whose bias and four weights it keeps in registers
+struct H1Unit {
+  float b, w[4];
+};
+
+__device__ __forceinline__ H1Unit load_h1_unit(const float* __restrict__ m) {
+  const int j = threadIdx.x % FL_HID;
+  return H1Unit{m[FO_B1 + j], {m[FO_W1 + j], m[FO_W1 + FL_HID + j], m[FO_W1 + 2 * FL_HID + j], m[FO_W1 + 3 * FL_HID + j]}};
+}
+
+// h1 of `rows` events (cond [rows][4] in LDS) -> bf16 in LDS (stride FL_LDA), by the whole
+// block; explicit fma order so every kernel gets the same bits
+__device__ __forceinline__ void mlp_h1(const H1Unit& u, const float (*cond)[4], uint16_t* h1, int rows) {
+  const int j = threadIdx.x % FL_HID;
+  for (int e = threadIdx.x / FL_HID; e < rows; e += blockDim.x / FL_HID) {
+    float a = u.b;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a = __fmaf_rn(cond[e][c], m[FO_W1 + c * FL_HID + j], a);
+    for (int c = 0; c < 4; ++c) a = __fmaf_rn(cond[e][c], u.w[c], a);
     h1[e * FL_LDA + j] = f2bf(fmaxf(a, 0.f));
   }
 }
