@@ -19,10 +19,11 @@ struct u32x4 {
 __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32 gives both halves)
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    const uint32_t lo0 = static_cast<uint32_t>(p0), hi0 = static_cast<uint32_t>(p0 >> 32);
+    const uint32_t lo1 = static_cast<uint32_t>(p1), hi1 = static_cast<uint32_t>(p1 >> 32);
     c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
@@ -30,10 +31,10 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
-// (hi:lo) -> odd multiple of 2^-53 in (0,1): top 52 bits w, value (2w+1) 2^-53 (exact)
+// (hi:lo) -> odd multiple of 2^-53 in (0,1): top 52 bits w, value (2w+1) 2^-53, formed
+// as hi 2^-32 + (lo >> 12) 2^-52 + 2^-53 -- disjoint bit ranges, so both fmas are exact
 __device__ __forceinline__ double words_to_unit(uint32_t hi, uint32_t lo) {
-  const uint64_t w = ((static_cast<uint64_t>(hi) << 32) | lo) >> 12;
-  return static_cast<double>(2 * w + 1) * 0x1p-53;
+  return __fma_rn(static_cast<double>(hi), 0x1p-32, __fma_rn(static_cast<double>(lo >> 12), 0x1p-52, 0x1p-53));
 }
 
 // ndim uniforms of event `ev` in iteration `it`; call k fills u[2k], u[2k+1]
