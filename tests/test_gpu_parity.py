@@ -46,7 +46,14 @@ def cases():
     for fam in (1, 2, 3, 4, 5, 6):
         out.append((f"genz{fam}", dict(process=W.GENZ, ndim=5, nbins=40, seed=9, alpha=1.5,
                                        params=W.genz_params(fam, 5, seed=fam, difficulty=6.0))))
+    out.append(("gauss16x255", GAUSS_MAX))
     return out
+
+
+# the largest grid (16 dimensions x 255 bins): its digit histogram (98 KB) exceeds one
+# block's LDS, so every iteration folds from the records with the dimensions split
+# over blocks
+GAUSS_MAX = dict(process=W.GAUSS, ndim=16, nbins=255, seed=5, alpha=1.5, params=[0.5, 0.3])
 
 
 def compare_weights(wg, wo, tag):
@@ -133,11 +140,13 @@ def run_schedule(P, cfg, n, n_iter, **launch):
     return b"".join(blobs)
 
 
-@pytest.mark.parametrize("name", ["w_plus", "ww_4l", "genz2"])
+@pytest.mark.parametrize("name", ["w_plus", "ww_4l", "genz2", "gauss16x255"])
 def test_bit_identical_across_launch_configurations(P, name):
     if name == "genz2":
         cfg = dict(process=W.GENZ, ndim=5, nbins=40, seed=9, alpha=1.5,
                    params=W.genz_params(2, 5, seed=2, difficulty=6.0))
+    elif name == "gauss16x255":
+        cfg = GAUSS_MAX
     else:
         cfg = W.config(name)
     n = 50_021 if name != "ww_4l" else 20_011
