@@ -44,7 +44,8 @@ constexpr int kMaxRowsAcc = 1024;       // cap on accumulation blocks (rows of t
 constexpr int kFusedLdsMax = 48 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
 
 struct DevBufs {
-  double* edges;                 // [D][n+1]
+  double* edges;                 // [D][n+1] current grid
+  double* edges_alt;             // [D][n+1] the grid refined speculatively by k_finalize
   double* rec_w;                 // [maxN]
   uint32_t* rec_bins;            // [ceil(D/4)][maxN], 4 bins of 8 bits per word
   unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max, cleared by k_finalize)
@@ -345,9 +346,15 @@ struct FinArgs {
   int ndim, nbins;
   uint32_t iter;
   int fused;
+  int spec;      // also refine the grid into b.edges_alt (waves 0..D-1, one dimension each)
+  int fold_lds;  // bytes of dynamic LDS before the refinement scratch (the re-fold's digits)
+  double alpha;
 };
 
-__device__ void finalize_block(const FinArgs& f, unsigned char* smem) {
+__device__ __forceinline__ void refine_dim(bool active, int n, double alpha, const double* hist, const double* e_in, double* e_out,
+                           double* sm);
+
+__device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* smem) {
   __shared__ double s12[2];
   const DevBufs& b = f.b;
   const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol = 3 * (2 + nslot);
@@ -414,6 +421,16 @@ __device__ void finalize_block(const FinArgs& f, unsigned char* smem) {
     b.cnt[0] = 0ull;
     b.cnt[1] = 0ull;
   }
+  if (f.spec) {
+    // the refinement vegas_refine would compute from this histogram, so that it only
+    // has to swap the grid buffers (the same routine as k_refine: the same bits)
+    __syncthreads();  // b.hist of every slot written by this block
+    const int d = threadIdx.x >> 6;
+    const bool active = d < nd;
+    double* sm = reinterpret_cast<double*>(smem + f.fold_lds) + (active ? d : 0) * 4 * (n + 1);
+    refine_dim(active, n, f.alpha, b.hist + (active ? d : 0) * n, b.edges + (active ? d : 0) * (n + 1),
+               b.edges_alt + (active ? d : 0) * (n + 1), sm);
+  }
 }
 
 // column sums of the per-block partial rows: block (x, y) covers 32 columns and rows
@@ -451,75 +468,104 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
-__global__ void k_refine(DevBufs b, int nbins, double alpha) {
-  __shared__ double hs[VEGAS_MAX_BINS + 1];   // histogram of this dimension
-  __shared__ double dm[VEGAS_MAX_BINS + 1];   // smoothed histogram, then damped importance m
-  __shared__ double cm[VEGAS_MAX_BINS + 1];   // cumulative importance: cm[k] = m_0 + ... + m_{k-1}
-  __shared__ double eo[VEGAS_MAX_BINS + 1];   // old edges
-  const int d = blockIdx.x, lane = threadIdx.x;
-  const int n = nbins;
-  double* e = b.edges + d * (n + 1);
-  for (int k = lane; k < n; k += kWave) hs[k] = b.hist[d * n + k];
-  for (int k = lane; k <= n; k += kWave) eo[k] = e[k];
+// Refinement of dimension d by one wave (lane = threadIdx.x % 64) with LDS scratch
+// sm[4 (n + 1)]; every wave of the block calls it the same number of times (its
+// barriers are block-wide); active == false only keeps the barriers.  Reads the
+// histogram hist[n] and edges e_in[n + 1], writes e_out[n + 1] (may equal e_in).
+// An empty histogram keeps the dimension's grid.
+__device__ __forceinline__ void refine_dim(bool active, int n, double alpha, const double* hist, const double* e_in, double* e_out,
+                           double* sm) {
+  double* hs = sm;               // histogram of this dimension
+  double* dm = sm + (n + 1);     // smoothed histogram, then damped importance m
+  double* cm = sm + 2 * (n + 1); // cumulative importance: cm[k] = m_0 + ... + m_{k-1}
+  double* eo = sm + 3 * (n + 1); // old edges
+  const int lane = threadIdx.x & 63;
+  if (active) {
+    for (int k = lane; k < n; k += kWave) hs[k] = hist[k];
+    for (int k = lane; k <= n; k += kWave) eo[k] = e_in[k];
+  }
   __syncthreads();
   double s = 0.0, sb = 0.0;
-  for (int k = lane; k < n; k += kWave) {
-    double v;
-    if (k == 0) v = (hs[0] + hs[1]) / 2.0;
-    else if (k == n - 1) v = (hs[n - 2] + hs[n - 1]) / 2.0;
-    else v = (hs[k - 1] + hs[k] + hs[k + 1]) / 3.0;
-    dm[k] = v;
-    s += hs[k];
-    sb += v;
-  }
+  if (active)
+    for (int k = lane; k < n; k += kWave) {
+      double v;
+      if (k == 0) v = (hs[0] + hs[1]) / 2.0;
+      else if (k == n - 1) v = (hs[n - 2] + hs[n - 1]) / 2.0;
+      else v = (hs[k - 1] + hs[k] + hs[k + 1]) / 3.0;
+      dm[k] = v;
+      s += hs[k];
+      sb += v;
+    }
   s = wave_sum_f64(s);
   sb = wave_sum_f64(sb);
-  if (!(s > 0.0)) return;  // whole block: an empty histogram keeps this dimension's grid
+  const bool work = active && s > 0.0;  // wave-uniform
   __syncthreads();
-  for (int k = lane; k < n; k += kWave) {
-    const double r = dm[k] / sb;
-    double m;
-    if (r == 0.0) m = 0.0;
-    else if (r == 1.0) m = 1.0;
-    else m = pow((r - 1.0) / log(r), alpha);
-    dm[k] = m;
-  }
-  __syncthreads();
-  // inclusive prefix sums: lane l sums bins [4l, 4l+4) in order, then a wave scan
-  double part = 0.0;
-  for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) part += dm[k];
-  double incl = part;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const double o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
-  }
-  double run = incl - part;  // exclusive prefix of this lane's chunk
-  if (lane == 0) cm[0] = 0.0;
-  for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) {
-    run += dm[k];
-    cm[k + 1] = run;
-  }
-  __syncthreads();
-  const double stp = cm[n] / n;
-  // new interior edge k sits in the old bin j with cm[j] < k*stp <= cm[j+1]
-  for (int k = 1 + lane; k < n; k += kWave) {
-    const double target = k * stp;
-    int lo = 0, hi = n - 1;  // largest j in [0, n-1] with cm[j] < target
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (cm[mid] < target) lo = mid;
-      else hi = mid - 1;
+  if (work) {
+    const double isb = 1.0 / sb;
+    for (int k = lane; k < n; k += kWave) {
+      const double r = dm[k] * isb;
+      double m;
+      if (r == 0.0) {
+        m = 0.0;
+      } else if (r == 1.0) {
+        m = 1.0;
+      } else {
+        const double y = (r - 1.0) / log(r);
+        m = alpha == 1.5 ? y * sqrt(y) : pow(y, alpha);  // the usual damping exponent without pow
+      }
+      dm[k] = m;
     }
-    const int j = lo;
-    double frac = dm[j] > 0.0 ? (target - cm[j]) / dm[j] : 0.0;
-    frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
-    e[k] = eo[j] + frac * (eo[j + 1] - eo[j]);
   }
-  if (lane == 0) {
-    e[0] = 0.0;
-    e[n] = 1.0;
+  __syncthreads();
+  if (work) {
+    // inclusive prefix sums: lane l sums bins [4l, 4l+4) in order, then a wave scan
+    double part = 0.0;
+    for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) part += dm[k];
+    double incl = part;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    double run = incl - part;  // exclusive prefix of this lane's chunk
+    if (lane == 0) cm[0] = 0.0;
+    for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) {
+      run += dm[k];
+      cm[k + 1] = run;
+    }
   }
+  __syncthreads();
+  if (work) {
+    const double stp = cm[n] / n;
+    // new interior edge k sits in the old bin j with cm[j] < k*stp <= cm[j+1]
+    for (int k = 1 + lane; k < n; k += kWave) {
+      const double target = k * stp;
+      int lo = 0, hi = n - 1;  // largest j in [0, n-1] with cm[j] < target
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cm[mid] < target) lo = mid;
+        else hi = mid - 1;
+      }
+      const int j = lo;
+      double frac = dm[j] > 0.0 ? (target - cm[j]) / dm[j] : 0.0;
+      frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+      e_out[k] = eo[j] + frac * (eo[j + 1] - eo[j]);
+    }
+    if (lane == 0) {
+      e_out[0] = 0.0;
+      e_out[n] = 1.0;
+    }
+  } else if (active && e_out != e_in) {
+    for (int k = lane; k <= n; k += kWave) e_out[k] = eo[k];
+  }
+}
+
+// one 64-lane block per dimension, in place
+__global__ void k_refine(DevBufs b, int nbins, double alpha) {
+  extern __shared__ unsigned char smem[];
+  const int d = blockIdx.x, n = nbins;
+  double* e = b.edges + d * (n + 1);
+  refine_dim(true, n, alpha, b.hist + d * n, e, e, reinterpret_cast<double*>(smem));
 }
 
 // ---------------------------------------------------------------------------
@@ -596,7 +642,7 @@ namespace {
 thread_local std::string g_last_hip_error;
 
 struct Layout {
-  size_t edges, rec_w, rec_bins, maxw, cnt, fxs, part_acc, acc_tot, hist, history, iter_out, result, total;
+  size_t edges, edges_alt, rec_w, rec_bins, maxw, cnt, fxs, part_acc, acc_tot, hist, history, iter_out, result, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -611,6 +657,7 @@ Layout make_layout(int D, int n, int64_t maxN) {
   };
   const int words = (D + 3) / 4;
   L.edges = take(sizeof(double) * D * (n + 1));
+  L.edges_alt = take(sizeof(double) * D * (n + 1));
   L.rec_w = take(sizeof(double) * maxN);
   L.rec_bins = take(sizeof(uint32_t) * words * maxN);
   L.maxw = take(sizeof(unsigned long long) * 2);
@@ -788,6 +835,9 @@ struct vegas_state {
   int event_lds, acc_lds, fused_lds, fin_lds;
   int acc_dpg, acc_groups;      // histogram dimensions per k_accum block, and blocks along y
   bool fused_ok;                // the fused fold fits in LDS for this configuration
+  bool spec_ok;                 // the finalisation can also refine (scratch fits, D <= 16)
+  bool spec_ready;              // b.edges_alt holds the refinement of the current grid and histogram
+  int refine_lds;               // LDS of the refinement scratch: D * 4 (n + 1) doubles
   bool scale_valid;             // the device holds scales from a previous iteration (b.fxs)
   int ncu, occ_event, occ_event_fused, occ_acc;  // CUs, and resident 256-thread blocks per CU
   // optional per-stage kernel timing with HIP events on the handle's stream
@@ -1023,6 +1073,7 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   }
   char* B = static_cast<char*>(h->base);
   h->b.edges = reinterpret_cast<double*>(B + L.edges);
+  h->b.edges_alt = reinterpret_cast<double*>(B + L.edges_alt);
   h->b.rec_w = reinterpret_cast<double*>(B + L.rec_w);
   h->b.rec_bins = reinterpret_cast<uint32_t*>(B + L.rec_bins);
   h->b.maxw = reinterpret_cast<unsigned long long*>(B + L.maxw);
@@ -1053,6 +1104,8 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
     h->fused_lds = h->event_lds + full;
     h->fused_ok = h->fused_lds <= kFusedLdsMax;
     h->fin_lds = h->fused_ok ? full : 0;
+    h->refine_lds = static_cast<int>(sizeof(double) * 4 * D * (n + 1));
+    h->spec_ok = D <= 16 && h->fin_lds + h->refine_lds <= static_cast<int>(smem);
     h->occ_event = occupancy_event(h, false);
     h->occ_event_fused = h->fused_ok ? occupancy_event(h, true) : 1;
     int nb = 0;
@@ -1194,6 +1247,9 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     fa.nbins = h->n;
     fa.iter = h->iter;
     fa.fused = fused ? 1 : 0;
+    fa.spec = (h->spec_ok && !ext_y) ? 1 : 0;
+    fa.fold_lds = fused ? h->fin_lds : 0;
+    fa.alpha = h->cfg.alpha;
     {
       TimedLaunch t(h, 2);
       hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
@@ -1201,9 +1257,10 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
       VG_HIP(t.done());
     }
     TimedLaunch t(h, 2);
-    hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused ? 1024 : 256), fused ? h->fin_lds : 0, h->stream, t.e0,
-                          t.e1, 0, fa);
+    hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused || fa.spec ? 1024 : 256),
+                          fa.fold_lds + (fa.spec ? h->refine_lds : 0), h->stream, t.e0, t.e1, 0, fa);
     VG_HIP(t.done());
+    h->spec_ready = fa.spec != 0;
   }
   h->scale_valid = true;
   const uint32_t j = h->iter;
@@ -1264,9 +1321,16 @@ int vegas_export(vegas_handle h, int64_t first, int64_t n, float* y_dev, double*
 int vegas_refine(vegas_handle h) {
   if (!h) return VEGAS_EINVAL;
   if (!h->have_hist) return VEGAS_ESTATE;
-  TimedLaunch t(h, 3);
-  hipExtLaunchKernelGGL(k_refine, dim3(h->D), dim3(kWave), 0, h->stream, t.e0, t.e1, 0, h->b, h->n, h->cfg.alpha);
-  VG_HIP(t.done());
+  if (h->spec_ready) {
+    // the finalisation already refined this grid from this histogram: swap buffers
+    std::swap(h->b.edges, h->b.edges_alt);
+  } else {
+    TimedLaunch t(h, 3);
+    hipExtLaunchKernelGGL(k_refine, dim3(h->D), dim3(kWave), sizeof(double) * 4 * (h->n + 1), h->stream, t.e0,
+                          t.e1, 0, h->b, h->n, h->cfg.alpha);
+    VG_HIP(t.done());
+  }
+  h->spec_ready = false;
   h->have_hist = false;
   return VEGAS_OK;
 }
@@ -1306,6 +1370,7 @@ int vegas_set_grid(vegas_handle h, const double* edges) {
   VG_HIP(hipMemcpyAsync(h->b.edges, edges, sizeof(double) * h->D * (n + 1), hipMemcpyHostToDevice,
                         h->stream));
   VG_HIP(hipStreamSynchronize(h->stream));
+  h->spec_ready = false;  // a refinement must start from the new grid
   return VEGAS_OK;
 }
 
@@ -1460,6 +1525,7 @@ int vegas_set_state(vegas_handle h, const void* buf, size_t bytes) {
   VG_HIP(hipMemcpyAsync(h->b.fxs, hd.fxs, sizeof(hd.fxs), hipMemcpyHostToDevice, h->stream));
   VG_HIP(hipStreamSynchronize(h->stream));
   h->scale_valid = hd.fxs[0] == 1;
+  h->spec_ready = false;
   h->iter = hd.iter;
   h->any_iter = hd.iter > 0;
   h->have_hist = false;

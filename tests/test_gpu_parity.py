@@ -221,6 +221,25 @@ def test_fold_modes(P):
     assert np.max(np.abs(d1[m] / d0[m] - 1)) < 1e-13
 
 
+@pytest.mark.parametrize("name", ["w_plus", "ww_4l", "gauss16x255"])
+def test_refinement_in_finalisation_equals_refine_kernel(P, name):
+    """The finalisation refines the grid from the histogram it just formed (when
+    the scratch fits), and vegas_refine then only swaps grid buffers; after
+    set_grid the refinement runs as its own kernel.  Both give the same bytes."""
+    cfg = GAUSS_MAX if name == "gauss16x255" else W.config(name)
+    n = 30_011
+    mk = lambda: P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                              cfg["params"], max_events=n)
+    a, b = mk(), mk()
+    for it in range(3):
+        a.iterate(n)
+        b.iterate(n)
+        b.set_grid(b.get_grid())   # same grid, but forces the separate refinement kernel
+        a.refine()
+        b.refine()
+        assert np.array_equal(a.get_grid(), b.get_grid()), (name, it)
+
+
 def test_histogram_sums_and_zero_weight_edge_cases(P):
     cfg = W.config("w_plus")
     g = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=1000)
