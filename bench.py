@@ -30,9 +30,9 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 466.0, "f32": 0.0, "traffic": 19_724_698, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1495.5, "f32": 0.0, "traffic": 171_619_942, "events": 10_000_000},
-    ("ww_4l", "fp32me"): {"f64": 835.5, "f32": 606.0, "traffic": 170_322_330, "events": 10_000_000},
+    ("w_plus", "fp64"): {"f64": 478.0, "f32": 0.0, "traffic": 19_732_086, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_609_255, "events": 10_000_000},
+    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_332_816, "events": 10_000_000},
 }
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 157.3
