@@ -23,6 +23,8 @@ struct PhysConst {
   double M2, MG, invMG, rho_lo, rho_rng, m2lo, tlo;
   double invS;                // 1 / S (hadronic)
   double pdfA, pdfa, pdfb;
+  int pdf_pow;                // 1: a = a2/2 with integer a2 in [-8, 8] and integer b in [0, 16]
+  int pdf_a2, pdf_b;
   // Drell-Yan: Q_q Q_l and chiral Z couplings g[q][h] * g_l[h'] products
   double qql[2];              // Q_q * Q_l for q = u, d
   double gg[2][4];            // g_q,h g_l,h' for (h,h') = LL, LR, RL, RR
@@ -60,6 +62,30 @@ __device__ __forceinline__ double bw_map(double r, double M2, double MG, double 
   const double dm = m2 - M2;
   jac = rrng * (dm * dm + MG * MG) * invMG;
   return m2;
+}
+
+// ---------------------------------------------------------------------------
+// product of the two parton densities, f(x1) f(x2) = A^2 tau^a ((1-x1)(1-x2))^b with
+// tau = x1 x2, L = ln tau and P = (1-x1)(1-x2) (> 0).  For half-integer a and integer
+// b (the usual parametrisations) the powers are products, square roots and one
+// reciprocal; otherwise exp(a L + b ln P).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ipow_pos(double v, int k) {  // v^k, 0 <= k <= 16
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= v;
+  return r;
+}
+
+__device__ __forceinline__ double pdf_pair(const PhysConst& c, double tau, double L, double P) {
+  if (c.pdf_pow) {
+    const int a2 = c.pdf_a2;
+    const int ka = (a2 >= 0 ? a2 : -a2) >> 1;   // |a| rounded down
+    double ta = ipow_pos(tau, ka);
+    if (a2 & 1) ta *= sqrt(tau);
+    if (a2 < 0) ta = 1.0 / ta;
+    return c.pdfA * c.pdfA * ta * ipow_pos(P, c.pdf_b);
+  }
+  return c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(P));
 }
 
 // ---------------------------------------------------------------------------
@@ -137,9 +163,8 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
     l2 = L - l1;
   }
   const double jtau = -L * c.invS;
-  // f(x1) f(x2) = A^2 exp(a ln(x1 x2) + b ln((1-x1)(1-x2))), ln(x1 x2) = ln tau,
-  // 1 - x = -expm1(ln x)
-  const double ff = c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(expm1(l1) * expm1(l2)));
+  // f(x1) f(x2) with tau = x1 x2 = m2 / S and 1 - x = -expm1(ln x)
+  const double ff = pdf_pair(c, m2 * c.invS, L, expm1(l1) * expm1(l2));
   const double cs = 2.0 * x[2] - 1.0;
   // 1 / (shat - MZ^2 + i MZ GZ)
   const double ds = m2 - c.mz2;
@@ -189,7 +214,7 @@ __device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
   const double den = ds * ds + c.MG * c.MG;
   // |M|^2 / (2 shat) = g^4 |V|^2 / 24 * shat^2 (1 + cos^2) / den / (2 shat): one division
   const double me_flux = c.g4v2_24 * (0.5 * m2) * (1.0 + cs * cs) / den;
-  const double ff = c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(em1 * em2));
+  const double ff = pdf_pair(c, m2 * c.invS, L, em1 * em2);
   // conv * J_bw * J_tau * |M|^2 / (2 shat) * (2 * 2 pi)/(32 pi^2)
   return c.conv * jbw * jtau * (1.0 / (8.0 * kPi)) * ff * me_flux;
 }

@@ -745,6 +745,14 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
   k.pdfA = p[VEGAS_P_PDF_A];
   k.pdfa = p[VEGAS_P_PDF_a];
   k.pdfb = p[VEGAS_P_PDF_b];
+  {
+    const double a2 = 2.0 * k.pdfa;
+    const bool a_ok = a2 == std::floor(a2) && std::fabs(a2) <= 8.0;
+    const bool b_ok = k.pdfb == std::floor(k.pdfb) && k.pdfb >= 0.0 && k.pdfb <= 16.0;
+    k.pdf_pow = a_ok && b_ok ? 1 : 0;
+    k.pdf_a2 = a_ok ? static_cast<int>(a2) : 0;
+    k.pdf_b = b_ok ? static_cast<int>(k.pdfb) : 0;
+  }
   k.invS = 1.0 / (rs * rs);
   k.e4 = e2 * e2;
   k.s_ee = rs * rs;
