@@ -351,8 +351,8 @@ struct FinArgs {
   double alpha;
 };
 
-__device__ __forceinline__ void refine_dim(bool active, int n, double alpha, const double* hist, const double* e_in, double* e_out,
-                           double* sm);
+__device__ __forceinline__ void refine_dim(bool active, bool preloaded, int n, double alpha, const double* hist,
+                                           const double* e_in, double* e_out, double* sm);
 
 __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* smem) {
   __shared__ double s12[2];
@@ -372,6 +372,10 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
       E2 = b.fxs[2];
     }
   }
+  double* rsm = reinterpret_cast<double*>(smem + f.fold_lds);  // refinement scratch [D][4 (n + 1)]
+  if (f.spec)  // the grid the refinement starts from, loaded while the totals are converted
+    for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x)
+      rsm[(i / (n + 1)) * 4 * (n + 1) + 3 * (n + 1) + i % (n + 1)] = b.edges[i];
   const long long* tot = b.acc_tot;
   if (fold == 2) {  // block-uniform
     long long* acc = reinterpret_cast<long long*>(smem);
@@ -399,6 +403,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     const int h = slot < 2 ? nslot + slot : slot - 2;
     b.hist[h] = v;
     if (slot < 2) s12[slot] = v;
+    else if (f.spec) rsm[(h / n) * 4 * (n + 1) + h % n] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -424,12 +429,12 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
   if (f.spec) {
     // the refinement vegas_refine would compute from this histogram, so that it only
     // has to swap the grid buffers (the same routine as k_refine: the same bits)
-    __syncthreads();  // b.hist of every slot written by this block
+    // (the histogram and the old grid are already in the scratch; refine_dim's first
+    // barrier orders those LDS writes before its reads)
     const int d = threadIdx.x >> 6;
     const bool active = d < nd;
-    double* sm = reinterpret_cast<double*>(smem + f.fold_lds) + (active ? d : 0) * 4 * (n + 1);
-    refine_dim(active, n, f.alpha, b.hist + (active ? d : 0) * n, b.edges + (active ? d : 0) * (n + 1),
-               b.edges_alt + (active ? d : 0) * (n + 1), sm);
+    refine_dim(active, true, n, f.alpha, nullptr, nullptr, b.edges_alt + (active ? d : 0) * (n + 1),
+               rsm + (active ? d : 0) * 4 * (n + 1));
   }
 }
 
@@ -471,16 +476,17 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // Refinement of dimension d by one wave (lane = threadIdx.x % 64) with LDS scratch
 // sm[4 (n + 1)]; every wave of the block calls it the same number of times (its
 // barriers are block-wide); active == false only keeps the barriers.  Reads the
-// histogram hist[n] and edges e_in[n + 1], writes e_out[n + 1] (may equal e_in).
-// An empty histogram keeps the dimension's grid.
-__device__ __forceinline__ void refine_dim(bool active, int n, double alpha, const double* hist, const double* e_in, double* e_out,
-                           double* sm) {
+// histogram hist[n] and edges e_in[n + 1] (or finds them already in sm[0..n) and
+// sm[3 (n + 1) ..] when preloaded), writes e_out[n + 1] (may equal e_in).  An empty
+// histogram keeps the dimension's grid.
+__device__ __forceinline__ void refine_dim(bool active, bool preloaded, int n, double alpha, const double* hist,
+                                           const double* e_in, double* e_out, double* sm) {
   double* hs = sm;               // histogram of this dimension
   double* dm = sm + (n + 1);     // smoothed histogram, then damped importance m
   double* cm = sm + 2 * (n + 1); // cumulative importance: cm[k] = m_0 + ... + m_{k-1}
   double* eo = sm + 3 * (n + 1); // old edges
   const int lane = threadIdx.x & 63;
-  if (active) {
+  if (active && !preloaded) {
     for (int k = lane; k < n; k += kWave) hs[k] = hist[k];
     for (int k = lane; k <= n; k += kWave) eo[k] = e_in[k];
   }
@@ -565,7 +571,7 @@ __global__ void k_refine(DevBufs b, int nbins, double alpha) {
   extern __shared__ unsigned char smem[];
   const int d = blockIdx.x, n = nbins;
   double* e = b.edges + d * (n + 1);
-  refine_dim(true, n, alpha, b.hist + d * n, e, e, reinterpret_cast<double*>(smem));
+  refine_dim(true, false, n, alpha, b.hist + d * n, e, e, reinterpret_cast<double*>(smem));
 }
 
 // ---------------------------------------------------------------------------
