@@ -138,7 +138,10 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result *out);
 /* Re-optimise the grid from the last iteration's histogram (Sec. 2.1: serial
  * grid optimisation between iterations): per dimension, neighbour smoothing,
  * r_k = dbar_k / sum dbar, damping m_k = ((r_k - 1)/ln r_k)^alpha, new edges at
- * equal cumulative m.  Asynchronous on the stream.
+ * equal cumulative m.  The iteration's finalisation normally computes this
+ * grid already (into a second buffer) and the call only swaps the buffers;
+ * after vegas_set_grid or vegas_set_state it runs as its own kernel.  Either
+ * way the result is the same and ordered on the stream.
  * Errors: VEGAS_ESTATE (no iteration since init or since the last refine). */
 int vegas_refine(vegas_handle h);
 
