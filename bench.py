@@ -271,6 +271,18 @@ def main():
     ms_ev, n_ev = st["event"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
     roof = roofline(args.workload, args.precision, N, avg_ev)
+    # histogram stage: the column sums of the per-block partial rows (S1, S2 and the
+    # per-bin d digits) -- HBM-bound; algorithmic bytes = rows x columns x 8 read
+    shape = g.last_launch()
+    ms_fold, n_fold = st["fold"]
+    hist_bytes = shape["fold_rows"] * shape["fold_cols"] * 8
+    avg_fold = ms_fold / max(n_fold, 1) * 1e-3
+    hist_stage = {"kernel": "k_accsum", "bound": "hbm", "bytes_per_launch": hist_bytes,
+                  "avg_launch_ms": avg_fold * 1e3,
+                  "achieved_gbs": hist_bytes / avg_fold / 1e9 if avg_fold > 0 else None,
+                  "peak_gbs": PEAK_HBM_GBS,
+                  "frac": hist_bytes / avg_fold / 1e9 / PEAK_HBM_GBS if avg_fold > 0 else None,
+                  "launch": shape}
     line = {
         "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
         "value": events_per_s,
@@ -292,6 +304,7 @@ def main():
         "rel_error": eps,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
         "roofline": roof,
+        "histogram_stage": hist_stage,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters,

@@ -180,13 +180,21 @@ int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks
 
 /* Per-stage kernel timing (off by default).  When on, every kernel is
  * launched with a start and a stop HIP event bound to its own dispatch
- * (hipExtLaunchKernel), so timing adds no work between kernels.
- * vegas_stage_times waits for the stream and returns, for the stages
- * {events, accumulation, finalisation, refinement}, the summed kernel
+ * (hipExtLaunchKernel), so timing adds no work between kernels (it does add
+ * host time per launch).  vegas_stage_times waits for the stream and returns,
+ * for the stages {events (k_event, with the fused fold), fold (the column sums
+ * of the per-block partial rows, and the first iteration's fold from the
+ * records), finalisation (estimate, next scales, speculative refinement),
+ * refinement (only when it runs as its own kernel)}, the summed kernel
  * milliseconds ms[4] and kernel counts launches[4] (host arrays, either
- * nullable) since the last reset; reset != 0 clears them.  One iteration
- * launches one kernel in each of the first two stages and two in the third. */
+ * nullable) since the last reset; reset != 0 clears them. */
 int vegas_set_timing(vegas_handle h, int32_t enable);
+
+/* Launch shape of the last iteration: info[0] event-kernel blocks, info[1]
+ * threads per block, info[2] rows of per-block partials folded, info[3] int64
+ * columns per row (3 (2 + ndim nbins)); host array of 4.
+ * Errors: VEGAS_EINVAL, VEGAS_ESTATE (no iteration yet). */
+int vegas_last_launch(vegas_handle h, int64_t *info);
 int vegas_stage_times(vegas_handle h, double *ms, int64_t *launches, int32_t reset);
 
 /* Adjoint of the Drell-Yan estimator (process VEGAS_DY_Z only).  For B parameter

@@ -860,6 +860,7 @@ struct vegas_state {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;  // (stage, start/stop)
   double stage_ms[4];
   int64_t stage_n[4];
+  int64_t last_launch[4];  // event blocks, threads per block, fold rows, fold columns of the last iteration
   // adjoint scratch (library-allocated on first use, grown on demand)
   double* gbuf;
   size_t gbuf_doubles;
@@ -1164,6 +1165,13 @@ int vegas_destroy(vegas_handle h) {
   return rc;
 }
 
+int vegas_last_launch(vegas_handle h, int64_t* info) {
+  if (!h || !info) return VEGAS_EINVAL;
+  if (!h->any_iter) return VEGAS_ESTATE;
+  for (int i = 0; i < 4; ++i) info[i] = h->last_launch[i];
+  return VEGAS_OK;
+}
+
 int vegas_set_timing(vegas_handle h, int32_t enable) {
   if (!h) return VEGAS_EINVAL;
   h->timing = enable != 0;
@@ -1253,6 +1261,16 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   }
   const int ncol = 3 * (2 + nslot);
   {
+    TimedLaunch t(h, 1);
+    hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
+                          dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
+    VG_HIP(t.done());
+  }
+  h->last_launch[0] = ev_blocks;
+  h->last_launch[1] = threads;
+  h->last_launch[2] = rows;
+  h->last_launch[3] = ncol;
+  {
     FinArgs fa;
     fa.b = h->b;
     fa.nev = n_events;
@@ -1264,12 +1282,6 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     fa.spec = (h->spec_ok && !ext_y) ? 1 : 0;
     fa.fold_lds = fused ? h->fin_lds : 0;
     fa.alpha = h->cfg.alpha;
-    {
-      TimedLaunch t(h, 2);
-      hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
-                            dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
-      VG_HIP(t.done());
-    }
     TimedLaunch t(h, 2);
     hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused || fa.spec ? 1024 : 256),
                           fa.fold_lds + (fa.spec ? h->refine_lds : 0), h->stream, t.e0, t.e1, 0, fa);

@@ -24,7 +24,7 @@ MAX_ITER = 4096
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
-           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad",
+           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_last_launch",
            "vegas_export", "vegas_iterate_flow", "vegas_flow_create", "vegas_flow_destroy",
            "vegas_flow_get_params", "vegas_flow_set_params", "vegas_flow_density",
            "vegas_flow_loss_grad", "vegas_flow_train_step", "vegas_flow_sample"]
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     L.vegas_destroy.argtypes = [vp]
     L.vegas_set_timing.argtypes = [vp, i32]
     L.vegas_stage_times.argtypes = [vp, vp, vp, i32]
+    L.vegas_last_launch.argtypes = [vp, vp]
     L.vegas_strerror.argtypes = [C.c_int]
     L.vegas_strerror.restype = C.c_char_p
     L.vegas_grad.argtypes = [vp, vp, i32, i64, C.c_uint32, vp, vp]
@@ -235,8 +236,16 @@ class Integrator:
         n = np.zeros(4, dtype=np.int64)
         _check(self._L.vegas_stage_times(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0),
                "vegas_stage_times")
-        names = ("event", "accumulate", "finalize", "refine")
+        names = ("event", "fold", "finalize", "refine")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(names)}
+
+    def last_launch(self):
+        """Launch shape of the last iteration: event blocks, threads per block, folded
+        partial rows, int64 columns per row."""
+        info = np.zeros(4, dtype=np.int64)
+        _check(self._L.vegas_last_launch(self._h, info.ctypes.data), "vegas_last_launch")
+        return {"event_blocks": int(info[0]), "threads": int(info[1]), "fold_rows": int(info[2]),
+                "fold_cols": int(info[3])}
 
     def grad(self, theta, n_events, iteration):
         """sigma[B] and dsigma/dtheta[B,5] (Drell-Yan only) for theta[B,5] at the current
