@@ -267,6 +267,19 @@ def main():
     eps = sig / abs(I)
     events_per_s = args.steps * N / T
     eff = 1.0 / (eps * eps * T)
+    # Kish effective sample size of each timed iteration, (sum w)^2 / sum w^2 =
+    # N I^2 / (I^2 + (N - 1) var), per second of the timed region
+    kish = sum(N * i * i / (i * i + (N - 1) * v) if (i * i + v) > 0 else 0.0 for i, v in timed)
+    # spread over repetitions: 10 more blocks of K steps (ms per step, min / avg / max)
+    reps = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            g.iterate(N, sync=False)
+            g.refine()
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t1) / args.steps * 1e3)
 
     ms_ev, n_ev = st["event"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
@@ -300,6 +313,8 @@ def main():
                    "nbins": cfg["nbins"], "iterations_timed": args.steps},
         "effective_events_per_s": eff,
         "time_to_1e-3_s": 1e6 / eff,
+        "kish_ess_per_s": kish / T,
+        "ms_per_step_10_repeats": {"min": min(reps), "avg": sum(reps) / len(reps), "max": max(reps)},
         "integral_pb": I,
         "rel_error": eps,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},

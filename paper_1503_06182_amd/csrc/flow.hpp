@@ -17,6 +17,7 @@
 // coordinate) for the spline.  The backward kernel recomputes the same MLP
 // (tiles of 32, B from global memory, the same MFMA sequence, so the same bits).
 #pragma once
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,10 +49,9 @@ __device__ __constant__ const int kFlowC[FL_NLAYER][4] = {{0, 1, 2, 3}, {4, 5, 6
 typedef short __attribute__((ext_vector_type(4))) bf16x4_t;
 typedef float __attribute__((ext_vector_type(4))) f32x4_t;
 
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+  const __hip_bfloat16 b = __float2bfloat16(f);
+  return *reinterpret_cast<const uint16_t*>(&b);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 // spline parameters are rounded to binary16 (round to nearest even) in both directions

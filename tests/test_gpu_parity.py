@@ -250,13 +250,21 @@ def test_histogram_sums_and_zero_weight_edge_cases(P):
     assert np.allclose(d.sum(axis=1), s[1], rtol=1e-14)
     w = g.get_weights(0, 1000, with_bins=False)
     assert np.isclose(w.sum(), s[0], rtol=1e-14) and np.isclose((w * w).sum(), s[1], rtol=1e-14)
+    r = g.iterate(2)                       # minimum event count, fused fold
+    assert r["n_events"] == 2 and r["fold"] in (1, 2)
+    w = g.get_weights(0, 2, with_bins=False)
+    assert np.isclose(r["I"], w.mean(), rtol=1e-14)
 
 
 def test_nonfinite_weights_counted(P):
     par = np.concatenate([[9.0], np.ones(3), np.full(3, 0.5)])  # unknown Genz family -> NaN
     g = P.Integrator(W.GENZ, 3, 10, 1, 1.5, par, max_events=500)
-    r = g.iterate(500)
-    assert r["n_nonfinite"] == 500 and r["I"] == 0.0
+    for it in range(3):  # the two-pass fold, then the fused fold with a max |w| of zero
+        r = g.iterate(500)
+        assert r["n_nonfinite"] == 500 and r["n_nonzero"] == 0 and r["I"] == 0.0 and r["var"] == 0.0
+        assert r["fold"] == (0 if it == 0 else 1)
+    d, s = g.get_hist()
+    assert not d.any() and not s.any()
 
 
 def test_errors_and_call_order(P):
