@@ -30,9 +30,9 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 478.0, "f32": 0.0, "traffic": 19_732_086, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_609_255, "events": 10_000_000},
-    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_332_816, "events": 10_000_000},
+    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_739_229, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_614_699, "events": 10_000_000},
+    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_327_973, "events": 10_000_000},
 }
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 157.3
@@ -63,7 +63,7 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "adjoint", "flow"])
+    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "ww_4l_paper", "adjoint", "flow"])
     ap.add_argument("--train-events", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--events", type=int, default=0, help="events per iteration (0: workload's)")
@@ -114,6 +114,90 @@ def cpu_baseline(cfg, iters, events):
     return {"value": iters * events / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} iterations x {events} events of the same workload, serial "
                       f"FP64 C oracle on one host core, {dt:.1f} s"}
+
+
+def bench_paper_schedule(args):
+    """The W+W- integrand on the two-stage schedule of the paper's timing runs
+    (4 x 1,000 + 10 x 10,000 events, grid refined after every iteration, the warm-up
+    stage dropped from the result).  One step = the whole schedule from the uniform
+    grid (the state is restored between steps, outside the timed region); at these
+    sizes the iteration is bound by launch and synchronisation latency."""
+    import torch
+
+    import paper_1503_06182_amd as P
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    cfg = W.config("ww_4l_paper")
+    sched, first = cfg["schedule"], cfg["discard_first"]
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"], max_events=max(sched))
+    s0 = g.get_state()
+
+    def one():
+        g.set_state(s0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in sched:
+            g.iterate(n, sync=False)
+            g.refine()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        one()
+    times = [one() for _ in range(args.steps)]
+    T = sum(times)
+    r, rall = g.result(first=first), g.result()
+    eps = r["sigma"] / abs(r["I"])
+    # event-kernel time per schedule from a pass with HIP events bound to each dispatch
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    one()
+    st = g.stage_times()
+    g.set_timing(False)
+    ms_ev = st["event"][0]
+    flop = EVENT_KERNEL_WORK[("ww_4l", "fp64")]["f64"] * sum(sched)
+    roof = {"kernel": "k_event", "bound": "alu", "achieved": flop / (ms_ev * 1e-3) / 1e12,
+            "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": flop / (ms_ev * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+            "avg_launch_ms": ms_ev / st["event"][1],
+            "note": "14 launches of 1e3 and 1e4 events: launch-latency bound"}
+    n_step = sum(sched)
+    line = {
+        "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
+        "value": args.steps * n_step / T, "unit": "events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (counter-based Philox stream, seed 1)",
+        "config": {"workload": "ww_4l_paper", "schedule": "4x1000+10x10000", "ndim": cfg["ndim"],
+                   "nbins": cfg["nbins"], "discard_first": first},
+        "effective_events_per_s": 1.0 / (eps * eps * (T / args.steps)),
+        "ms_per_step_min_avg_max": [min(times) * 1e3, T / args.steps * 1e3, max(times) * 1e3],
+        "ms_per_iteration": T / args.steps / len(sched) * 1e3,
+        "integral_pb": r["I"], "rel_error": eps, "chi2_dof": r["chi2_dof"],
+        "integral_all_iterations_pb": rall["I"],
+        "kernel_ms_per_step": {k: v[0] for k, v in st.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        reps = 10
+        o_t = 0.0
+        for _ in range(reps):
+            o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                             cfg["params"])
+            t0 = time.perf_counter()
+            for n in sched:
+                o.iterate(n)
+                o.refine()
+            o_t += time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": reps * n_step / o_t, "unit": "events/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{reps} runs of the whole schedule, serial FP64 C oracle on "
+                                          f"one host core, {o_t:.1f} s"}
+    g.close()
+    print(json.dumps(line), flush=True)
 
 
 def bench_adjoint(args):
@@ -224,6 +308,9 @@ def main():
         return
     if args.workload == "flow":
         bench_flow(args)
+        return
+    if args.workload == "ww_4l_paper":
+        bench_paper_schedule(args)
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

@@ -153,6 +153,16 @@ int vegas_refine(vegas_handle h);
 int vegas_result(vegas_handle h, double *integral, double *error, double *chi2_dof,
                  int32_t *n_iter);
 
+/* The same combination over iterations first .. (last) only.  The timing runs
+ * of Sec. 3.2 use a two-stage schedule (a few small iterations, then larger
+ * ones); whether the first stage enters the result is not stated, and this
+ * call lets a caller drop it (first = number of warm-up iterations; first = 0
+ * is vegas_result).  n_iter receives the number of iterations combined.
+ * Errors: VEGAS_ESTATE (no iteration yet), VEGAS_EINVAL (first < 0 or first
+ * not below the number of iterations done). */
+int vegas_result_from(vegas_handle h, int32_t first, double *integral, double *error,
+                      double *chi2_dof, int32_t *n_iter);
+
 /* Grid edges, host array [ndim][nbins+1] (waits for the stream). */
 int vegas_get_grid(vegas_handle h, double *edges);
 /* Replace the grid (host [ndim][nbins+1]; e_0 = 0, e_n = 1, non-decreasing).

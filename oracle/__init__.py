@@ -69,6 +69,7 @@ def lib():
         L.ora_iterate.argtypes = [C.c_void_p, C.c_int64, _dp]
         L.ora_refine.argtypes = [C.c_void_p]
         L.ora_result.argtypes = [C.c_void_p, _dp]
+        L.ora_result_from.argtypes = [C.c_void_p, C.c_int, _dp]
         L.ora_get_grid.argtypes = [C.c_void_p, _dp]
         L.ora_set_grid.argtypes = [C.c_void_p, _dp]
         L.ora_get_hist.argtypes = [C.c_void_p, _dp, _dp]
@@ -188,9 +189,10 @@ class Vegas:
         if lib().ora_refine(self._h) != 0:
             raise RuntimeError("refine before iterate")
 
-    def result(self):
+    def result(self, first=0):
         out = np.zeros(4)
-        lib().ora_result(self._h, out)
+        if lib().ora_result_from(self._h, first, out) != 0:
+            raise ValueError("no iteration, or first out of range")
         return {"I": out[0], "sigma": out[1], "chi2_dof": out[2], "n_iter": int(out[3])}
 
     def get_grid(self):

@@ -898,37 +898,44 @@ int ora_refine(ora_state *s) {
   return 0;
 }
 
-/* Inverse-variance combination over all iterations so far; chi^2 per degree
- * of freedom about the combined value.  Iterations with zero variance (a
- * constant integrand) are exact: their plain mean is returned with sigma 0. */
-int ora_result(const ora_state *s, double out[4]) {
+/* Inverse-variance combination over iterations first .. n_iter-1; chi^2 per
+ * degree of freedom about the combined value.  Iterations with zero variance
+ * (a constant integrand) are exact: their plain mean is returned with sigma 0.
+ * first > 0 drops the warm-up stage of a two-stage schedule such as the one of
+ * the timing runs in Sec. 3.2. */
+int ora_result_from(const ora_state *s, int first, double out[4]) {
   int n = s->n_iter;
   out[0] = out[1] = out[2] = 0.0;
-  out[3] = n;
+  out[3] = 0.0;
   if (n == 0) return -2;
+  if (first < 0 || first >= n) return -1;
+  out[3] = n - first;
   int nzero = 0;
   long double zsum = 0.0L;
-  for (int j = 0; j < n; ++j)
+  for (int j = first; j < n; ++j)
     if (s->varj[j] <= 0.0) { ++nzero; zsum += s->Ij[j]; }
   if (nzero) {
     out[0] = (double)(zsum / nzero);
     return 0;
   }
   long double wsum = 0.0L, iwsum = 0.0L;
-  for (int j = 0; j < n; ++j) {
+  for (int j = first; j < n; ++j) {
     wsum += 1.0L / s->varj[j];
     iwsum += (long double)s->Ij[j] / s->varj[j];
   }
   long double comb = iwsum / wsum;
   out[0] = (double)comb;
   out[1] = (double)sqrtl(1.0L / wsum);
-  if (n > 1) {
+  if (n - first > 1) {
     long double chi = 0.0L;
-    for (int j = 0; j < n; ++j) chi += (s->Ij[j] - comb) * (s->Ij[j] - comb) / s->varj[j];
-    out[2] = (double)(chi / (n - 1));
+    for (int j = first; j < n; ++j) chi += (s->Ij[j] - comb) * (s->Ij[j] - comb) / s->varj[j];
+    out[2] = (double)(chi / (n - first - 1));
   }
   return 0;
 }
+
+/* All iterations so far. */
+int ora_result(const ora_state *s, double out[4]) { return ora_result_from(s, 0, out); }
 
 int ora_get_grid(const ora_state *s, double *edges) {
   memcpy(edges, s->edges, sizeof(double) * s->ndim * (s->nbins + 1));

@@ -80,6 +80,7 @@ int ora_iterate(ora_state *s, int64_t n, double out[4]);
 int ora_refine(ora_state *s);
 /* out = {I, sigma, chi2/dof, n_iter} */
 int ora_result(const ora_state *s, double out[4]);
+int ora_result_from(const ora_state *s, int first, double out[4]);
 int ora_get_grid(const ora_state *s, double *edges);
 int ora_set_grid(ora_state *s, const double *edges);
 int ora_get_hist(const ora_state *s, double *d, double sums[2]);

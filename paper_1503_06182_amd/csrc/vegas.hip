@@ -41,6 +41,11 @@ constexpr int kWave = 64;
 
 constexpr int kMaxRowsEvent = 1 << 16;  // cap on event-kernel blocks
 constexpr int kMaxRowsAcc = 1024;       // cap on accumulation blocks (rows of the digit partials)
+
+// row stride of the digit partials: the ncol = 3 (2 + D n) columns padded to a whole
+// number of 32-column (256-byte) tiles, so that every tile the column reduction reads
+// is aligned to the 128-byte lines it is fetched in
+__host__ __device__ constexpr int part_ld(int ncol) { return (ncol + 31) & ~31; }
 constexpr int kFusedLdsMax = 48 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
 
 struct DevBufs {
@@ -51,7 +56,7 @@ struct DevBufs {
   unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max, cleared by k_finalize)
   unsigned long long* cnt;       // [2] n_nonzero, n_nonfinite (atomic, cleared by k_finalize)
   int* fxs;                      // [4] valid, E1, E2 of the fused fold (set by k_finalize for the next iteration)
-  long long* part_acc;           // [rows][3*(2+D*n)] per-block digit sums: S1, S2, d[...]
+  long long* part_acc;           // [rows][part_ld(3*(2+D*n))] per-block digit sums: S1, S2, d[...]
   long long* acc_tot;            // [3*(2+D*n)] digit sums over all blocks
   double* hist;                  // [D*n + 2] d, S1, S2 of the last iteration
   double* history;               // [VEGAS_MAX_ITER][2] I_j, var_j
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     if (blk[2]) atomicAdd(&a.b.cnt[1], blk[2]);
   }
   if constexpr (FUSED) {
-    long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * ncol;
+    long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * part_ld(ncol);
     for (int i = threadIdx.x; i < ncol; i += blockDim.x) row[i] = acc[i];
   }
 }
@@ -323,7 +328,7 @@ __global__ void k_accum(AccArgs a) {
   }
   acc_sums_to_lds(ls, acc);
   __syncthreads();
-  long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * ncol;
+  long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * part_ld(ncol);
   if (blockIdx.y == 0)
     for (int i = threadIdx.x; i < 6; i += blockDim.x) row[i] = acc[i];
   for (int i = threadIdx.x; i < lcol - 6; i += blockDim.x) row[3 * (2 + dlo * n) + i] = acc[6 + i];
@@ -445,10 +450,11 @@ __global__ void k_accsum(DevBufs b, int ncol, int rows) {
   __shared__ long long red[8][kColTile];
   const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
   const int col = blockIdx.x * kColTile + c;
+  const int64_t ld = part_ld(ncol);
   long long sum = 0;
   if (col < ncol)
     for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8)
-      sum += b.part_acc[static_cast<int64_t>(r) * ncol + col];
+      sum += b.part_acc[r * ld + col];
   red[rg][c] = sum;
   __syncthreads();
   if (rg == 0 && col < ncol) {
@@ -577,11 +583,11 @@ __global__ void k_refine(DevBufs b, int nbins, double alpha) {
 // ---------------------------------------------------------------------------
 // K5: inverse-variance combination over the iterations
 // ---------------------------------------------------------------------------
-__global__ void k_result(DevBufs b, int n_iter) {
+__global__ void k_result(DevBufs b, int first, int n_iter) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int nzero = 0;
   double zsum = 0.0, ws = 0.0, iws = 0.0;
-  for (int j = 0; j < n_iter; ++j) {
+  for (int j = first; j < n_iter; ++j) {
     const double I = b.history[2 * j], v = b.history[2 * j + 1];
     if (v <= 0.0) {
       ++nzero;
@@ -591,6 +597,7 @@ __global__ void k_result(DevBufs b, int n_iter) {
       iws += I / v;
     }
   }
+  const int n = n_iter - first;
   if (nzero) {
     b.result[0] = zsum / nzero;
     b.result[1] = 0.0;
@@ -598,15 +605,15 @@ __global__ void k_result(DevBufs b, int n_iter) {
   } else {
     const double I = iws / ws;
     double chi = 0.0;
-    for (int j = 0; j < n_iter; ++j) {
+    for (int j = first; j < n_iter; ++j) {
       const double dI = b.history[2 * j] - I;
       chi += dI * dI / b.history[2 * j + 1];
     }
     b.result[0] = I;
     b.result[1] = sqrt(1.0 / ws);
-    b.result[2] = n_iter > 1 ? chi / (n_iter - 1) : 0.0;
+    b.result[2] = n > 1 ? chi / (n - 1) : 0.0;
   }
-  b.result[3] = n_iter;
+  b.result[3] = n;
 }
 
 // training data for the learned proposal: the uniform points (binary32) and weights
@@ -669,7 +676,7 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.maxw = take(sizeof(unsigned long long) * 2);
   L.cnt = take(sizeof(unsigned long long) * 2);
   L.fxs = take(sizeof(int) * 4);
-  L.part_acc = take(sizeof(long long) * kMaxRowsAcc * 3 * (2 + D * n));
+  L.part_acc = take(sizeof(long long) * kMaxRowsAcc * part_ld(3 * (2 + D * n)));
   L.acc_tot = take(sizeof(long long) * 3 * (2 + D * n));
   L.hist = take(sizeof(double) * (D * n + 2));
   L.history = take(sizeof(double) * 2 * VEGAS_MAX_ITER);
@@ -1361,10 +1368,13 @@ int vegas_refine(vegas_handle h) {
   return VEGAS_OK;
 }
 
-int vegas_result(vegas_handle h, double* integral, double* error, double* chi2_dof, int32_t* n_iter) {
+int vegas_result_from(vegas_handle h, int32_t first, double* integral, double* error, double* chi2_dof,
+                      int32_t* n_iter) {
   if (!h) return VEGAS_EINVAL;
   if (!h->any_iter || h->iter == 0) return VEGAS_ESTATE;
-  hipLaunchKernelGGL(k_result, dim3(1), dim3(64), 0, h->stream, h->b, static_cast<int>(h->iter));
+  if (first < 0 || static_cast<uint64_t>(first) >= h->iter) return VEGAS_EINVAL;
+  hipLaunchKernelGGL(k_result, dim3(1), dim3(64), 0, h->stream, h->b, static_cast<int>(first),
+                     static_cast<int>(h->iter));
   VG_HIP(hipGetLastError());
   double r[4];
   VG_HIP(hipMemcpyAsync(r, h->b.result, sizeof(r), hipMemcpyDeviceToHost, h->stream));
@@ -1374,6 +1384,10 @@ int vegas_result(vegas_handle h, double* integral, double* error, double* chi2_d
   if (chi2_dof) *chi2_dof = r[2];
   if (n_iter) *n_iter = static_cast<int32_t>(r[3]);
   return VEGAS_OK;
+}
+
+int vegas_result(vegas_handle h, double* integral, double* error, double* chi2_dof, int32_t* n_iter) {
+  return vegas_result_from(h, 0, integral, error, chi2_dof, n_iter);
 }
 
 int vegas_get_grid(vegas_handle h, double* edges) {

@@ -22,6 +22,7 @@ NPHYS = 16
 MAX_ITER = 4096
 
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
+           "vegas_result_from",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
            "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_last_launch",
@@ -67,6 +68,7 @@ def load(path: str = LIB_PATH):
     L.vegas_iterate.argtypes = [vp, i64, C.POINTER(IterResult)]
     L.vegas_refine.argtypes = [vp]
     L.vegas_result.argtypes = [vp, dp, dp, dp, C.POINTER(i32)]
+    L.vegas_result_from.argtypes = [vp, i32, dp, dp, dp, C.POINTER(i32)]
     L.vegas_get_grid.argtypes = [vp, vp]
     L.vegas_set_grid.argtypes = [vp, vp]
     L.vegas_get_hist.argtypes = [vp, vp, vp]
@@ -186,11 +188,12 @@ class Integrator:
     def refine(self):
         _check(self._L.vegas_refine(self._h), "vegas_refine")
 
-    def result(self):
+    def result(self, first=0):
+        """Combined estimate over iterations first .. last (first > 0 drops warm-up iterations)."""
         I, e, c = C.c_double(), C.c_double(), C.c_double()
         n = C.c_int32()
-        _check(self._L.vegas_result(self._h, C.byref(I), C.byref(e), C.byref(c), C.byref(n)),
-               "vegas_result")
+        _check(self._L.vegas_result_from(self._h, first, C.byref(I), C.byref(e), C.byref(c), C.byref(n)),
+               "vegas_result_from")
         return {"I": I.value, "sigma": e.value, "chi2_dof": c.value, "n_iter": n.value}
 
     def get_grid(self):

@@ -125,6 +125,27 @@ def test_full_schedule_end_to_end(P, name):
     assert rg["n_iter"] == ro["n_iter"] == cfg["n_iter"]
 
 
+def test_paper_schedule_with_and_without_warm_up(P):
+    """The two-stage schedule of the timing runs in Sec. 3.2 (4 x 1,000 then
+    10 x 10,000 events) on the W+W- integrand, no grid injection: the combination
+    of all iterations and that of the second stage only agree with the oracle's."""
+    cfg = W.config("ww_4l")
+    g, o = make_pair(P, cfg, 10_000)
+    for n in [1000] * 4 + [10_000] * 10:
+        g.iterate(n)
+        g.refine()
+        o.iterate(n)
+        o.refine()
+    for first, n_iter in ((0, 14), (4, 10), (13, 1)):
+        rg, ro = g.result(first=first), o.result(first=first)
+        assert rg["n_iter"] == ro["n_iter"] == n_iter
+        assert rel(rg["I"], ro["I"]) < REL_ITER, first
+        assert rel(rg["sigma"], ro["sigma"]) < 1e-8, first
+        assert abs(rg["chi2_dof"] - ro["chi2_dof"]) < 1e-6 * max(1.0, ro["chi2_dof"]), first
+    with pytest.raises(P.VegasError):
+        g.result(first=14)
+
+
 def run_schedule(P, cfg, n, n_iter, **launch):
     g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
                      cfg["params"], max_events=n, **launch)

@@ -150,3 +150,50 @@ def test_iteration_counter_keys_the_stream():
     assert np.array_equal(w0, w0b)
     w1, _ = v.event_weights(1, 0, 100)
     assert not np.array_equal(w0, w1)
+
+
+def test_result_from_last_iteration_is_that_iteration():
+    """Combining only the last iteration returns that iteration's own estimate
+    (I_j, sqrt(var_j)) as iterate() reported it, with one iteration counted."""
+    cfg = W.config("gauss4")
+    v = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"])
+    for _ in range(2):
+        v.iterate(3000)
+        v.refine()
+    last = v.iterate(5000)
+    r = v.result(first=2)
+    assert r["n_iter"] == 1 and r["chi2_dof"] == 0.0
+    assert abs(r["I"] - last["I"]) <= 1e-15 * abs(last["I"])
+    assert abs(r["sigma"] - math.sqrt(last["var"])) <= 1e-15 * math.sqrt(last["var"])
+    assert v.result()["n_iter"] == 3
+
+
+def test_result_from_out_of_range_is_an_error():
+    v = oracle.Vegas(W.GAUSS, 2, 10, 1, 1.5, [0.5, 0.1])
+    with pytest.raises(ValueError):
+        v.result()
+    v.iterate(100)
+    for first in (-1, 1, 5):
+        with pytest.raises(ValueError):
+            v.result(first=first)
+
+
+def test_two_stage_schedule_pulls_after_dropping_warm_up():
+    """The timing schedule of Sec. 3.2 (4 small iterations, then 10 ten times
+    larger), with the warm-up iterations dropped: the pulls against the exact
+    Gaussian integral over seeds have mean 0 and width 1, and the error of the
+    second stage alone is larger than that of all iterations together."""
+    pulls = []
+    for seed in range(1, 41):
+        v = oracle.Vegas(W.GAUSS, 2, 20, seed, 1.5, [0.4, 0.15])
+        for n in [300] * 4 + [3000] * 10:
+            v.iterate(n)
+            v.refine()
+        r, rall = v.result(first=4), v.result()
+        assert r["n_iter"] == 10 and rall["n_iter"] == 14
+        assert r["sigma"] > rall["sigma"]
+        pulls.append((r["I"] - gauss_exact(0.4, 0.15, 2)) / r["sigma"])
+    pulls = np.array(pulls)
+    assert abs(pulls.mean()) < 0.5
+    assert 0.7 < pulls.std() < 1.35

@@ -50,6 +50,12 @@ def config(name: str) -> dict:
         return dict(process=WW_4L, ndim=8, nbins=100, seed=1, alpha=1.5,
                     params=phys_params(500.0),
                     n_iter=10, n_events=10_000_000)
+    if name == "ww_4l_paper":  # the W+W- integrand on the two-stage schedule of the timing
+        # runs in Sec. 3.2: 4 x 1,000 then 10 x 10,000 events, the first stage dropped
+        c = config("ww_4l")
+        c.update(schedule=[1000] * 4 + [10_000] * 10, discard_first=4,
+                 n_iter=14, n_events=10_000)
+        return c
     if name == "eemumu":
         return dict(process=EEMUMU, ndim=2, nbins=50, seed=1, alpha=1.5,
                     params=phys_params(91.0), n_iter=5, n_events=100_000)
