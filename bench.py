@@ -6,6 +6,12 @@ pT > 20 GeV and |eta| < 2.5, synthetic PDFs A x^-0.5 (1-x)^3, seed 1.
 One step = one full VEGAS iteration: events -> exact accumulation ->
 finalisation (vegas_iterate) -> grid refinement (vegas_refine).
 
+Warm-up: 0.2 s of the same steps on a throwaway handle (the clocks settle over the
+first tens of milliseconds of sustained load), then --warmup W (default 2) untimed
+steps on the measured handle and K = --steps (default 10) timed steps: the timed
+iterations are iterations W .. W+K-1 of a fresh integrator, as in the
+configuration's schedule.
+
 Prints one JSON line: events/s over the timed steps, the variance-weighted
 effective events/s 1/(eps^2 T) of the timed iterations' combined estimate, the
 roofline of the dominant kernel (timed with HIP events on the library's own
@@ -30,10 +36,13 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_739_229, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_614_699, "events": 10_000_000},
-    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_327_973, "events": 10_000_000},
+    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_747_421, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_451_421, "events": 10_000_000},
+    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_332_256, "events": 10_000_000},
 }
+# HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
+# workload's default event count
+HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 7_799_324}
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -62,7 +71,9 @@ def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default: 2 for the VEGAS iteration, whose grid they adapt; "
+                         "as many as fill 0.2 s for the other workloads)")
     ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "ww_4l_paper", "adjoint", "flow"])
     ap.add_argument("--train-events", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=20)
@@ -74,6 +85,49 @@ def parse_args():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
+
+
+def warm_up(args, step, min_s=0.2, cap=2000):
+    """Untimed steps before the timed region: exactly --warmup if given, else steps
+    until 0.2 s of them have run (at least 2, at most cap) -- under sustained load the
+    clocks settle over the first tens of milliseconds.  Only for steps that leave the
+    state unchanged (the VEGAS iteration refines its grid: see clock_warm_up).
+    Returns the count."""
+    import torch
+    if args.warmup is not None:
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        return args.warmup
+    n = 0
+    t0 = time.perf_counter()
+    while n < 2 or (n < cap and time.perf_counter() - t0 < min_s):
+        step()
+        n += 1
+        if n % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return n
+
+
+def clock_warm_up(make, step, seconds=0.2, cap=2000):
+    """The same steps on a throwaway handle for `seconds`, so that the measured handle
+    starts at settled clocks without running more iterations than its schedule:
+    continued refinement at a fixed event count lets the grid's bin widths start to
+    alternate after a few tens of iterations, and the timed iterations are meant to
+    be those of the configuration's schedule."""
+    import torch
+    h = make()
+    n = 0
+    t0 = time.perf_counter()
+    while n < 2 or (n < cap and time.perf_counter() - t0 < seconds):
+        step(h)
+        n += 1
+        if n % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    h.close()
+    return time.perf_counter() - t0
 
 
 def copy_calibration(nbytes):
@@ -144,8 +198,7 @@ def bench_paper_schedule(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    for _ in range(args.warmup):
-        one()
+    Wn = warm_up(args, one)
     times = [one() for _ in range(args.steps)]
     T = sum(times)
     r, rall = g.result(first=first), g.result()
@@ -167,7 +220,7 @@ def bench_paper_schedule(args):
     line = {
         "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
         "value": args.steps * n_step / T, "unit": "events/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3,
+        "steps": args.steps, "warmup": Wn, "ms_per_step": T / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (counter-based Philox stream, seed 1)",
         "config": {"workload": "ww_4l_paper", "schedule": "4x1000+10x10000", "ndim": cfg["ndim"],
@@ -216,9 +269,7 @@ def bench_adjoint(args):
         g.refine()
     theta = torch.tensor(W.adjoint_points(64), device="cuda")
     N = args.events or 1_000_000
-    for _ in range(args.warmup):
-        g.grad(theta, N, 5)
-    torch.cuda.synchronize()
+    Wn = warm_up(args, lambda: g.grad(theta, N, 5))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         sig, ds = g.grad(theta, N, 5)
@@ -226,7 +277,7 @@ def bench_adjoint(args):
     T = time.perf_counter() - t0
     line = {"metric": "adjoint point-events/s (sigma and 5 derivatives per point and event)",
             "value": args.steps * N * 64 / T, "unit": "point-events/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3,
+            "steps": args.steps, "warmup": Wn, "ms_per_step": T / args.steps * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic", "config": {"workload": "adjoint", "points": 64, "events": N},
             "sigma_mean_pb": float(sig.mean())}
@@ -268,9 +319,7 @@ def bench_flow(args):
         torch.cuda.synchronize()
         return rs, time.perf_counter() - t
 
-    for _ in range(args.warmup):
-        g.iterate_flow(f, N)
-        g.iterate(N)
+    Wn = warm_up(args, lambda: (g.iterate_flow(f, N), g.iterate(N)))
     rf, tf = run("flow", args.steps)
     rv, tv = run("vegas", args.steps)
     If, sf = combine([(r["I"], r["var"]) for r in rf])
@@ -281,7 +330,7 @@ def bench_flow(args):
     relvar_v = sum(r["var"] * N / r["I"] ** 2 for r in rv) / len(rv)
     line = {"metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
             "value": args.steps * N / tf, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": tf / args.steps * 1e3, "higher_is_better": True,
+            "warmup": Wn, "ms_per_step": tf / args.steps * 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mlp/f32-spline/f64-weight",
             "data": "synthetic (counter-based Philox stream, seed 1; parametric PDFs)",
             "config": {"workload": "flow", "integrand": "ww_4l", "events_per_iteration": N,
@@ -324,11 +373,19 @@ def main():
     cfg = W.config(args.workload)
     N = args.events or cfg["n_events"]
     prec = P.FP32_ME if args.precision == "fp32me" else P.FP64
-    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
-                     cfg["params"], precision=prec, max_events=N)
-    for _ in range(args.warmup):
-        g.iterate(N, sync=False)
-        g.refine()
+    def make():
+        return P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                            cfg["params"], precision=prec, max_events=N)
+
+    def step(h):
+        h.iterate(N, sync=False)
+        h.refine()
+
+    clock_s = clock_warm_up(make, step)
+    g = make()
+    Wn = 2 if args.warmup is None else args.warmup
+    for _ in range(Wn):
+        step(g)
     torch.cuda.synchronize()
     # throughput: K steps with nothing between the kernels
     t0 = time.perf_counter()
@@ -338,7 +395,7 @@ def main():
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     hist = history_from_state(g.get_state(), cfg["ndim"], cfg["nbins"])
-    timed = hist[args.warmup:args.warmup + args.steps]
+    timed = hist[Wn:Wn + args.steps]
     # kernel durations: K more steps with HIP start/stop events bound to each kernel's
     # dispatch on the library's stream (the events cost host time per launch, so this
     # pass is kept apart from the throughput pass)
@@ -382,6 +439,7 @@ def main():
                   "achieved_gbs": hist_bytes / avg_fold / 1e9 if avg_fold > 0 else None,
                   "peak_gbs": PEAK_HBM_GBS,
                   "frac": hist_bytes / avg_fold / 1e9 / PEAK_HBM_GBS if avg_fold > 0 else None,
+                  "traffic": HIST_STAGE_TRAFFIC.get((args.workload, N)) if prec == P.FP64 else None,
                   "launch": shape}
     line = {
         "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
@@ -389,7 +447,8 @@ def main():
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": Wn,
+        "gpu_clock_warmup_s": round(clock_s, 3),
         "ms_per_step": T / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",

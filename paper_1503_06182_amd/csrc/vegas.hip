@@ -451,10 +451,16 @@ __global__ void k_accsum(DevBufs b, int ncol, int rows) {
   const int c = threadIdx.x & 31, rg = threadIdx.x >> 5;
   const int col = blockIdx.x * kColTile + c;
   const int64_t ld = part_ld(ncol);
+  // the rows rg, rg + 8, ... of this tile: all loads issued before the first add
+  long long v[kRowTile / 8];
+#pragma unroll
+  for (int k = 0; k < kRowTile / 8; ++k) {
+    const int r = blockIdx.y * kRowTile + rg + 8 * k;
+    v[k] = (col < ncol && r < rows) ? b.part_acc[r * ld + col] : 0;
+  }
   long long sum = 0;
-  if (col < ncol)
-    for (int r = blockIdx.y * kRowTile + rg; r < rows && r < (blockIdx.y + 1) * kRowTile; r += 8)
-      sum += b.part_acc[r * ld + col];
+#pragma unroll
+  for (int k = 0; k < kRowTile / 8; ++k) sum += v[k];
   red[rg][c] = sum;
   __syncthreads();
   if (rg == 0 && col < ncol) {

@@ -326,3 +326,41 @@ def test_full_size_sampled_parity_bench_workload(P):
     # the tail of the launch
     wt, _ = o.event_weights(3, n - 300, 300)
     compare_weights(wg[n - 300:], wt, "w_plus tail")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32me"])
+def test_full_size_sampled_parity_ww(P, prec):
+    """W+W- at its measured size (1e7 events per iteration, default launch) in both
+    matrix-element precisions: every 9973rd event and the launch's last 300
+    recomputed one by one by the oracle at the same grid (bins bit-exact; weights
+    to 1e-12 in FP64, to the binary32 bars max 2e-4 / mean 2e-6 in FP32-ME), and
+    the iteration's I and var equal to the mean and variance of all 1e7 weights."""
+    cfg = W.config("ww_4l")
+    n = cfg["n_events"]
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"],
+                     precision=P.FP32_ME if prec == "fp32me" else P.FP64, max_events=n)
+    o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
+    for _ in range(2):
+        g.iterate(n)
+        g.refine()
+    o.set_grid(g.get_grid())
+    r = g.iterate(n)
+    wg, bg = g.get_weights(0, n)
+    idx = np.concatenate([np.arange(0, n - 300, 9973), np.arange(n - 300, n)])
+    wo = np.empty(len(idx))
+    bo = np.empty((len(idx), cfg["ndim"]), dtype=bg.dtype)
+    for k, i in enumerate(idx):
+        w1, b1 = o.event_weights(2, int(i), 1)
+        wo[k], bo[k] = w1[0], b1[0]
+    assert np.array_equal(bg[idx], bo), "bin indices differ"
+    if prec == "fp64":
+        compare_weights(wg[idx], wo, "ww_4l full size")
+    else:
+        m = wo != 0
+        e = np.abs(wg[idx][m] - wo[m]) / np.abs(wo[m])
+        assert e.max() <= 2e-4 and e.mean() <= 2e-6, (e.max(), e.mean())
+    mean = np.sum(wg) / n
+    var = (np.sum(wg * wg) / n - mean * mean) / (n - 1)
+    assert rel(r["I"], mean) < 1e-12
+    assert rel(r["var"], var) < 1e-9
+    assert r["n_events"] == n and r["n_nonzero"] == int(np.count_nonzero(wg))
