@@ -108,25 +108,29 @@ __device__ __forceinline__ void mlp_tile32(const float* __restrict__ m, const ui
 // Tiles of 64 events; each wave keeps the B operands of its output columns (W2: 2
 // column blocks, W3: 3) for all eight k-steps in registers for the whole launch.
 template <bool SAMPLE>
-__global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__ master,
+__global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__ master,
                                                         const uint16_t* __restrict__ wb, int l, const float* vin,
                                                         float* vout, float* logq, int64_t B) {
+  // h1 is dead once the second layer has run (a barrier follows it), so the spline
+  // parameters the third layer writes share its space: 44 KB per block, 3 blocks per CU
+  static_assert(FL_TILE_F * FL_LDH * sizeof(_Float16) >= FL_TILE_F * FL_LDA * sizeof(uint16_t), "h1 / par union");
   __shared__ float cond[FL_TILE_F][4];
-  __shared__ __align__(16) uint16_t h1[FL_TILE_F * FL_LDA];
+  __shared__ __align__(16) _Float16 h1_par[FL_TILE_F * FL_LDH];
   __shared__ __align__(16) uint16_t h2[FL_TILE_F * FL_LDA];
-  __shared__ __align__(16) _Float16 par[FL_TILE_F * FL_LDH];
+  uint16_t* const h1 = reinterpret_cast<uint16_t*>(h1_par);
+  _Float16* const par = h1_par;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float* m = master + l * FL_LAYER;
   const uint16_t* w = wb + static_cast<int64_t>(l) * FB_LAYER;
-  bf16x4_t b2[2][FL_HID / 16], b3[3][FL_HID / 16];
+  bf16x8_t b2[2][FL_HID / 32], b3[3][FL_HID / 32];
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
-    for (int ks = 0; ks < FL_HID / 16; ++ks) b2[cc][ks] = load_bfrag(w + FB_W2T, FL_HID, (2 * wave + cc) * 16, ks * 16, lane);
+    for (int ks = 0; ks < FL_HID / 32; ++ks) b2[cc][ks] = load_bfrag(w + FB_W2T, FL_HID, (2 * wave + cc) * 16, ks * 32, lane);
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-    for (int ks = 0; ks < FL_HID / 16; ++ks) b3[cc][ks] = load_bfrag(w + FB_W3T, FL_HID, (3 * wave + cc) * 16, ks * 16, lane);
+    for (int ks = 0; ks < FL_HID / 32; ++ks) b3[cc][ks] = load_bfrag(w + FB_W3T, FL_HID, (3 * wave + cc) * 16, ks * 32, lane);
   float bias2[2], bias3[3];
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc) bias2[cc] = m[FO_B2 + (2 * wave + cc) * 16 + (lane & 15)];
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__
     bias3[cc] = col < FL_NOUT ? m[FO_B3 + col] : 0.f;
   }
   const H1Unit u1 = load_h1_unit(m);
-  const int ri = lane & 15, kq = 4 * (lane >> 4);
+  const int ri = lane & 15, kq = 4 * (lane >> 4), kq8 = 8 * (lane >> 4);
   for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE_F; e0 < B;
        e0 += static_cast<int64_t>(gridDim.x) * FL_TILE_F) {
     {
@@ -153,9 +157,9 @@ __global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__
       for (int cc = 0; cc < 2; ++cc) {
         f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < FL_HID / 16; ++ks) {
-          const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(h1 + (rb * 16 + ri) * FL_LDA + ks * 16 + kq);
-          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b2[cc][ks], acc, 0, 0, 0);
+        for (int ks = 0; ks < FL_HID / 32; ++ks) {
+          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h1 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
+          acc = mfma_step(a, b2[cc][ks], acc);
         }
         const int col = (2 * wave + cc) * 16 + ri;
 #pragma unroll
@@ -168,9 +172,9 @@ __global__ __launch_bounds__(256, 2) void k_flow_layer(const float* __restrict__
       for (int cc = 0; cc < 3; ++cc) {
         f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < FL_HID / 16; ++ks) {
-          const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(h2 + (rb * 16 + ri) * FL_LDA + ks * 16 + kq);
-          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b3[cc][ks], acc, 0, 0, 0);
+        for (int ks = 0; ks < FL_HID / 32; ++ks) {
+          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h2 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
+          acc = mfma_step(a, b3[cc][ks], acc);
         }
         const int col = (3 * wave + cc) * 16 + ri;
 #pragma unroll
@@ -344,18 +348,19 @@ constexpr int kWgMaxSplit = 64;
 constexpr int kWgBlocksX = (kWgTiles + (kWgValu + 63) / 64 + 3) / 4;
 
 // C(16x16 at m0, n0) = sum_k A[m][k] B[k][n] with A = Ht (feature-major [m][ld]) and
-// B = Dt ([n][ld]): lane l supplies Ht[m0 + l%16][k0 + 4(l/16) .. +3] and
-// Dt[n0 + l%16][k0 + 4(l/16) .. +3], one 8-byte load each
+// B = Dt ([n][ld]) over k in [k_lo, k_hi) (multiples of 32): lane l supplies
+// Ht[m0 + l%16][k0 + 8(l/16) .. +7] and Dt[n0 + l%16][k0 + 8(l/16) .. +7], one
+// 16-byte load each
 __device__ __forceinline__ f32x4_t mfma_tn(const uint16_t* __restrict__ Ht, const uint16_t* __restrict__ Dt,
                                            int64_t ld, int m0, int n0, int64_t k_lo, int64_t k_hi, int lane) {
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  const uint16_t* ap = Ht + (m0 + (lane & 15)) * ld + 4 * (lane >> 4);
-  const uint16_t* bp = Dt + (n0 + (lane & 15)) * ld + 4 * (lane >> 4);
+  const uint16_t* ap = Ht + (m0 + (lane & 15)) * ld + 8 * (lane >> 4);
+  const uint16_t* bp = Dt + (n0 + (lane & 15)) * ld + 8 * (lane >> 4);
 #pragma unroll 4
-  for (int64_t k0 = k_lo; k0 < k_hi; k0 += 16) {
-    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(ap + k0);
-    const bf16x4_t b = *reinterpret_cast<const bf16x4_t*>(bp + k0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  for (int64_t k0 = k_lo; k0 < k_hi; k0 += 32) {
+    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(ap + k0);
+    const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(bp + k0);
+    acc = mfma_step(a, b, acc);
   }
   return acc;
 }
@@ -377,7 +382,7 @@ __device__ __forceinline__ float dot_run(const float* __restrict__ x, const floa
   return a;
 }
 
-// k_hi is the batch rounded up to 16 (the padded rows hold zero gradients)
+// k_hi is the batch rounded up to 32 (the padded rows hold zero gradients)
 __global__ __launch_bounds__(256) void k_flow_wgrad_part(int64_t Bp, int kc, FlowBwdBufs s, float* part) {
   const int lane = threadIdx.x & 63;
   const int wave_g = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -554,9 +559,9 @@ int flow_prep(vegas_flow_state* f) {
   return VEGAS_OK;
 }
 
-// forward-kernel blocks: two resident per CU (LDS 60 KB, 256 VGPRs); more tiles per block
-// amortise the per-launch load of the weights into registers
-constexpr int kFwdBlocks = 2 * 256;
+// forward-kernel blocks: three resident per CU (LDS 44 KB, at most 168 VGPRs); more tiles
+// per block amortise the per-launch load of the weights into registers
+constexpr int kFwdBlocks = 3 * 256;
 
 int64_t grid_for(int64_t n, int per_block, int cap) {
   int64_t g = (n + per_block - 1) / per_block;
@@ -594,9 +599,9 @@ int flow_backward(vegas_flow_state* f, const double* w, int64_t B, double* loss_
     hipLaunchKernelGGL(k_flow_layer_bwd, dim3(grid_for(B, FL_TILE, 4096)), dim3(256), 0, f->stream, f->master, f->wb,
                        l, f->V + l * stride, gout, gin, f->glq, B, f->bw);
     VF_HIP(hipGetLastError());
-    const int64_t Bp = (B + 15) / 16 * 16;  // rows past B (written by the backward) hold zero gradients
+    const int64_t Bp = (B + 31) / 32 * 32;  // rows past B (written by the backward) hold zero gradients
     int kc = 256;
-    if ((Bp + kc - 1) / kc > kWgMaxSplit) kc = static_cast<int>(((Bp + kWgMaxSplit - 1) / kWgMaxSplit + 15) / 16 * 16);
+    if ((Bp + kc - 1) / kc > kWgMaxSplit) kc = static_cast<int>(((Bp + kWgMaxSplit - 1) / kWgMaxSplit + 31) / 32 * 32);
     const int nsplit = static_cast<int>((Bp + kc - 1) / kc);
     hipLaunchKernelGGL(k_flow_wgrad_part, dim3(kWgBlocksX, nsplit), dim3(256), 0, f->stream, Bp, kc, f->bw, f->wpart);
     VF_HIP(hipGetLastError());

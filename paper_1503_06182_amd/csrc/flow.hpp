@@ -11,7 +11,7 @@
 //
 // The forward kernels give each block (256 threads = 4 waves) tiles of 64
 // events: the first layer of the MLP on the VALU (K = 4), the two 128-wide
-// contractions on v_mfma_f32_16x16x16_bf16 (A from LDS; B, the layer's weights,
+// contractions on v_mfma_f32_16x16x32_bf16 (A from LDS; B, the layer's weights,
 // held in each wave's registers for the whole launch), the spline parameters
 // rounded to binary16 in LDS, then one thread per (event, transformed
 // coordinate) for the spline.  The backward kernel recomputes the same MLP
@@ -34,8 +34,10 @@ constexpr int FO_W1 = 0, FO_B1 = 512, FO_W2 = 640, FO_B2 = 17024, FO_W3 = 17152,
 constexpr int FB_W2T = 0, FB_W3T = 16384, FB_W2N = 16384 + 24576, FB_W3N = 2 * 16384 + 24576;
 constexpr int FB_LAYER = 2 * 16384 + 2 * 24576;  // 81920 bf16 per layer
 constexpr float FL_EPS = 1e-3f;
-constexpr int FL_LDA = FL_HID + 4;   // LDS row stride (bf16) of the activation tiles: no bank conflicts
-constexpr int FL_LDP = FL_NOUTP + 4; // LDS row stride (fp32) of the spline-parameter tile (backward)
+// LDS row strides: whole 16-byte units (the matrix-core operands are 16-byte loads),
+// offset from a power of two against bank conflicts
+constexpr int FL_LDA = FL_HID + 8;   // bf16 activation tiles
+constexpr int FL_LDP = FL_NOUTP + 8; // fp32 spline-parameter tile of the backward (and its bf16 gradient)
 constexpr int FL_LDH = FL_NOUTP + 8; // LDS row stride (binary16) of the spline-parameter tile (forward)
 constexpr int FL_TILE_F = 64;        // events per tile of the forward kernels
 constexpr float FL_DSHIFT = 0.53974242f;  // log(expm1(1 - eps)) for eps = 1e-3: raw 0 gives derivative 1
@@ -46,7 +48,7 @@ __device__ __constant__ const int kFlowX[FL_NLAYER][4] = {{4, 5, 6, 7}, {0, 1, 2
 __device__ __constant__ const int kFlowC[FL_NLAYER][4] = {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 2, 4, 6},
                                                            {1, 3, 5, 7}, {0, 1, 4, 5}, {2, 3, 6, 7}};
 
-typedef short __attribute__((ext_vector_type(4))) bf16x4_t;
+typedef __bf16 __attribute__((ext_vector_type(8))) bf16x8_t;
 typedef float __attribute__((ext_vector_type(4))) f32x4_t;
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
@@ -80,24 +82,32 @@ __device__ __forceinline__ void mlp_h1(const H1Unit& u, const float (*cond)[4], 
   }
 }
 
-// B operand of one 16x16x16 step: lane l supplies Bt[c0 + l%16][k0 + 4(l/16) .. +3]
-__device__ __forceinline__ bf16x4_t load_bfrag(const uint16_t* __restrict__ Bt, int ldb, int c0, int k0, int lane) {
-  return *reinterpret_cast<const bf16x4_t*>(Bt + static_cast<int64_t>(c0 + (lane & 15)) * ldb + k0 + 4 * (lane >> 4));
+// One 16x16x32 step: lane l supplies A[r0 + l%16][k0 + 8(l/16) .. +7] and
+// Bt[c0 + l%16][k0 + 8(l/16) .. +7] (one 16-byte load each) and receives
+// acc[j] = C[r0 + 4(l/16) + j][c0 + l%16].  The instruction sums over all 32 k of
+// the step; A and B supply them in the same lane order, so which k the hardware
+// pairs inside a lane group is immaterial.
+__device__ __forceinline__ bf16x8_t load_bfrag(const uint16_t* __restrict__ Bt, int ldb, int c0, int k0, int lane) {
+  return *reinterpret_cast<const bf16x8_t*>(Bt + static_cast<int64_t>(c0 + (lane & 15)) * ldb + k0 + 8 * (lane >> 4));
 }
 
-// C(16x16 at r0, c0) = sum_k A[r][k] Bt[c][k]: A rows in LDS (stride lda, bf16), Bt rows in
-// global memory (stride ldb, bf16).  Lane l supplies A[r0 + l%16][k0 + 4(l/16) .. +3] and
-// Bt[c0 + l%16][k0 + 4(l/16) .. +3]; acc[j] = C[r0 + 4(l/16) + j][c0 + l%16].
+__device__ __forceinline__ f32x4_t mfma_step(bf16x8_t a, bf16x8_t b, f32x4_t acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+// C(16x16 at r0, c0) = sum_k A[r][k] Bt[c][k] over K (a multiple of 32): A rows in LDS
+// (stride lda, bf16), Bt rows in global memory (stride ldb, bf16); strides and k
+// offsets are multiples of 8 elements (16-byte loads).
 __device__ __forceinline__ f32x4_t mfma_rowcol(const uint16_t* A, int lda, const uint16_t* __restrict__ Bt, int ldb,
                                                int r0, int c0, int K, int lane) {
   f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-  const int ri = lane & 15, kq = 4 * (lane >> 4);
+  const int ri = lane & 15, kq = 8 * (lane >> 4);
   const uint16_t* ap = A + (r0 + ri) * lda + kq;
   const uint16_t* bp = Bt + static_cast<int64_t>(c0 + ri) * ldb + kq;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(ap + k0);
-    const bf16x4_t b = *reinterpret_cast<const bf16x4_t*>(bp + k0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(ap + k0);
+    const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(bp + k0);
+    acc = mfma_step(a, b, acc);
   }
   return acc;
 }
