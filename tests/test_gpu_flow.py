@@ -267,3 +267,43 @@ def test_training_gain_on_ww(env, capsys):
     assert losses[-1][1] < losses[0][1]
     assert diff < 5
     assert rel_f < rel_v
+
+
+def test_full_size_sampled_flow_iteration(env):
+    """A flow iteration at its measured size (1e7 W+W- events, the benchmark's
+    launch): for every 99991st event and the last 100, z is the binary32 of the
+    counter-stream uniforms of (seed, iteration, event); Flow.sample(z) gives the
+    y and log q the iteration used, and the oracle's grid map and integrand at
+    that y give w = J f / q to 1e-12 (so the stream, the map and the weight are
+    the oracle's); log q against the bf16-emulating flow oracle within the
+    rounding-noise bars; I equal to the mean of all 1e7 weights."""
+    import oracle
+    P, torch = env
+    cfg = W.config("ww_4l")
+    n = cfg["n_events"]
+    g = P.Integrator(cfg["process"], 8, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"], max_events=n)
+    for _ in range(2):
+        g.iterate(n)
+        g.refine()
+    theta = random_theta(torch, 5)
+    f = P.Flow(max_batch=4096, max_sample=n, seed=1)
+    f.set_params(theta)
+    r = g.iterate_flow(f, n)
+    it = r["iteration"]
+    wg = g.get_weights(0, n, with_bins=False)
+    idx = np.concatenate([np.arange(0, n - 100, 99_991), np.arange(n - 100, n)])
+    z = torch.tensor(np.array([oracle.uniforms(cfg["seed"], it, int(i), 8) for i in idx])).to(torch.float32)
+    y, lq = f.sample(z.cuda())
+    y64, lq64 = y.cpu().to(torch.float64).numpy(), lq.cpu().to(torch.float64).numpy()
+    o = oracle.Vegas(cfg["process"], 8, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
+    o.set_grid(g.get_grid())
+    wo = np.empty(len(idx))
+    for k in range(len(idx)):
+        x, J, _ = o.grid_map(np.clip(y64[k], 2.0 ** -40, 1.0 - 2.0 ** -40))
+        wo[k] = J * oracle.integrand(W.WW_4L, cfg["params"], x) * math.exp(-lq64[k])
+    assert np.all(wo > 0)
+    rel = np.abs(wg[idx] - wo) / wo
+    assert rel.max() <= 1e-12, rel.max()
+    _, lqo = OF.sample(z.to(torch.float64), theta, bf16_emulation=True)
+    assert_rounding_noise(np.abs(lq64 - lqo.numpy()), "log q at full size")
+    assert abs(r["I"] - wg.sum() / n) <= 1e-12 * abs(r["I"])
