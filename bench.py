@@ -399,8 +399,10 @@ def main():
     hist = history_from_state(g.get_state(), cfg["ndim"], cfg["nbins"])
     timed = hist[Wn:Wn + args.steps]
     # kernel durations: K more steps with HIP start/stop events bound to each kernel's
-    # dispatch on the library's stream (the events cost host time per launch, so this
-    # pass is kept apart from the throughput pass)
+    # dispatch on the library's stream.  The events cost host time per launch: inside
+    # the throughput pass, even on the event kernel alone, they slowed the W+ step by
+    # 16 % (the host could no longer run ahead of the GPU), so this identical pass
+    # follows the timed region instead
     g.set_timing(True)
     g.stage_times(reset=True)
     for _ in range(args.steps):

@@ -188,17 +188,24 @@ int vegas_set_state(vegas_handle h, const void *buf, size_t bytes);
 /* Change the launch configuration (must not change any result). */
 int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks);
 
-/* Per-stage kernel timing (off by default).  When on, every kernel is
- * launched with a start and a stop HIP event bound to its own dispatch
- * (hipExtLaunchKernel), so timing adds no work between kernels (it does add
- * host time per launch).  vegas_stage_times waits for the stream and returns,
- * for the stages {events (k_event, with the fused fold), fold (the column sums
- * of the per-block partial rows, and the first iteration's fold from the
- * records), finalisation (estimate, next scales, speculative refinement),
- * refinement (only when it runs as its own kernel)}, the summed kernel
- * milliseconds ms[4] and kernel counts launches[4] (host arrays, either
- * nullable) since the last reset; reset != 0 clears them. */
-int vegas_set_timing(vegas_handle h, int32_t enable);
+/* Per-stage kernel timing (off by default).  stages is a mask over the four
+ * stages {events (k_event, with the fused fold) = VEGAS_TIME_EVENTS, fold (the
+ * column sums of the per-block partial rows, and the first iteration's fold
+ * from the records) = VEGAS_TIME_FOLD, finalisation (estimate, next scales,
+ * speculative refinement) = VEGAS_TIME_FINAL, refinement (only when it runs as
+ * its own kernel) = VEGAS_TIME_REFINE}; 0 turns timing off.  Every kernel of a
+ * selected stage is launched with a start and a stop HIP event bound to its
+ * own dispatch (hipExtLaunchKernel), so timing adds no work between kernels; it
+ * does add host time per launch, which a long kernel (the event kernel) hides
+ * and a short one may not.  vegas_stage_times waits for the stream and returns
+ * the summed kernel milliseconds ms[4] and kernel counts launches[4] per stage
+ * (host arrays, either nullable) since the last reset; reset != 0 clears them.
+ * Errors: VEGAS_EINVAL (stages outside 0 .. VEGAS_TIME_ALL). */
+enum {
+  VEGAS_TIME_EVENTS = 1, VEGAS_TIME_FOLD = 2, VEGAS_TIME_FINAL = 4, VEGAS_TIME_REFINE = 8,
+  VEGAS_TIME_ALL = 15
+};
+int vegas_set_timing(vegas_handle h, int32_t stages);
 
 /* Launch shape of the last iteration: info[0] event-kernel blocks, info[1]
  * threads per block, info[2] rows of per-block partials folded, info[3] int64

@@ -867,8 +867,9 @@ struct vegas_state {
   int refine_lds;               // LDS of the refinement scratch: D * 4 (n + 1) doubles
   bool scale_valid;             // the device holds scales from a previous iteration (b.fxs)
   int ncu, occ_event, occ_event_fused, occ_acc;  // CUs, and resident 256-thread blocks per CU
-  // optional per-stage kernel timing with HIP events on the handle's stream
-  bool timing;
+  // optional per-stage kernel timing with HIP events on the handle's stream:
+  // bit s set = the kernels of stage s are timed
+  uint32_t timing;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;  // (stage, start/stop)
   double stage_ms[4];
@@ -925,7 +926,7 @@ struct TimedLaunch {
   int stage;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TimedLaunch(vegas_state* hh, int st) : h(hh), stage(st) {
-    if (!h->timing) return;
+    if (!((h->timing >> stage) & 1u)) return;
     e0 = pool_event(h);
     e1 = e0 ? pool_event(h) : nullptr;
     if (e0 && !e1) {
@@ -1185,9 +1186,9 @@ int vegas_last_launch(vegas_handle h, int64_t* info) {
   return VEGAS_OK;
 }
 
-int vegas_set_timing(vegas_handle h, int32_t enable) {
-  if (!h) return VEGAS_EINVAL;
-  h->timing = enable != 0;
+int vegas_set_timing(vegas_handle h, int32_t stages) {
+  if (!h || stages < 0 || stages > VEGAS_TIME_ALL) return VEGAS_EINVAL;
+  h->timing = static_cast<uint32_t>(stages);
   return VEGAS_OK;
 }
 

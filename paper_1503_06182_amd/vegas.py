@@ -230,8 +230,17 @@ class Integrator:
         buf = C.create_string_buffer(blob, len(blob))
         _check(self._L.vegas_set_state(self._h, buf, len(blob)), "vegas_set_state")
 
-    def set_timing(self, enable=True):
-        _check(self._L.vegas_set_timing(self._h, 1 if enable else 0), "vegas_set_timing")
+    STAGES = ("event", "fold", "finalize", "refine")
+
+    def set_timing(self, enable=True, stages=None):
+        """Kernel timing with HIP events on the handle's stream: all stages, or only
+        the named ones (a subset of STAGES); enable=False turns it off."""
+        mask = 0
+        if enable:
+            names = self.STAGES if stages is None else stages
+            for nm in names:
+                mask |= 1 << self.STAGES.index(nm)
+        _check(self._L.vegas_set_timing(self._h, mask), "vegas_set_timing")
 
     def stage_times(self, reset=False):
         """Summed kernel milliseconds and launch counts per stage since the last reset."""
