@@ -43,6 +43,13 @@ EVENT_KERNEL_WORK = {
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count
 HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 7_799_317}
+# FP64 FLOPs of the adjoint's event kernel per (event, parameter point), and its HBM
+# bytes per call at 64 points x 1e6 events, from the same kind of counter runs
+ADJOINT_KERNEL_WORK = {"f64": 264.9, "traffic": 48_225_306, "events": 1_000_000}
+# matrix-core FLOPs of one coupling layer per event: the two 128-wide products,
+# 2 x (128 x 128 + 128 x 192) per event (the 4-input layer runs on the VALU)
+FLOW_LAYER_MFMA_FLOP = 2 * (128 * 128 + 128 * 192)
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -277,12 +284,45 @@ def bench_adjoint(args):
         sig, ds = g.grad(theta, N, 5)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    # kernel durations: K more calls with HIP events bound to each dispatch (the
+    # adjoint's event kernel is timed as the events stage, its tree as the fold)
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    for _ in range(args.steps):
+        g.grad(theta, N, 5)
+    torch.cuda.synchronize()
+    st = g.stage_times()
+    g.set_timing(False)
+    avg = st["event"][0] / max(st["event"][1], 1) * 1e-3
+    work = ADJOINT_KERNEL_WORK
+    f64 = work["f64"] * N * 64 / avg / 1e12 if avg > 0 and work["f64"] else None
+    roof = {"kernel": "k_dy_grad", "bound": "alu", "achieved": f64, "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": f64 / PEAK_FP64_VALU_TFLOPS if f64 else None,
+            "traffic": work["traffic"] if N == work["events"] else None, "avg_launch_ms": avg * 1e3,
+            "flop_per_point_event": work["f64"]}
     line = {"metric": "adjoint point-events/s (sigma and 5 derivatives per point and event)",
             "value": args.steps * N * 64 / T, "unit": "point-events/s", "n_gpus": 1,
             "steps": args.steps, "warmup": Wn, "ms_per_step": T / args.steps * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic", "config": {"workload": "adjoint", "points": 64, "events": N},
-            "sigma_mean_pb": float(sig.mean())}
+            "sigma_mean_pb": float(sig.mean()),
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items() if k != "refine"},
+            "roofline": roof}
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.Vegas(cfg["process"], 3, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
+        for _ in range(cfg["n_iter"]):
+            o.iterate(cfg["n_events"])
+            o.refine()
+        pts, ns = W.adjoint_points(64)[::4], 20_000
+        t0 = time.perf_counter()
+        for th in pts:
+            o.dy_grad(5, ns, th)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": len(pts) * ns / dt, "unit": "point-events/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{len(pts)} of the 64 points x {ns} events, dual-number FP64 C "
+                                          f"oracle on one host core, {dt:.1f} s"}
     print(json.dumps(line), flush=True)
 
 
@@ -330,6 +370,23 @@ def bench_flow(args):
     eff_v = 1.0 / ((sv / Iv) ** 2 * tv)
     relvar_f = sum(r["var"] * N / r["I"] ** 2 for r in rf) / len(rf)
     relvar_v = sum(r["var"] * N / r["I"] ** 2 for r in rv) / len(rv)
+    # the matrix-core roofline of the sampling layers: Flow.sample of N points (the six
+    # k_flow_layer<true> launches a flow iteration runs), HIP events on the flow's stream
+    zs = torch.rand(N, 8, device="cuda", dtype=torch.float32)
+    f.sample(zs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        f.sample(zs)
+    e1.record()
+    torch.cuda.synchronize()
+    t_layer = e0.elapsed_time(e1) * 1e-3 / reps / 6
+    mfma = FLOW_LAYER_MFMA_FLOP * N / t_layer / 1e12
+    roof = {"kernel": "k_flow_layer<true> (one coupling layer, sampling)", "bound": "mfma", "achieved": mfma,
+            "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": mfma / PEAK_BF16_MFMA_TFLOPS,
+            "traffic": None, "avg_launch_ms": t_layer * 1e3, "flop_per_event": FLOW_LAYER_MFMA_FLOP}
+    del zs
     line = {"metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
             "value": args.steps * N / tf, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
             "warmup": Wn, "ms_per_step": tf / args.steps * 1e3, "higher_is_better": True,
@@ -343,7 +400,34 @@ def bench_flow(args):
             "flow_uses": "flow" if eff_f > eff_v else "vegas (fallback)",
             "integral_pb": {"flow": If, "flow_sigma": sf, "vegas": Iv, "vegas_sigma": sv},
             "training": {"seconds": t_train, "steps": steps_train, "loss_first": losses[0][1],
-                         "loss_last": losses[-1][1]}}
+                         "loss_last": losses[-1][1]},
+            "roofline": roof}
+    if not args.no_cpu_baseline:
+        # the oracle's flow iteration on a bounded sample: z from the counter stream,
+        # y = F^-1(z) by the float64 flow oracle, w = J f / q by the C oracle
+        import math
+
+        import numpy as np
+
+        import oracle
+        import oracle.flow as OF
+        theta = f.get_params().cpu().to(torch.float64)
+        o = oracle.Vegas(cfg["process"], 8, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
+        o.set_grid(g.get_grid())
+        ns, it = 20_000, rf[0]["iteration"]
+        t0 = time.perf_counter()
+        z = torch.tensor(np.array([oracle.uniforms(cfg["seed"], it, i, 8) for i in range(ns)]))
+        yo, lqo = OF.sample(z, theta)
+        yo, lqo = yo.numpy(), lqo.numpy()
+        for k in range(ns):
+            x, J, _ = o.grid_map(np.clip(yo[k], 2.0 ** -40, 1.0 - 2.0 ** -40))
+            J * oracle.integrand(cfg["process"], cfg["params"], x) * math.exp(-lqo[k])
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": ns / dt, "unit": "events/s", "cores": torch.get_num_threads(),
+                                "kind": "oracle",
+                                "sample": f"{ns} events of a flow iteration: float64 PyTorch flow oracle "
+                                          f"(up to {torch.get_num_threads()} threads) and the FP64 C oracle's "
+                                          f"map and integrand, {dt:.1f} s"}
     print(json.dumps(line), flush=True)
 
 

@@ -200,6 +200,8 @@ int vegas_set_launch(vegas_handle h, int32_t waves_per_block, int32_t max_blocks
  * and a short one may not.  vegas_stage_times waits for the stream and returns
  * the summed kernel milliseconds ms[4] and kernel counts launches[4] per stage
  * (host arrays, either nullable) since the last reset; reset != 0 clears them.
+ * vegas_grad's kernels count in the same stages: its event kernel as events,
+ * its tree reduction as fold, its output kernel as finalisation.
  * Errors: VEGAS_EINVAL (stages outside 0 .. VEGAS_TIME_ALL). */
 enum {
   VEGAS_TIME_EVENTS = 1, VEGAS_TIME_FOLD = 2, VEGAS_TIME_FINAL = 4, VEGAS_TIME_REFINE = 8,

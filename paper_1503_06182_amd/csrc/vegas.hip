@@ -1502,8 +1502,12 @@ int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_ev
     occ = 1;
   int64_t blocks = static_cast<int64_t>(h->ncu) * occ;
   if (blocks > groups) blocks = groups;
-  hipLaunchKernelGGL(k_dy_grad, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, h->stream, ga);
-  VG_HIP(hipGetLastError());
+  {
+    TimedLaunch t(h, 0);  // timed as the events stage
+    hipExtLaunchKernelGGL(k_dy_grad, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, h->stream, t.e0, t.e1, 0,
+                          ga);
+    VG_HIP(t.done());
+  }
   // fixed tree over tiles: 256-row chunks, level by level, ping-pong between the buffers
   const double* in = tiles;
   double* out = lvl;
@@ -1511,15 +1515,20 @@ int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_ev
   while (rows > 1) {
     const int64_t rout = (rows + kTreeRows - 1) / kTreeRows;
     const int gy = cols < 64 ? cols : 64;
-    hipLaunchKernelGGL(k_tree_level, dim3(static_cast<unsigned>(rout), gy), dim3(kTreeRows), 0, h->stream, in, out,
-                       rows, cols);
-    VG_HIP(hipGetLastError());
+    TimedLaunch t(h, 1);  // timed as the fold stage
+    hipExtLaunchKernelGGL(k_tree_level, dim3(static_cast<unsigned>(rout), gy), dim3(kTreeRows), 0, h->stream, t.e0,
+                          t.e1, 0, in, out, rows, cols);
+    VG_HIP(t.done());
     rows = rout;
     in = out;
     out = (out == lvl) ? tiles : lvl;
   }
-  hipLaunchKernelGGL(k_grad_out, dim3(1), dim3(64), 0, h->stream, in, B, n_events, sigma_dev, dsigma_dev);
-  VG_HIP(hipGetLastError());
+  {
+    TimedLaunch t(h, 2);  // timed as the finalisation stage
+    hipExtLaunchKernelGGL(k_grad_out, dim3(1), dim3(64), 0, h->stream, t.e0, t.e1, 0, in, B, n_events, sigma_dev,
+                          dsigma_dev);
+    VG_HIP(t.done());
+  }
   return VEGAS_OK;
 }
 

@@ -364,3 +364,39 @@ def test_full_size_sampled_parity_ww(P, prec):
     assert rel(r["I"], mean) < 1e-12
     assert rel(r["var"], var) < 1e-9
     assert r["n_events"] == n and r["n_nonzero"] == int(np.count_nonzero(wg))
+
+
+def test_stage_timing_and_launch_shape(P):
+    """Kernel timing per stage: only the selected stages are timed (one event-kernel,
+    one column-sum and one finalisation launch per iteration after the first), the
+    times are positive, timing changes no result, and the reported launch shape is
+    the one the iteration used."""
+    cfg = W.config("w_plus")
+    n = 100_000
+    g, _ = make_pair(P, cfg, n)
+    h = make_pair(P, cfg, n)[0]
+    for x in (g, h):
+        x.iterate(n)
+        x.refine()
+    g.set_timing(True, stages=("event",))
+    g.stage_times(reset=True)
+    ra = [g.iterate(n) for _ in range(2)]
+    st = g.stage_times(reset=True)
+    assert st["event"][1] == 2 and st["event"][0] > 0
+    assert st["fold"][1] == st["finalize"][1] == st["refine"][1] == 0
+    g.set_timing(True)
+    g.iterate(n)
+    st = g.stage_times(reset=True)
+    assert st["event"][1] == st["fold"][1] == st["finalize"][1] == 1
+    g.set_timing(False)
+    g.iterate(n)
+    assert sum(v[1] for v in g.stage_times().values()) == 0
+    rb = [h.iterate(n) for _ in range(2)]
+    assert [r["I"] for r in ra] == [r["I"] for r in rb] and [r["var"] for r in ra] == [r["var"] for r in rb]
+    shape = g.last_launch()
+    assert shape["threads"] % 64 == 0 and shape["event_blocks"] >= 1
+    assert shape["fold_cols"] == 3 * (2 + cfg["ndim"] * cfg["nbins"])
+    assert 1 <= shape["fold_rows"] <= 1024
+    from paper_1503_06182_amd import vegas as V
+    assert g._L.vegas_set_timing(g._h, 16) == V.EINVAL     # a stage mask outside 0..15
+    assert g._L.vegas_set_timing(g._h, -1) == V.EINVAL
