@@ -211,19 +211,31 @@ __global__ __launch_bounds__(256) void k_dy_grad(GradArgs a) {
 }
 
 // one level of the fixed tree: rows [256 c, 256 c + 256) of every column -> row c
-// (stride-halving pairwise sums over a zero-padded chunk; blockDim must be 256)
+// (stride-halving pairwise sums over a zero-padded chunk; blockDim must be 256).
+// Block (c, y) stages the chunk's rows of 16 columns at a time in LDS -- each row's
+// 16 doubles are one contiguous 128-byte load -- and then adds, per column, exactly
+// the pairs the stride-halving order prescribes.
+constexpr int kTreeCols = 16;
 __global__ __launch_bounds__(256) void k_tree_level(const double* in, double* out, int64_t rows, int cols) {
-  __shared__ double s[kTreeRows];
+  __shared__ double s[kTreeRows][kTreeCols + 1];  // +1: the column sums read across rows
   const int64_t chunk = blockIdx.x;
-  for (int c = blockIdx.y; c < cols; c += gridDim.y) {
-    const int64_t r = chunk * kTreeRows + threadIdx.x;
-    s[threadIdx.x] = r < rows ? in[r * cols + c] : 0.0;
+  const int tid = threadIdx.x, cc = tid % kTreeCols, rr = tid / kTreeCols;
+  for (int c0 = blockIdx.y * kTreeCols; c0 < cols; c0 += gridDim.y * kTreeCols) {
+    const int c = c0 + cc;
+#pragma unroll 4
+    for (int r = rr; r < kTreeRows; r += kTreeRows / kTreeCols) {
+      const int64_t row = chunk * kTreeRows + r;
+      s[r][cc] = row < rows && c < cols ? in[row * cols + c] : 0.0;
+    }
     __syncthreads();
     for (int stride = kTreeRows / 2; stride > 0; stride >>= 1) {
-      if (threadIdx.x < stride) s[threadIdx.x] += s[threadIdx.x + stride];
+      for (int i = tid; i < stride * kTreeCols; i += kTreeRows) {
+        const int r = i / kTreeCols, q = i % kTreeCols;
+        s[r][q] += s[r + stride][q];
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[chunk * cols + c] = s[0];
+    if (tid < kTreeCols && c0 + tid < cols) out[chunk * cols + c0 + tid] = s[0][tid];
     __syncthreads();
   }
 }

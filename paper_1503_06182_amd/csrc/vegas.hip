@@ -1514,7 +1514,7 @@ int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_ev
   int64_t rows = ntiles;
   while (rows > 1) {
     const int64_t rout = (rows + kTreeRows - 1) / kTreeRows;
-    const int gy = cols < 64 ? cols : 64;
+    const int tiles_c = (cols + kTreeCols - 1) / kTreeCols, gy = tiles_c < 64 ? tiles_c : 64;
     TimedLaunch t(h, 1);  // timed as the fold stage
     hipExtLaunchKernelGGL(k_tree_level, dim3(static_cast<unsigned>(rout), gy), dim3(kTreeRows), 0, h->stream, t.e0,
                           t.e1, 0, in, out, rows, cols);
