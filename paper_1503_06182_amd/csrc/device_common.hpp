@@ -98,6 +98,18 @@ __device__ __forceinline__ void fx_digits(double v, int E, long long& d0, long l
   d2 = a2;
 }
 
+// the same digits for a value known to be >= 0 (w^2 of a finite weight): no sign
+__device__ __forceinline__ void fx_digits_pos(double v, int E, long long& d0, long long& d1, long long& d2) {
+  const double X = fmin(ldexp(v, FX_BITS - E), 0x1p95);
+  const double h = trunc(X * 0x1p-64);
+  const double r = __fma_rn(-h, 0x1p64, X);
+  const double m = trunc(r * 0x1p-32);
+  const double l = trunc(__fma_rn(-m, 0x1p32, r));
+  d2 = static_cast<long long>(static_cast<uint32_t>(h));
+  d1 = static_cast<long long>(static_cast<uint32_t>(m));
+  d0 = static_cast<long long>(static_cast<uint32_t>(l));
+}
+
 // digit sums -> double, (D2 2^64 + D1 2^32 + D0) 2^(E-94), after carry normalisation
 __host__ __device__ __forceinline__ double fx_value(long long D0, long long D1, long long D2, int E) {
   long long c = D0 >> 32;  // arithmetic shift: floor division by 2^32

@@ -126,7 +126,7 @@ __device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls,
   ls.v[0] += d0;
   ls.v[1] += d1;
   ls.v[2] += d2;
-  fx_digits(w * w, E2, h0, h1, h2);
+  fx_digits_pos(w * w, E2, h0, h1, h2);  // w^2 of a finite weight: >= 0
   ls.v[3] += h0;
   ls.v[4] += h1;
   ls.v[5] += h2;
