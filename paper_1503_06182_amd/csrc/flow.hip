@@ -71,7 +71,7 @@ __global__ void k_flow_init(float* master, uint64_t seed) {
 __device__ __forceinline__ void mlp_tile32(const float* __restrict__ m, const uint16_t* __restrict__ w,
                                            const float (*cond)[4], uint16_t* h1, uint16_t* h2, float* par) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  mlp_h1(load_h1_unit(m), cond, h1, FL_TILE);
+  mlp_h1(load_h1_frag(m, wave, lane), cond, h1, FL_TILE);
   __syncthreads();
   // h2: 2 row blocks x 8 column blocks; wave w owns column blocks 2w, 2w+1
   for (int rb = 0; rb < 2; ++rb)
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
     const int col = (3 * wave + cc) * 16 + (lane & 15);
     bias3[cc] = col < FL_NOUT ? m[FO_B3 + col] : 0.f;
   }
-  const H1Unit u1 = load_h1_unit(m);
+  const H1Frag u1 = load_h1_frag(m, wave, lane);
   const int ri = lane & 15, kq = 4 * (lane >> 4), kq8 = 8 * (lane >> 4);
   for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE_F; e0 < B;
        e0 += static_cast<int64_t>(gridDim.x) * FL_TILE_F) {

@@ -59,26 +59,48 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(stati
 // spline parameters are rounded to binary16 (round to nearest even) in both directions
 __device__ __forceinline__ float round_h(float x) { return static_cast<float>(static_cast<_Float16>(x)); }
 
-// first MLP layer: thread t of a block (blockDim a multiple of 128) owns hidden unit
-// j = t % 128, whose bias and four weights it keeps in registers
-struct H1Unit {
-  float b, w[4];
+// first MLP layer on the matrix cores, binary32 (K = the 4 conditioning inputs), by a
+// block of 4 waves: wave w computes hidden units [32 w, 32 w + 32) as two 16-unit tiles.
+// Tile (t, event rows r0 .. r0+15): h1^T = W1^T cond^T + b1 on v_mfma_f32_16x16x4_f32 --
+// lane l supplies W1[l/16][u0 + l%16] (A) and cond[r0 + l%16][l/16] (B), starts from
+// the biases of units u0 + 4(l/16) .. +3 and receives those four units of event
+// r0 + l%16, stored as four bf16 in one 8-byte write.
+struct H1Frag {
+  float w[2], b[2][4];
 };
 
-__device__ __forceinline__ H1Unit load_h1_unit(const float* __restrict__ m) {
-  const int j = threadIdx.x % FL_HID;
-  return H1Unit{m[FO_B1 + j], {m[FO_W1 + j], m[FO_W1 + FL_HID + j], m[FO_W1 + 2 * FL_HID + j], m[FO_W1 + 3 * FL_HID + j]}};
+__device__ __forceinline__ H1Frag load_h1_frag(const float* __restrict__ m, int wave, int lane) {
+  H1Frag f;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int u0 = (2 * wave + t) * 16;
+    f.w[t] = m[FO_W1 + (lane >> 4) * FL_HID + u0 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.b[t][j] = m[FO_B1 + u0 + 4 * (lane >> 4) + j];
+  }
+  return f;
 }
 
-// h1 of `rows` events (cond [rows][4] in LDS) -> bf16 in LDS (stride FL_LDA), by the whole
-// block; explicit fma order so every kernel gets the same bits
-__device__ __forceinline__ void mlp_h1(const H1Unit& u, const float (*cond)[4], uint16_t* h1, int rows) {
-  const int j = threadIdx.x % FL_HID;
-  for (int e = threadIdx.x / FL_HID; e < rows; e += blockDim.x / FL_HID) {
-    float a = u.b;
+// four binary32 values -> four bf16 (round to nearest even) in one 8-byte word
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+  return make_uint2(static_cast<uint32_t>(f2bf(a)) | (static_cast<uint32_t>(f2bf(b)) << 16),
+                    static_cast<uint32_t>(f2bf(c)) | (static_cast<uint32_t>(f2bf(d)) << 16));
+}
+
+// h1 of `rows` events (a multiple of 16; cond [rows][4] in LDS) -> bf16 in LDS (stride
+// FL_LDA); every kernel runs this same sequence, so h1 has the same bits everywhere
+__device__ __forceinline__ void mlp_h1(const H1Frag& f, const float (*cond)[4], uint16_t* h1, int rows) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < rows; r0 += 16) {
+    const float c = cond[r0 + (lane & 15)][lane >> 4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a = __fmaf_rn(cond[e][c], u.w[c], a);
-    h1[e * FL_LDA + j] = f2bf(fmaxf(a, 0.f));
+    for (int t = 0; t < 2; ++t) {
+      f32x4_t acc = {f.b[t][0], f.b[t][1], f.b[t][2], f.b[t][3]};
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w[t], c, acc, 0, 0, 0);
+      const int u = (2 * wave + t) * 16 + 4 * (lane >> 4);
+      *reinterpret_cast<uint2*>(h1 + (r0 + (lane & 15)) * FL_LDA + u) =
+          pack_bf16x4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
+    }
   }
 }
 
