@@ -76,6 +76,10 @@ def lib():
         L.ora_set_iteration.argtypes = [C.c_void_p, C.c_uint32]
         L.ora_get_iteration.argtypes = [C.c_void_p]
         L.ora_get_iteration.restype = C.c_uint32
+        L.ora_observable.argtypes = [C.c_int, C.c_int, _dp, _dp]
+        L.ora_observable.restype = C.c_double
+        L.ora_set_observable.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int]
+        L.ora_get_observable.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.ora_event_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_int64, C.c_int64, _dp, _u8p]
         L.ora_grid_map.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_double),
                                    np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")]
@@ -113,6 +117,12 @@ def integrand(process: int, params, x) -> float:
     p = _f64(params)
     x = _f64(x)
     return lib().ora_integrand(process, len(x), p, len(p), x)
+
+
+def observable(process: int, params, x) -> float:
+    x = _f64(x)
+    p = _f64(params) if len(params) else np.zeros(1)
+    return lib().ora_observable(process, len(x), p, x)
 
 
 def me_dy(params, shat, c, flavour):
@@ -194,6 +204,20 @@ class Vegas:
         if lib().ora_result_from(self._h, first, out) != 0:
             raise ValueError("no iteration, or first out of range")
         return {"I": out[0], "sigma": out[1], "chi2_dof": out[2], "n_iter": int(out[3])}
+
+    def set_observable(self, nbins, lo=0.0, hi=1.0, first=0):
+        if lib().ora_set_observable(self._h, nbins, lo, hi, first) != 0:
+            raise ValueError("invalid observable binning")
+        self.nobs = nbins
+
+    def get_observable(self):
+        """(last, last_err, comb, comb_err), each of nbins + 2 (under- and overflow
+        at the ends)."""
+        k = getattr(self, "nobs", 0) + 2
+        a = [np.zeros(k) for _ in range(4)]
+        if lib().ora_get_observable(self._h, *a) != 0:
+            raise RuntimeError("observable off, or no iteration yet")
+        return tuple(a)
 
     def get_grid(self):
         e = np.zeros((self.ndim, self.nbins + 1))

@@ -79,7 +79,8 @@ void ora_uniforms(uint64_t seed, uint32_t iter, uint64_t event, int ndim, double
 /* ======================================================================
  * Test integrands
  * ====================================================================== */
-static double f_gauss(int ndim, const double *par, const double *x) {
+static double f_gauss(int ndim, const double *par, const double *x, double *obs) {
+  if (obs) *obs = x[0];
   double mu = par[0], sg = par[1];
   double f = 1.0;
   for (int d = 0; d < ndim; ++d) {
@@ -90,7 +91,8 @@ static double f_gauss(int ndim, const double *par, const double *x) {
 }
 
 /* Genz (1984) families; par = {family, a[ndim], w[ndim]} */
-static double f_genz(int ndim, const double *par, const double *x) {
+static double f_genz(int ndim, const double *par, const double *x, double *obs) {
+  if (obs) *obs = x[0];
   int fam = (int)par[0];
   const double *a = par + 1, *w = par + 1 + ndim;
   double s = 0.0, f = 1.0;
@@ -215,11 +217,12 @@ double ora_sigmahat_dy(const double *params, double shat, int flavour) {
 /* C0 reading: x0 -> m^2 by Breit-Wigner(M_Z, G_Z) on [mlo^2, mhi^2];
  * x1 -> ln x1 = x1 * ln tau, x2 = tau / x1, Jacobian |ln tau| / S;
  * x2 -> cos(theta) of the l- along beam 1 = 2 x2 - 1.  Both beam orderings. */
-static double f_dy(const double *par, const double *x) {
+static double f_dy(const double *par, const double *x, double *obs) {
   phys P = unpack(par);
   double S = P.sqrts * P.sqrts;
   double m2, jbw;
   bw_map(P.mz, P.gz, P.mlo * P.mlo, P.mhi * P.mhi, x[0], &m2, &jbw);
+  if (obs) *obs = sqrt(m2); /* the lepton-pair mass */
   double tau = m2 / S;
   double L = log(tau);
   double l1 = x[1] * L, l2 = L - l1;
@@ -238,7 +241,7 @@ static double f_dy(const double *par, const double *x) {
  * <|M|^2> = g^4 |V|^2 uhat^2 / (12 |shat - M_W^2 + i M_W G_W|^2),
  * uhat = (p_u - p_e+)^2 = -shat (1 - cos(u, e+)) / 2.
  * Cuts on the e+ in the lab: pT > ptmin and |eta| < etamax. */
-static double f_w(const double *par, const double *x) {
+static double f_w(const double *par, const double *x, double *obs) {
   phys P = unpack(par);
   double S = P.sqrts * P.sqrts;
   double mhi = P.mhi > 0 ? P.mhi : P.sqrts;
@@ -259,6 +262,7 @@ static double f_w(const double *par, const double *x) {
   double Elab = gam * (p[0] + beta * p[3]);
   double pzlab = gam * (p[3] + beta * p[0]);
   double pt = sqrt(p[1] * p[1] + p[2] * p[2]);
+  if (obs) *obs = pt; /* the e+ transverse momentum (boost-invariant along z) */
   double eta = atanh(pzlab / Elab);
   if (!(pt > P.ptmin && fabs(eta) < P.etamax)) return 0.0;
   double g2 = 4.0 * PI * P.alpha / P.sw2;
@@ -595,10 +599,11 @@ double ora_ww_me2(const double *params, const double mom[6][4], double m2p, doub
   return creal(M * conj(M));
 }
 
-static double f_ww(const double *par, const double *x) {
+static double f_ww(const double *par, const double *x, double *obs) {
   phys P = unpack(par);
   double mom[6][4], m2p, m2m, jac;
   ora_ww_momenta(par, x, mom, &m2p, &m2m, &jac);
+  if (obs) *obs = m2p > 0.0 ? sqrt(m2p) : 0.0; /* the e+ nu mass */
   if (!(jac > 0.0)) return 0.0;
   double shat = P.sqrts * P.sqrts;
   double me = 0.0;
@@ -665,26 +670,40 @@ int ora_ndim(int process, int ndim_requested) {
 
 /* e+e- -> mu+mu-: x0 -> cos(theta) = 2 x0 - 1, x1 -> phi = 2 pi x1; <|M|^2> from
  * explicit Dirac currents; flux 1/(2s), dPhi_2 = dOmega / (32 pi^2). */
-static double f_eemumu(const double *par, const double *x) {
+static double f_eemumu(const double *par, const double *x, double *obs) {
   phys P = unpack(par);
   double s = P.sqrts * P.sqrts;
   double c = 2.0 * x[0] - 1.0, phi = 2.0 * PI * x[1];
+  if (obs) *obs = c; /* cos(theta) of the mu- */
   double me = ora_me_eemumu_dirac(par, s, c, phi);
   return P.conv * (1.0 / (2.0 * s)) * me * (4.0 * PI) / (32.0 * PI * PI);
+}
+
+/* The integrand at x; obs (nullable) receives the process's observable: x_0
+ * (test integrands), cos(theta) of the mu- (e+e-), the lepton-pair mass (Drell-Yan),
+ * the e+ transverse momentum (W+), the e+ nu mass (W+W-). */
+static double integrand_obs(int process, int ndim, const double *params, const double *x, double *obs) {
+  switch (process) {
+    case ORA_GAUSS: return f_gauss(ndim, params, x, obs);
+    case ORA_GENZ: return f_genz(ndim, params, x, obs);
+    case ORA_EEMUMU: return f_eemumu(params, x, obs);
+    case ORA_DY_Z: return f_dy(params, x, obs);
+    case ORA_W_PLUS: return f_w(params, x, obs);
+    case ORA_WW_4L: return f_ww(params, x, obs);
+    default: return NAN;
+  }
 }
 
 double ora_integrand(int process, int ndim, const double *params, int nparams,
                      const double *x) {
   (void)nparams;
-  switch (process) {
-    case ORA_GAUSS: return f_gauss(ndim, params, x);
-    case ORA_GENZ: return f_genz(ndim, params, x);
-    case ORA_EEMUMU: return f_eemumu(params, x);
-    case ORA_DY_Z: return f_dy(params, x);
-    case ORA_W_PLUS: return f_w(params, x);
-    case ORA_WW_4L: return f_ww(params, x);
-    default: return NAN;
-  }
+  return integrand_obs(process, ndim, params, x, NULL);
+}
+
+double ora_observable(int process, int ndim, const double *params, const double *x) {
+  double o = NAN;
+  integrand_obs(process, ndim, params, x, &o);
+  return o;
 }
 
 /* ======================================================================
@@ -703,6 +722,14 @@ struct ora_state {
   uint32_t iter;
   int n_iter, cap;
   double *Ij, *varj;
+  /* observable histogram: nobs uniform bins on [lo, hi) plus under- and overflow */
+  int nobs, obs_first, obs_have;
+  double obs_lo, obs_hi;
+  long double obs_s1[ORA_MAX_OBS + 2], obs_s2[ORA_MAX_OBS + 2];
+  double obs_last[ORA_MAX_OBS + 2], obs_last_err[ORA_MAX_OBS + 2];
+  long double obs_acc_w[ORA_MAX_OBS + 2], obs_acc_v[ORA_MAX_OBS + 2], obs_zacc[ORA_MAX_OBS + 2];
+  long double obs_wsum;
+  int obs_zcount;
 };
 
 ora_state *ora_create(int process, int ndim, int nbins, uint64_t seed, double alpha,
@@ -761,12 +788,25 @@ int ora_grid_map(const ora_state *s, const double *u, double *x, double *jac, in
   return 0;
 }
 
-static double event_weight(const ora_state *s, uint32_t iter, uint64_t i, int *bins) {
+static double event_weight_obs(const ora_state *s, uint32_t iter, uint64_t i, int *bins, double *obs) {
   double u[16], x[16], J;
   ora_uniforms(s->seed, iter, i, s->ndim, u);
   grid_map(s, u, x, &J, bins);
-  double f = ora_integrand(s->process, s->ndim, s->params, s->nparams, x);
+  double f = integrand_obs(s->process, s->ndim, s->params, x, obs);
   return J * f;
+}
+
+static double event_weight(const ora_state *s, uint32_t iter, uint64_t i, int *bins) {
+  return event_weight_obs(s, iter, i, bins, NULL);
+}
+
+/* bin of observable value o: 1 .. nobs for lo <= o < hi (uniform width), 0 below,
+ * nobs + 1 at or above hi (and for a value that is not a number) */
+static int obs_bin(const ora_state *s, double o) {
+  if (o < s->obs_lo) return 0;
+  if (!(o < s->obs_hi)) return s->nobs + 1;
+  int b = (int)floor((o - s->obs_lo) * ((double)s->nobs / (s->obs_hi - s->obs_lo))) + 1;
+  return b > s->nobs ? s->nobs : b;
 }
 
 int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t n,
@@ -791,14 +831,22 @@ int ora_iterate(ora_state *s, int64_t n, double out[4]) {
   long double s1 = 0.0L, s2 = 0.0L;
   int64_t nz = 0, nnf = 0;
   int b[16];
+  const int nob = s->nobs ? s->nobs + 2 : 0;
+  for (int k = 0; k < nob; ++k) s->obs_s1[k] = s->obs_s2[k] = 0.0L;
   for (int64_t i = 0; i < n; ++i) {
-    double w = event_weight(s, s->iter, (uint64_t)i, b);
+    double o = 0.0;
+    double w = event_weight_obs(s, s->iter, (uint64_t)i, b, s->nobs ? &o : NULL);
     if (!isfinite(w)) { ++nnf; continue; }
     if (w != 0.0) ++nz;
     double w2 = w * w;
     s1 += w;
     s2 += w2;
     for (int d = 0; d < D; ++d) s->d[d * nb + b[d]] += w2;
+    if (s->nobs) {
+      int k = obs_bin(s, o);
+      s->obs_s1[k] += w;
+      s->obs_s2[k] += w2;
+    }
   }
   s->s1 = s1;
   s->s2 = s2;
@@ -812,6 +860,31 @@ int ora_iterate(ora_state *s, int64_t n, double out[4]) {
   }
   s->Ij[s->n_iter] = mean;
   s->varj[s->n_iter] = var;
+  if (s->nobs) {
+    /* this iteration's histogram (sum of w / n per bin) and its error; iterations
+     * from obs_first on enter the combination with the weights of the integral
+     * (1 / var_j), or as a plain mean if some iteration has zero variance */
+    for (int k = 0; k < nob; ++k) {
+      long double h = s->obs_s1[k] / (long double)n;
+      long double v = (s->obs_s2[k] / (long double)n - h * h) / (long double)(n - 1);
+      s->obs_last[k] = (double)h;
+      s->obs_last_err[k] = (double)sqrtl(v > 0.0L ? v : 0.0L);
+      if ((int)s->iter >= s->obs_first) {
+        if (var > 0.0) {
+          long double wj = 1.0L / (long double)var;
+          s->obs_acc_w[k] += wj * h;
+          s->obs_acc_v[k] += wj * wj * v;
+        } else {
+          s->obs_zacc[k] += h;
+        }
+      }
+    }
+    if ((int)s->iter >= s->obs_first) {
+      if (var > 0.0) s->obs_wsum += 1.0L / (long double)var;
+      else s->obs_zcount++;
+    }
+    s->obs_have = 1;
+  }
   s->n_iter++;
   s->iter++;
   out[0] = mean;
@@ -936,6 +1009,42 @@ int ora_result_from(const ora_state *s, int first, double out[4]) {
 
 /* All iterations so far. */
 int ora_result(const ora_state *s, double out[4]) { return ora_result_from(s, 0, out); }
+
+/* Observable histogram: nbins uniform bins on [lo, hi) plus under- and overflow
+ * (nbins = 0 turns it off); iterations from `first` (the iteration counter) on are
+ * combined.  Clears the combination. */
+int ora_set_observable(ora_state *s, int nbins, double lo, double hi, int first) {
+  if (nbins < 0 || nbins > ORA_MAX_OBS || (nbins > 0 && !(lo < hi)) || first < 0) return -1;
+  s->nobs = nbins;
+  s->obs_lo = lo;
+  s->obs_hi = hi;
+  s->obs_first = first;
+  s->obs_have = 0;
+  for (int k = 0; k < ORA_MAX_OBS + 2; ++k) s->obs_acc_w[k] = s->obs_acc_v[k] = s->obs_zacc[k] = 0.0L;
+  s->obs_wsum = 0.0L;
+  s->obs_zcount = 0;
+  return 0;
+}
+
+/* last iteration's histogram and error, and the combination and its error
+ * (arrays of nbins + 2, each nullable); -2 before any iteration with it on */
+int ora_get_observable(const ora_state *s, double *last, double *last_err, double *comb, double *comb_err) {
+  if (!s->nobs || !s->obs_have) return -2;
+  for (int k = 0; k < s->nobs + 2; ++k) {
+    if (last) last[k] = s->obs_last[k];
+    if (last_err) last_err[k] = s->obs_last_err[k];
+    double c = 0.0, e = 0.0;
+    if (s->obs_zcount) {
+      c = (double)(s->obs_zacc[k] / s->obs_zcount);
+    } else if (s->obs_wsum > 0.0L) {
+      c = (double)(s->obs_acc_w[k] / s->obs_wsum);
+      e = (double)(sqrtl(s->obs_acc_v[k]) / s->obs_wsum);
+    }
+    if (comb) comb[k] = c;
+    if (comb_err) comb_err[k] = e;
+  }
+  return 0;
+}
 
 int ora_get_grid(const ora_state *s, double *edges) {
   memcpy(edges, s->edges, sizeof(double) * s->ndim * (s->nbins + 1));

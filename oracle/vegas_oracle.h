@@ -57,6 +57,10 @@ void ora_uniforms(uint64_t seed, uint32_t iter, uint64_t event, int ndim, double
 int ora_ndim(int process, int ndim_requested);
 double ora_integrand(int process, int ndim, const double *params, int nparams,
                      const double *x);
+/* the process's observable at x (x_0 for the test integrands, cos(theta) of the
+ * mu- for e+e-, the lepton-pair mass for Drell-Yan, the e+ transverse momentum
+ * for W+, the e+ nu mass for W+W-) */
+double ora_observable(int process, int ndim, const double *params, const double *x);
 
 /* ---- physics building blocks exposed for the tests ---- */
 double ora_me_dy(const double *params, double shat, double c, int flavour);   /* <|M|^2> */
@@ -86,6 +90,14 @@ int ora_set_grid(ora_state *s, const double *edges);
 int ora_get_hist(const ora_state *s, double *d, double sums[2]);
 int ora_set_iteration(ora_state *s, uint32_t iter);
 uint32_t ora_get_iteration(const ora_state *s);
+/* observable histograms: nbins (<= ORA_MAX_OBS) uniform bins on [lo, hi) plus
+ * an underflow (index 0) and an overflow (index nbins + 1) bin; each iteration's
+ * per-bin sum of w / N with its error; iterations numbered >= first are combined
+ * with the integral's weights 1 / var_j.  nbins = 0 turns it off. */
+#define ORA_MAX_OBS 254
+int ora_set_observable(ora_state *s, int nbins, double lo, double hi, int first);
+int ora_get_observable(const ora_state *s, double *last, double *last_err, double *comb,
+                       double *comb_err);
 /* weights (and bin indices, [n][ndim]) of events [first, first+n) of iteration iter at the current grid */
 int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t n,
                       double *w, uint8_t *bins);
