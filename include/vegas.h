@@ -74,6 +74,7 @@ enum {
 #define VEGAS_MAX_BINS 255
 #define VEGAS_MAX_PARAMS 64
 #define VEGAS_MAX_ITER 4096
+#define VEGAS_MAX_OBS_BINS 254
 
 typedef struct {
   int32_t process;         /* vegas_process                                          */
@@ -163,6 +164,34 @@ int vegas_result(vegas_handle h, double *integral, double *error, double *chi2_d
 int vegas_result_from(vegas_handle h, int32_t first, double *integral, double *error,
                       double *chi2_dof, int32_t *n_iter);
 
+/* Histogram of the process's observable, filled by the same events and weights
+ * as the integral (Sec. 2.1: every event of an iteration serves all of its
+ * outputs; the timing runs of Sec. 3.2 fill observables alongside the total).
+ * The observable: x_0 (GAUSS, GENZ), cos(theta) of the mu- (EEMUMU), the
+ * lepton-pair mass (DY_Z), the e+ transverse momentum, taken before the cuts
+ * (W_PLUS), the e+ nu mass (WW_4L).  nbins (0..VEGAS_MAX_OBS_BINS; 0 turns it
+ * off) uniform bins on [lo, hi) (finite, lo < hi), plus an underflow bin
+ * (index 0, below lo) and an overflow bin (index nbins + 1, at or above hi);
+ * an event falls in bin floor((o - lo) * (nbins / (hi - lo))) + 1, the factor
+ * rounded once.  Each bin is the iteration's sum of w over its events divided
+ * by N, with error sqrt((S2_b / N - H_b^2) / (N - 1)); its sums are exact and
+ * launch-independent like the total's.  Iterations numbered >= first_iteration
+ * (the iteration counter) are combined bin by bin with the integral's weights
+ * 1 / var_j (the plain mean if an iteration has zero variance), so the bins of
+ * the combination add up to the combined integral over the same iterations.
+ * Clears the combination; takes effect from the next iteration.  Records one
+ * byte per event and six digit columns per bin.
+ * Errors: VEGAS_EINVAL. */
+int vegas_set_observable(vegas_handle h, int32_t nbins, double lo, double hi,
+                         int32_t first_iteration);
+
+/* Last iteration's histogram and its errors, and the combination and its errors:
+ * host arrays of nbins + 2 (underflow first, overflow last), each nullable.
+ * Waits for the stream.  Errors: VEGAS_ESTATE (no observable set, or no
+ * iteration since it was set or since vegas_set_state). */
+int vegas_get_observable(vegas_handle h, double *last, double *last_err, double *comb,
+                         double *comb_err);
+
 /* Grid edges, host array [ndim][nbins+1] (waits for the stream). */
 int vegas_get_grid(vegas_handle h, double *edges);
 /* Replace the grid (host [ndim][nbins+1]; e_0 = 0, e_n = 1, non-decreasing).
@@ -181,6 +210,8 @@ int vegas_get_weights(vegas_handle h, int64_t first, int64_t n, double *w, uint8
 /* Checkpoint: grid, iteration counter and the per-iteration estimates.
  * vegas_get_state with buf == NULL sets *bytes to the size needed.  A restored
  * handle continues bit-identically, because events are keyed by (seed, j, i).
+ * The observable histogram is not part of it: vegas_set_state keeps the
+ * handle's binning and clears the combination.
  * Errors: VEGAS_EINVAL (size or configuration mismatch). */
 int vegas_get_state(vegas_handle h, void *buf, size_t *bytes);
 int vegas_set_state(vegas_handle h, const void *buf, size_t bytes);

@@ -805,8 +805,8 @@ static double event_weight(const ora_state *s, uint32_t iter, uint64_t i, int *b
 static int obs_bin(const ora_state *s, double o) {
   if (o < s->obs_lo) return 0;
   if (!(o < s->obs_hi)) return s->nobs + 1;
-  int b = (int)floor((o - s->obs_lo) * ((double)s->nobs / (s->obs_hi - s->obs_lo))) + 1;
-  return b > s->nobs ? s->nobs : b;
+  double t = floor((o - s->obs_lo) * ((double)s->nobs / (s->obs_hi - s->obs_lo)));
+  return t < (double)s->nobs ? (int)t + 1 : s->nobs; /* the last bin holds [hi - width, hi) */
 }
 
 int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t n,
@@ -1014,7 +1014,9 @@ int ora_result(const ora_state *s, double out[4]) { return ora_result_from(s, 0,
  * (nbins = 0 turns it off); iterations from `first` (the iteration counter) on are
  * combined.  Clears the combination. */
 int ora_set_observable(ora_state *s, int nbins, double lo, double hi, int first) {
-  if (nbins < 0 || nbins > ORA_MAX_OBS || (nbins > 0 && !(lo < hi)) || first < 0) return -1;
+  if (nbins < 0 || nbins > ORA_MAX_OBS || first < 0) return -1;
+  if (nbins > 0 && !(isfinite(lo) && isfinite(hi) && lo < hi && isfinite((double)nbins / (hi - lo))))
+    return -1;
   s->nobs = nbins;
   s->obs_lo = lo;
   s->obs_hi = hi;

@@ -152,9 +152,11 @@ __device__ __forceinline__ double f_eemumu(const PhysConst& c, const double* x) 
 // q qbar -> photon/Z -> l- l+ (both beam orderings).  With one PDF for all
 // four flavours the two orderings sum to sum_{hh'} |A_hh'|^2 * 2 (1 + c^2).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
+// obs_sq: the square of the observable, the lepton-pair mass m_ll^2
+__device__ __forceinline__ double f_dy(const PhysConst& c, const double* x, double& obs_sq) {
   double jbw;
   const double m2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  obs_sq = m2;
   double L, l1, l2;
   {
 #pragma clang fp contract(off)
@@ -191,7 +193,8 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x) {
 // boost-invariant pT^2 = (shat/4)(1 - c^2) and the lab polar cosine
 // (c + beta)/(1 + beta c), beta = (x1 - x2)/(x1 + x2).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
+// obs_sq: the square of the observable, the e+ transverse momentum (taken before the cuts)
+__device__ __forceinline__ double f_w(const PhysConst& c, const double* x, double& obs_sq) {
   double jbw;
   const double m2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
   double L, l1, l2;
@@ -206,6 +209,7 @@ __device__ __forceinline__ double f_w(const PhysConst& c, const double* x) {
   // x = 1 + expm1(ln x): beta = (x1 - x2)/(x1 + x2) and 1 - x from the same two values
   const double em1 = expm1(l1), em2 = expm1(l2);
   const double pt2 = 0.25 * m2 * (1.0 - cs) * (1.0 + cs);
+  obs_sq = pt2;
   const double beta = (em1 - em2) / (2.0 + em1 + em2);
   const double num = cs + beta, dnm = 1.0 + beta * cs;
   const bool pass = (pt2 > c.ptmin2) && (num * num < c.th2 * dnm * dnm);
@@ -408,10 +412,12 @@ __device__ __forceinline__ void sincos_2pi(float x, float& s, float& c) { sincos
 // x2, x3 -> W+ direction, x4..x7 -> lepton directions in the W rest frames.
 // Phase space (masses, momenta, lambda, Jacobian) is binary64; only the
 // amplitude (spinors, currents, diagrams) is evaluated in R.
+// obs_sq: the square of the observable, the e+ nu mass m_+^2 (0 where the map gives none)
 template <typename R>
-__device__ __forceinline__ double f_ww(const PhysConst& c, const double* x) {
+__device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, double& obs_sq) {
   double jp, jm;
   const double mp2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jp);
+  obs_sq = mp2 > 0.0 ? mp2 : 0.0;
   if (!(mp2 > 0.0)) return 0.0;
   const double mp = sqrt(mp2);
   const double up = (c.rs - mp) * (c.rs - mp);

@@ -47,6 +47,9 @@ constexpr int kMaxRowsAcc = 1024;       // cap on accumulation blocks (rows of t
 // is aligned to the 128-byte lines it is fetched in
 __host__ __device__ constexpr int part_ld(int ncol) { return (ncol + 31) & ~31; }
 constexpr int kFusedLdsMax = 48 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
+// observable histogram: bins 1..nobs uniform on [lo, hi), 0 = underflow, nobs + 1 = overflow
+constexpr int kObsLd = VEGAS_MAX_OBS_BINS + 2;
+__host__ __device__ constexpr int obs_cols(int nobs) { return nobs > 0 ? 6 * (nobs + 2) : 0; }
 
 struct DevBufs {
   double* edges;                 // [D][n+1] current grid
@@ -59,6 +62,10 @@ struct DevBufs {
   long long* part_acc;           // [rows][part_ld(3*(2+D*n))] per-block digit sums: S1, S2, d[...]
   long long* acc_tot;            // [3*(2+D*n)] digit sums over all blocks
   double* hist;                  // [D*n + 2] d, S1, S2 of the last iteration
+  uint8_t* rec_obs;              // [maxN] observable bin of each event (with an observable set)
+  double* obs_acc;               // [3 kObsLd + 2] combination: sum w_j H, sum w_j^2 var, sum H (zero-variance
+                                 //   iterations), then sum w_j and the count of zero-variance iterations
+  double* obs_out;               // [4][kObsLd] last H, its error, the combination, its error
   double* history;               // [VEGAS_MAX_ITER][2] I_j, var_j
   double* iter_out;              // [8] I_j, var_j, nz, nnf, N
   double* result;                // [4] I, sigma, chi2/dof, n_iter
@@ -92,15 +99,44 @@ __device__ __forceinline__ double grid_map(const double* __restrict__ e_lds, int
   return J;
 }
 
+// q: the process's observable (x_0, cos(theta) of the mu-), or its square (m_ll,
+// the e+ p_T, the e+ nu mass), see obs_is_square
 template <int PROC, int PREC, int D>
-__device__ __forceinline__ double integrand(const PhysConst& c, const double* x) {
-  if constexpr (PROC == VEGAS_GAUSS) return f_gauss<D>(c, x);
-  else if constexpr (PROC == VEGAS_GENZ) return f_genz<D>(c, x);
-  else if constexpr (PROC == VEGAS_EEMUMU) return f_eemumu(c, x);
-  else if constexpr (PROC == VEGAS_DY_Z) return f_dy(c, x);
-  else if constexpr (PROC == VEGAS_W_PLUS) return f_w(c, x);
-  else if constexpr (PREC == VEGAS_FP32_ME) return f_ww<float>(c, x);
-  else return f_ww<double>(c, x);
+__device__ __forceinline__ double integrand(const PhysConst& c, const double* x, double& q) {
+  if constexpr (PROC == VEGAS_GAUSS) {
+    q = x[0];
+    return f_gauss<D>(c, x);
+  } else if constexpr (PROC == VEGAS_GENZ) {
+    q = x[0];
+    return f_genz<D>(c, x);
+  } else if constexpr (PROC == VEGAS_EEMUMU) {
+    q = 2.0 * x[0] - 1.0;
+    return f_eemumu(c, x);
+  } else if constexpr (PROC == VEGAS_DY_Z) {
+    return f_dy(c, x, q);
+  } else if constexpr (PROC == VEGAS_W_PLUS) {
+    return f_w(c, x, q);
+  } else if constexpr (PREC == VEGAS_FP32_ME) {
+    return f_ww<float>(c, x, q);
+  } else {
+    return f_ww<double>(c, x, q);
+  }
+}
+
+template <int PROC>
+constexpr bool obs_is_square() {
+  return PROC == VEGAS_DY_Z || PROC == VEGAS_W_PLUS || PROC == VEGAS_WW_4L;
+}
+
+// bin of an observable value o: 0 below lo, nobs + 1 at or above hi (and for a NaN),
+// else floor((o - lo) nobs / (hi - lo)) + 1 with scale = nobs / (hi - lo) rounded once,
+// at most nobs (the clamp is taken in binary64, so the index stays in 0 .. nobs + 1
+// whatever the product)
+__device__ __forceinline__ int obs_bin(double o, double lo, double hi, double scale, int nobs) {
+  if (o < lo) return 0;
+  if (!(o < hi)) return nobs + 1;
+  const double t = floor((o - lo) * scale);
+  return t < static_cast<double>(nobs) ? static_cast<int>(t) + 1 : nobs;
 }
 
 // ---------------------------------------------------------------------------
@@ -118,10 +154,9 @@ __device__ __forceinline__ void lane_sums_zero(LaneSums& ls) {
   for (int k = 0; k < 6; ++k) ls.v[k] = 0;
 }
 
-// S1, S2 digits of w; returns the digits of w^2 for the histogram
-__device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls, long long& h0, long long& h1,
-                                         long long& h2) {
-  long long d0, d1, d2;
+// S1, S2 digits of w; returns the digits of w (d) and of w^2 (h) for the histograms
+__device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls, long long& d0, long long& d1,
+                                         long long& d2, long long& h0, long long& h1, long long& h2) {
   fx_digits(w, E1, d0, d1, d2);
   ls.v[0] += d0;
   ls.v[1] += d1;
@@ -137,6 +172,18 @@ __device__ __forceinline__ void acc_hist(long long* acc, int col, long long h0, 
   if (h0) atomicAdd(p + 0, static_cast<unsigned long long>(h0));
   if (h1) atomicAdd(p + 1, static_cast<unsigned long long>(h1));
   if (h2) atomicAdd(p + 2, static_cast<unsigned long long>(h2));
+}
+
+// observable bin: the digits of w, then those of w^2
+__device__ __forceinline__ void acc_obs(long long* acc, int col, long long d0, long long d1, long long d2,
+                                       long long h0, long long h1, long long h2) {
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + col);
+  if (d0) atomicAdd(p + 0, static_cast<unsigned long long>(d0));
+  if (d1) atomicAdd(p + 1, static_cast<unsigned long long>(d1));
+  if (d2) atomicAdd(p + 2, static_cast<unsigned long long>(d2));
+  if (h0) atomicAdd(p + 3, static_cast<unsigned long long>(h0));
+  if (h1) atomicAdd(p + 4, static_cast<unsigned long long>(h1));
+  if (h2) atomicAdd(p + 5, static_cast<unsigned long long>(h2));
 }
 
 // per-lane S1, S2 -> wave butterfly -> LDS columns 0..5 (call with the whole block)
@@ -160,6 +207,8 @@ struct EventArgs {
   int ndim, nbins;
   const float* ext_y;   // learned proposal: points y [nev][8] and log q(y) [nev] (EXT kernels only)
   const float* ext_lq;
+  int nobs;             // observable bins (OBS kernels only)
+  double obs_lo, obs_hi, obs_scale;
 };
 
 // ---------------------------------------------------------------------------
@@ -178,11 +227,14 @@ constexpr int event_min_waves() {
 // FUSED: the event also adds its exact digits at the scales fixed by the
 // previous iteration (b.fxs) and the block writes one row of partials; the
 // finalisation re-folds from the records if the scales turn out not to fit.
-template <int PROC, int PREC, int D, int MAXT, bool EXT = false, bool FUSED = false>
+// OBS: the event's observable bin is recorded (and, fused, its w and w^2 digits
+// go to that bin's six columns after the grid histogram's).
+template <int PROC, int PREC, int D, int MAXT, bool EXT = false, bool FUSED = false, bool OBS = false>
 __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) void k_event(EventArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.nbins, nd = D > 0 ? D : a.ndim;
-  const int ncol = 3 * (2 + nd * n);
+  const int ncol_h = 3 * (2 + nd * n);
+  const int ncol = ncol_h + (OBS ? obs_cols(a.nobs) : 0);
   double* e_lds = reinterpret_cast<double*>(smem);
   long long* acc = reinterpret_cast<long long*>(e_lds + nd * (n + 1));  // FUSED: [ncol]
   for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x) e_lds[i] = a.b.edges[i];
@@ -218,8 +270,14 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
       event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
     }
     const double J = grid_map<D>(e_lds, n, nd, u, x, bins);
-    const double f = integrand<PROC, PREC, D>(a.pc, x);
+    double q;
+    const double f = integrand<PROC, PREC, D>(a.pc, x, q);
     double w = J * f;
+    int obin = 0;
+    if constexpr (OBS) {
+      obin = obs_bin(obs_is_square<PROC>() ? sqrt(q) : q, a.obs_lo, a.obs_hi, a.obs_scale, a.nobs);
+      a.b.rec_obs[i] = static_cast<uint8_t>(obin);
+    }
     if constexpr (EXT) w *= exp(-static_cast<double>(a.ext_lq[i]));
     if (!isfinite(w * w)) {
       ++nnf;
@@ -241,13 +299,14 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     wmax = wb > wmax ? wb : wmax;
     if constexpr (FUSED) {
       if (w != 0.0) {
-        long long h0, h1, h2;
-        acc_sums(w, E1, E2, ls, h0, h1, h2);
+        long long d0, d1, d2, h0, h1, h2;
+        acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
 #pragma unroll
         for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
           if (d >= nd) break;
           acc_hist(acc, 3 * (2 + d * n + bins[d]), h0, h1, h2);
         }
+        if constexpr (OBS) acc_obs(acc, ncol_h + 6 * obin, d0, d1, d2, h0, h1, h2);
       }
     }
   }
@@ -295,16 +354,20 @@ struct AccArgs {
   int64_t stride_rec;
   int ndim, nbins;
   int dims_per_group;
+  int nobs;  // observable bins (the y == 0 blocks fold them with S1, S2)
 };
 
 __global__ void k_accum(AccArgs a) {
   extern __shared__ unsigned char smem[];
-  const int n = a.nbins, nd = a.ndim, ncol = 3 * (2 + nd * n);
+  const int n = a.nbins, nd = a.ndim, ncol_h = 3 * (2 + nd * n);
+  const int ncol = ncol_h + obs_cols(a.nobs);
   const int dlo = blockIdx.y * a.dims_per_group;
   const int dhi = min(nd, dlo + a.dims_per_group);
   const int lcol = 3 * (2 + (dhi - dlo) * n);
-  long long* acc = reinterpret_cast<long long*>(smem);  // [lcol]: S1, S2, d of the group's dimensions
-  for (int i = threadIdx.x; i < lcol; i += blockDim.x) acc[i] = 0;
+  const int ocol = blockIdx.y == 0 ? obs_cols(a.nobs) : 0;  // block-uniform
+  // [lcol]: S1, S2, d of the group's dimensions; then [ocol]: the observable's bins
+  long long* acc = reinterpret_cast<long long*>(smem);
+  for (int i = threadIdx.x; i < lcol + ocol; i += blockDim.x) acc[i] = 0;
   // one scale per quantity: 2^(94 - E) with |w| < 2^E1 and w^2 < 2^E2 for every event
   const double wmax = __longlong_as_double(static_cast<long long>(a.b.maxw[0]));
   const int E1 = fx_exponent(wmax);
@@ -317,14 +380,15 @@ __global__ void k_accum(AccArgs a) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
     const double w = a.b.rec_w[i];
     if (w == 0.0) continue;
-    long long h0, h1, h2;
-    acc_sums(w, E1, E2, ls, h0, h1, h2);
+    long long d0, d1, d2, h0, h1, h2;
+    acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
     // the same digits of w^2 go to the event's bin in every dimension
     for (int d = dlo; d < dhi; ++d) {
       const uint32_t word = a.b.rec_bins[(d >> 2) * a.stride_rec + i];
       const int bin = static_cast<int>((word >> (8 * (d & 3))) & 0xffu);
       acc_hist(acc, 3 * (2 + (d - dlo) * n + bin), h0, h1, h2);
     }
+    if (ocol) acc_obs(acc, lcol + 6 * static_cast<int>(a.b.rec_obs[i]), d0, d1, d2, h0, h1, h2);
   }
   acc_sums_to_lds(ls, acc);
   __syncthreads();
@@ -332,6 +396,7 @@ __global__ void k_accum(AccArgs a) {
   if (blockIdx.y == 0)
     for (int i = threadIdx.x; i < 6; i += blockDim.x) row[i] = acc[i];
   for (int i = threadIdx.x; i < lcol - 6; i += blockDim.x) row[3 * (2 + dlo * n) + i] = acc[6 + i];
+  for (int i = threadIdx.x; i < ocol; i += blockDim.x) row[ncol_h + i] = acc[lcol + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -353,6 +418,8 @@ struct FinArgs {
   int fused;
   int spec;      // also refine the grid into b.edges_alt (waves 0..D-1, one dimension each)
   int fold_lds;  // bytes of dynamic LDS before the refinement scratch (the re-fold's digits)
+  int obs_lds;   // byte offset of the observable scratch [2 (nobs + 2)] doubles
+  int nobs, obs_first;
   double alpha;
 };
 
@@ -362,7 +429,8 @@ __device__ __forceinline__ void refine_dim(bool active, bool preloaded, int n, d
 __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* smem) {
   __shared__ double s12[2];
   const DevBufs& b = f.b;
-  const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol = 3 * (2 + nslot);
+  const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol_h = 3 * (2 + nslot);
+  const int ncol = ncol_h + obs_cols(f.nobs);
   const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
   const unsigned long long nz = b.cnt[0], nnf = b.cnt[1];
   const int Ec1 = fx_exponent(wmax), Ec2 = fx_exponent(wmax * wmax);
@@ -391,19 +459,32 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     for (int64_t i = threadIdx.x; i < f.nev; i += blockDim.x) {
       const double w = b.rec_w[i];
       if (w == 0.0) continue;
-      long long h0, h1, h2;
-      acc_sums(w, E1, E2, ls, h0, h1, h2);
+      long long d0, d1, d2, h0, h1, h2;
+      acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
       for (int d = 0; d < nd; ++d) {
         const uint32_t word = b.rec_bins[(d >> 2) * f.stride_rec + i];
         acc_hist(acc, 3 * (2 + d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), h0, h1, h2);
       }
+      if (f.nobs) acc_obs(acc, ncol_h + 6 * static_cast<int>(b.rec_obs[i]), d0, d1, d2, h0, h1, h2);
     }
     acc_sums_to_lds(ls, acc);
     __syncthreads();
     tot = acc;
   }
-  for (int slot = threadIdx.x; slot < nslot + 2; slot += blockDim.x) {
+  // observable bins: slot nslot + 2 + 2k holds sum w of bin k (scale E1), the next
+  // one sum w^2 (scale E2); their values go to osm
+  double* osm = reinterpret_cast<double*>(smem + f.obs_lds);
+  const int nslot_all = nslot + 2 + (f.nobs ? 2 * (f.nobs + 2) : 0);
+  // the combination so far (read before the barrier that precedes its update)
+  const double ws_old = f.nobs ? b.obs_acc[3 * kObsLd] : 0.0;
+  const double zc_old = f.nobs ? b.obs_acc[3 * kObsLd + 1] : 0.0;
+  for (int slot = threadIdx.x; slot < nslot_all; slot += blockDim.x) {
     const long long* t = tot + 3 * slot;
+    if (slot >= nslot + 2) {
+      const int so = slot - (nslot + 2);
+      osm[so] = fx_value(t[0], t[1], t[2], (so & 1) ? E2 : E1);
+      continue;
+    }
     const double v = fx_value(t[0], t[1], t[2], slot == 0 ? E1 : E2);
     const int h = slot < 2 ? nslot + slot : slot - 2;
     b.hist[h] = v;
@@ -430,6 +511,50 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     b.maxw[0] = 0ull;
     b.cnt[0] = 0ull;
     b.cnt[1] = 0ull;
+  }
+  if (f.nobs) {
+    // per bin: H = S1_b / N and var_b = (S2_b / N - H^2) / (N - 1), as for the
+    // integral; iterations from obs_first on are combined with the integral's
+    // weights 1 / var_j (the plain mean once an iteration has zero variance)
+    const double N = static_cast<double>(f.nev);
+    const double I = s12[0] / N;
+    const double var = fma(-I, I, s12[1] / N) / (N - 1.0);
+    const bool on = f.iter >= static_cast<uint32_t>(f.obs_first);
+    const bool pos = var > 0.0;
+    const double wj = pos ? 1.0 / var : 0.0;
+    const double ws = on && pos ? ws_old + wj : ws_old;
+    const double zc = on && !pos ? zc_old + 1.0 : zc_old;
+    for (int k = threadIdx.x; k < f.nobs + 2; k += blockDim.x) {
+      const double h = osm[2 * k] / N;
+      const double v = fma(-h, h, osm[2 * k + 1] / N) / (N - 1.0);
+      double aw = b.obs_acc[k], av = b.obs_acc[kObsLd + k], az = b.obs_acc[2 * kObsLd + k];
+      if (on) {
+        if (pos) {
+          aw += wj * h;
+          av += wj * wj * v;
+          b.obs_acc[k] = aw;
+          b.obs_acc[kObsLd + k] = av;
+        } else {
+          az += h;
+          b.obs_acc[2 * kObsLd + k] = az;
+        }
+      }
+      double c = 0.0, e = 0.0;
+      if (zc > 0.0) {
+        c = az / zc;
+      } else if (ws > 0.0) {
+        c = aw / ws;
+        e = sqrt(av) / ws;
+      }
+      b.obs_out[k] = h;
+      b.obs_out[kObsLd + k] = sqrt(v > 0.0 ? v : 0.0);
+      b.obs_out[2 * kObsLd + k] = c;
+      b.obs_out[3 * kObsLd + k] = e;
+    }
+    if (threadIdx.x == 0) {
+      b.obs_acc[3 * kObsLd] = ws;
+      b.obs_acc[3 * kObsLd + 1] = zc;
+    }
   }
   if (f.spec) {
     // the refinement vegas_refine would compute from this histogram, so that it only
@@ -661,7 +786,8 @@ namespace {
 thread_local std::string g_last_hip_error;
 
 struct Layout {
-  size_t edges, edges_alt, rec_w, rec_bins, maxw, cnt, fxs, part_acc, acc_tot, hist, history, iter_out, result, total;
+  size_t edges, edges_alt, rec_w, rec_bins, rec_obs, maxw, cnt, fxs, part_acc, acc_tot, hist, obs_acc, obs_out,
+      history, iter_out, result, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -679,12 +805,17 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.edges_alt = take(sizeof(double) * D * (n + 1));
   L.rec_w = take(sizeof(double) * maxN);
   L.rec_bins = take(sizeof(uint32_t) * words * maxN);
+  L.rec_obs = take(maxN);
   L.maxw = take(sizeof(unsigned long long) * 2);
   L.cnt = take(sizeof(unsigned long long) * 2);
   L.fxs = take(sizeof(int) * 4);
-  L.part_acc = take(sizeof(long long) * kMaxRowsAcc * part_ld(3 * (2 + D * n)));
-  L.acc_tot = take(sizeof(long long) * 3 * (2 + D * n));
+  // digit columns for the largest observable histogram
+  const int ncol_max = 3 * (2 + D * n) + obs_cols(VEGAS_MAX_OBS_BINS);
+  L.part_acc = take(sizeof(long long) * kMaxRowsAcc * part_ld(ncol_max));
+  L.acc_tot = take(sizeof(long long) * ncol_max);
   L.hist = take(sizeof(double) * (D * n + 2));
+  L.obs_acc = take(sizeof(double) * (3 * kObsLd + 2));
+  L.obs_out = take(sizeof(double) * 4 * kObsLd);
   L.history = take(sizeof(double) * 2 * VEGAS_MAX_ITER);
   L.iter_out = take(sizeof(double) * 8);
   L.result = take(sizeof(double) * 4);
@@ -864,6 +995,10 @@ struct vegas_state {
   bool fused_ok;                // the fused fold fits in LDS for this configuration
   bool spec_ok;                 // the finalisation can also refine (scratch fits, D <= 16)
   bool spec_ready;              // b.edges_alt holds the refinement of the current grid and histogram
+  int nobs, obs_first;          // observable histogram: bins (0 = off) and first combined iteration
+  double obs_lo, obs_hi;
+  bool obs_have;                // an iteration ran since the observable was set
+  size_t smem_max;              // LDS per block the launches may use
   int refine_lds;               // LDS of the refinement scratch: D * 4 (n + 1) doubles
   bool scale_valid;             // the device holds scales from a previous iteration (b.fxs)
   int ncu, occ_event, occ_event_fused, occ_acc;  // CUs, and resident 256-thread blocks per CU
@@ -962,17 +1097,23 @@ void stage_collect(vegas_state* h) {
   h->ev_pending.clear();
 }
 
-template <int PROC, int PREC, int D, bool EXT, bool FUSED>
-hipError_t launch_event_tf(vegas_state* h, const EventArgs& a, int blocks, int threads) {
+template <int PROC, int PREC, int D, bool EXT, bool FUSED, bool OBS>
+hipError_t launch_event_tfo(vegas_state* h, const EventArgs& a, int blocks, int threads) {
   TimedLaunch t(h, 0);
   const int lds = FUSED ? h->fused_lds : h->event_lds;
   if (EXT || threads <= 256)
-    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 256, EXT, FUSED>), dim3(blocks), dim3(EXT ? 256 : threads), lds,
-                          h->stream, t.e0, t.e1, 0, a);
+    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 256, EXT, FUSED, OBS>), dim3(blocks), dim3(EXT ? 256 : threads),
+                          lds, h->stream, t.e0, t.e1, 0, a);
   else
-    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 1024, false, FUSED>), dim3(blocks), dim3(threads), lds, h->stream,
-                          t.e0, t.e1, 0, a);
+    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 1024, false, FUSED, OBS>), dim3(blocks), dim3(threads), lds,
+                          h->stream, t.e0, t.e1, 0, a);
   return t.done();
+}
+
+template <int PROC, int PREC, int D, bool EXT, bool FUSED>
+hipError_t launch_event_tf(vegas_state* h, const EventArgs& a, int blocks, int threads) {
+  return a.nobs > 0 ? launch_event_tfo<PROC, PREC, D, EXT, FUSED, true>(h, a, blocks, threads)
+                    : launch_event_tfo<PROC, PREC, D, EXT, FUSED, false>(h, a, blocks, threads);
 }
 
 template <int PROC, int PREC, int D, bool EXT = false>
@@ -1015,10 +1156,13 @@ bool ext_supported(const vegas_state* h) {
 }
 
 template <int PROC, int PREC, int D>
-int occupancy_event_t(int lds, bool fused) {
+int occupancy_event_t(int lds, bool fused, bool obs) {
   int nb = 0;
-  const void* k = fused ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, true>)
-                        : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256>);
+  const void* k =
+      fused ? (obs ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, true, true>)
+                   : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, true>))
+            : (obs ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, false, true>)
+                   : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256>));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -1026,17 +1170,48 @@ int occupancy_event_t(int lds, bool fused) {
 
 int occupancy_event(const vegas_state* h, bool fused) {
   const int lds = fused ? h->fused_lds : h->event_lds;
+  const bool o = h->nobs > 0;
   switch (h->cfg.process) {
-    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds, fused);
-    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds, fused);
-    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds, fused);
-    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds, fused);
-    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds, fused);
+    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds, fused, o);
+    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds, fused, o);
+    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds, fused, o);
+    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds, fused, o);
+    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds, fused, o);
     case VEGAS_WW_4L:
-      if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds, fused);
-      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds, fused);
+      if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds, fused, o);
+      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds, fused, o);
   }
   return 1;
+}
+
+// LDS sizes, the fused-fold and speculative-refinement switches and the occupancies
+// for the current digit columns (grid histogram plus the observable's bins)
+void configure_lds(vegas_state* h) {
+  const int D = h->D, n = h->n;
+  const size_t smem = h->smem_max;
+  const int ocol = obs_cols(h->nobs);
+  // histogram dimensions per k_accum block: as many as fit in the block's LDS
+  // (the y == 0 blocks also hold S1, S2 and the observable's bins)
+  const size_t per_dim = sizeof(long long) * 3 * n;
+  int dpg = static_cast<int>((smem - sizeof(long long) * (6 + ocol)) / per_dim);
+  dpg = dpg < 1 ? 1 : (dpg > D ? D : dpg);
+  h->acc_dpg = dpg;
+  h->acc_groups = (D + dpg - 1) / dpg;
+  h->acc_lds = static_cast<int>(sizeof(long long) * (6 + 3 * dpg * n + ocol));
+  const int full = static_cast<int>(sizeof(long long) * (3 * (2 + D * n) + ocol));
+  h->fused_lds = h->event_lds + full;
+  h->fused_ok = h->fused_lds <= kFusedLdsMax;
+  h->fin_lds = h->fused_ok ? full : 0;
+  h->refine_lds = static_cast<int>(sizeof(double) * 4 * D * (n + 1));
+  const int obs_lds = h->nobs ? static_cast<int>(sizeof(double) * 2 * (h->nobs + 2)) : 0;
+  h->spec_ok = D <= 16 && h->fin_lds + h->refine_lds + obs_lds <= static_cast<int>(smem);
+  h->occ_event = occupancy_event(h, false);
+  h->occ_event_fused = h->fused_ok ? occupancy_event(h, true) : 1;
+  int nb = 0;
+  h->occ_acc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_accum), 256,
+                                                            h->acc_lds) == hipSuccess && nb > 0
+                   ? nb
+                   : 1;
 }
 
 }  // namespace
@@ -1111,6 +1286,9 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   h->b.part_acc = reinterpret_cast<long long*>(B + L.part_acc);
   h->b.acc_tot = reinterpret_cast<long long*>(B + L.acc_tot);
   h->b.hist = reinterpret_cast<double*>(B + L.hist);
+  h->b.rec_obs = reinterpret_cast<uint8_t*>(B + L.rec_obs);
+  h->b.obs_acc = reinterpret_cast<double*>(B + L.obs_acc);
+  h->b.obs_out = reinterpret_cast<double*>(B + L.obs_out);
   h->b.history = reinterpret_cast<double*>(B + L.history);
   h->b.iter_out = reinterpret_cast<double*>(B + L.iter_out);
   h->b.result = reinterpret_cast<double*>(B + L.result);
@@ -1120,28 +1298,9 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
     const bool have_prop = hipGetDeviceProperties(&prop, h->device) == hipSuccess;
     h->ncu = have_prop ? prop.multiProcessorCount : 256;
     if (h->ncu < 1) h->ncu = 1;
-    // histogram dimensions per k_accum block: as many as fit in the block's LDS
     size_t smem = have_prop ? prop.sharedMemPerBlock : 65536;
-    if (smem > 65536) smem = 65536;
-    const size_t per_dim = sizeof(long long) * 3 * n;
-    int dpg = static_cast<int>((smem - sizeof(long long) * 6) / per_dim);
-    dpg = dpg < 1 ? 1 : (dpg > D ? D : dpg);
-    h->acc_dpg = dpg;
-    h->acc_groups = (D + dpg - 1) / dpg;
-    h->acc_lds = static_cast<int>(sizeof(long long) * (6 + 3 * dpg * n));
-    const int full = static_cast<int>(sizeof(long long) * 3 * (2 + D * n));
-    h->fused_lds = h->event_lds + full;
-    h->fused_ok = h->fused_lds <= kFusedLdsMax;
-    h->fin_lds = h->fused_ok ? full : 0;
-    h->refine_lds = static_cast<int>(sizeof(double) * 4 * D * (n + 1));
-    h->spec_ok = D <= 16 && h->fin_lds + h->refine_lds <= static_cast<int>(smem);
-    h->occ_event = occupancy_event(h, false);
-    h->occ_event_fused = h->fused_ok ? occupancy_event(h, true) : 1;
-    int nb = 0;
-    h->occ_acc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_accum), 256,
-                                                              h->acc_lds) == hipSuccess && nb > 0
-                     ? nb
-                     : 1;
+    h->smem_max = smem > 65536 ? 65536 : smem;
+    configure_lds(h);
   }
   // zero the device-wide atomics and every buffer after the partials with a fill kernel
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, h->stream,
@@ -1248,6 +1407,10 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   ea.nbins = h->n;
   ea.ext_y = ext_y;
   ea.ext_lq = ext_lq;
+  ea.nobs = h->nobs;
+  ea.obs_lo = h->obs_lo;
+  ea.obs_hi = h->obs_hi;
+  ea.obs_scale = h->nobs ? static_cast<double>(h->nobs) / (h->obs_hi - h->obs_lo) : 0.0;
   // fused fold (digits added by the event kernel at the previous iteration's scales)
   // whenever such scales exist and the digits fit in LDS; the choice depends on
   // the history and the configuration only, never on the launch shape
@@ -1267,13 +1430,14 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     aa.ndim = h->D;
     aa.nbins = h->n;
     aa.dims_per_group = h->acc_dpg;
+    aa.nobs = h->nobs;
     rows = pick_blocks(h, n_events, threads, h->occ_acc, kMaxRowsAcc);
     TimedLaunch t(h, 1);
     hipExtLaunchKernelGGL(k_accum, dim3(rows, h->acc_groups), dim3(threads), h->acc_lds, h->stream, t.e0, t.e1, 0,
                           aa);
     VG_HIP(t.done());
   }
-  const int ncol = 3 * (2 + nslot);
+  const int ncol = 3 * (2 + nslot) + obs_cols(h->nobs);
   {
     TimedLaunch t(h, 1);
     hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
@@ -1295,10 +1459,14 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     fa.fused = fused ? 1 : 0;
     fa.spec = (h->spec_ok && !ext_y) ? 1 : 0;
     fa.fold_lds = fused ? h->fin_lds : 0;
+    fa.obs_lds = fa.fold_lds + (fa.spec ? h->refine_lds : 0);
+    fa.nobs = h->nobs;
+    fa.obs_first = h->obs_first;
     fa.alpha = h->cfg.alpha;
+    const int lds = fa.obs_lds + (h->nobs ? static_cast<int>(sizeof(double) * 2 * (h->nobs + 2)) : 0);
     TimedLaunch t(h, 2);
-    hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused || fa.spec ? 1024 : 256),
-                          fa.fold_lds + (fa.spec ? h->refine_lds : 0), h->stream, t.e0, t.e1, 0, fa);
+    hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused || fa.spec ? 1024 : 256), lds, h->stream, t.e0, t.e1, 0,
+                          fa);
     VG_HIP(t.done());
     h->spec_ready = fa.spec != 0;
   }
@@ -1308,6 +1476,7 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   h->have_hist = ext_y == nullptr;  // the grid stays frozen under the learned proposal
   h->last_flow = ext_y != nullptr;
   h->any_iter = true;
+  h->obs_have = h->nobs > 0;
   h->last_n = n_events;
   if (out) {
     double o[6];
@@ -1395,6 +1564,37 @@ int vegas_result_from(vegas_handle h, int32_t first, double* integral, double* e
 
 int vegas_result(vegas_handle h, double* integral, double* error, double* chi2_dof, int32_t* n_iter) {
   return vegas_result_from(h, 0, integral, error, chi2_dof, n_iter);
+}
+
+int vegas_set_observable(vegas_handle h, int32_t nbins, double lo, double hi, int32_t first_iteration) {
+  if (!h || nbins < 0 || nbins > VEGAS_MAX_OBS_BINS || first_iteration < 0) return VEGAS_EINVAL;
+  if (nbins > 0 && !(std::isfinite(lo) && std::isfinite(hi) && lo < hi &&
+                    std::isfinite(static_cast<double>(nbins) / (hi - lo))))
+    return VEGAS_EINVAL;
+  h->nobs = nbins;
+  h->obs_lo = nbins ? lo : 0.0;
+  h->obs_hi = nbins ? hi : 0.0;
+  h->obs_first = first_iteration;
+  h->obs_have = false;
+  configure_lds(h);
+  // clear the combination (a fill kernel on the handle's stream)
+  hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, h->stream,
+                     reinterpret_cast<unsigned long long*>(h->b.obs_acc), static_cast<int64_t>(3 * kObsLd + 2));
+  VG_HIP(hipGetLastError());
+  return VEGAS_OK;
+}
+
+int vegas_get_observable(vegas_handle h, double* last, double* last_err, double* comb, double* comb_err) {
+  if (!h) return VEGAS_EINVAL;
+  if (!h->nobs || !h->obs_have) return VEGAS_ESTATE;
+  const int k = h->nobs + 2;
+  std::vector<double> buf(4 * static_cast<size_t>(kObsLd));
+  VG_HIP(hipMemcpyAsync(buf.data(), h->b.obs_out, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
+  double* outs[4] = {last, last_err, comb, comb_err};
+  for (int q = 0; q < 4; ++q)
+    if (outs[q]) std::memcpy(outs[q], buf.data() + q * kObsLd, sizeof(double) * k);
+  return VEGAS_OK;
 }
 
 int vegas_get_grid(vegas_handle h, double* edges) {
@@ -1582,6 +1782,13 @@ int vegas_set_state(vegas_handle h, const void* buf, size_t bytes) {
   VG_HIP(hipStreamSynchronize(h->stream));
   h->scale_valid = hd.fxs[0] == 1;
   h->spec_ready = false;
+  // the observable histogram keeps its binning; its combination starts afresh
+  if (h->nobs) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, h->stream,
+                       reinterpret_cast<unsigned long long*>(h->b.obs_acc), static_cast<int64_t>(3 * kObsLd + 2));
+    VG_HIP(hipGetLastError());
+  }
+  h->obs_have = false;
   h->iter = hd.iter;
   h->any_iter = hd.iter > 0;
   h->have_hist = false;

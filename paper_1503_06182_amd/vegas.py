@@ -20,9 +20,10 @@ FP64, FP32_ME = 0, 1
 OK, EINVAL, ESTATE, ENOMEM, EHIP = 0, -1, -2, -3, -4
 NPHYS = 16
 MAX_ITER = 4096
+MAX_OBS_BINS = 254
 
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
-           "vegas_result_from",
+           "vegas_result_from", "vegas_set_observable", "vegas_get_observable",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
            "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_last_launch",
@@ -69,6 +70,8 @@ def load(path: str = LIB_PATH):
     L.vegas_refine.argtypes = [vp]
     L.vegas_result.argtypes = [vp, dp, dp, dp, C.POINTER(i32)]
     L.vegas_result_from.argtypes = [vp, i32, dp, dp, dp, C.POINTER(i32)]
+    L.vegas_set_observable.argtypes = [vp, i32, C.c_double, C.c_double, i32]
+    L.vegas_get_observable.argtypes = [vp, vp, vp, vp, vp]
     L.vegas_get_grid.argtypes = [vp, vp]
     L.vegas_set_grid.argtypes = [vp, vp]
     L.vegas_get_hist.argtypes = [vp, vp, vp]
@@ -195,6 +198,19 @@ class Integrator:
         _check(self._L.vegas_result_from(self._h, first, C.byref(I), C.byref(e), C.byref(c), C.byref(n)),
                "vegas_result_from")
         return {"I": I.value, "sigma": e.value, "chi2_dof": c.value, "n_iter": n.value}
+
+    def set_observable(self, nbins, lo=0.0, hi=1.0, first=0):
+        """Histogram the process's observable in nbins uniform bins on [lo, hi)
+        (plus under- and overflow); iterations numbered >= first are combined."""
+        _check(self._L.vegas_set_observable(self._h, nbins, lo, hi, first), "vegas_set_observable")
+        self.nobs = nbins
+
+    def get_observable(self):
+        """(last, last_err, comb, comb_err), each of nbins + 2 (under- and overflow at the ends)."""
+        k = getattr(self, "nobs", 0) + 2
+        a = [np.zeros(k) for _ in range(4)]
+        _check(self._L.vegas_get_observable(self._h, *[x.ctypes.data for x in a]), "vegas_get_observable")
+        return tuple(a)
 
     def get_grid(self):
         e = np.zeros((self.ndim, self.nbins + 1))

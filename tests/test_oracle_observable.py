@@ -128,7 +128,8 @@ def test_set_observable_clears_and_validates():
     v = oracle.Vegas(c["process"], c["ndim"], c["nbins"], c["seed"], c["alpha"], c["params"])
     with pytest.raises(RuntimeError):
         v.get_observable()                     # off
-    for bad in [(-1, 0.0, 1.0), (255, 0.0, 1.0), (4, 1.0, 1.0), (4, 1.0, 0.0)]:
+    for bad in [(-1, 0.0, 1.0), (255, 0.0, 1.0), (4, 1.0, 1.0), (4, 1.0, 0.0),
+                (4, 0.0, math.inf), (4, math.nan, 1.0), (4, 0.0, 1e-310)]:
         with pytest.raises(ValueError):
             v.set_observable(*bad)
     v.set_observable(4, 0.0, 1.0)
