@@ -431,6 +431,51 @@ def bench_flow(args):
     print(json.dumps(line), flush=True)
 
 
+# the observable histogram of each measured workload: (bins, lo, hi) -- the lepton-pair
+# mass over the Drell-Yan window, the e+ p_T over its Jacobian peak, the e+ nu mass
+OBS_BINNING = {"dy_z": (40, 81.0, 101.0), "w_plus": (50, 20.0, 70.0), "ww_4l": (60, 60.0, 100.0)}
+
+
+def observable_leg(args, make, Wn, N, plain_ms_min, plain_event):
+    """The same steps with the observable histogram filled: ms per step (min over 10
+    blocks of K steps, like the plain path's) and the event kernel's average, so the
+    cost of the histogram is read against the plain path measured just before."""
+    import torch
+    nb, lo, hi = OBS_BINNING[args.workload]
+    g = make()
+    g.set_observable(nb, lo, hi, first=Wn)
+    for _ in range(Wn):
+        g.iterate(N, sync=False)
+        g.refine()
+    reps = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            g.iterate(N, sync=False)
+            g.refine()
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t1) / args.steps * 1e3)
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    for _ in range(args.steps):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    st = g.stage_times()
+    shape = g.last_launch()
+    g.close()
+    ev = st["event"][0] / max(st["event"][1], 1)
+    ev_plain = plain_event[0] / max(plain_event[1], 1)
+    return {"bins": nb, "range": [lo, hi], "first_combined": Wn,
+            "ms_per_step_min": min(reps), "ms_per_step_min_plain": plain_ms_min,
+            "step_overhead": min(reps) / plain_ms_min - 1.0,
+            "event_kernel_ms": ev, "event_kernel_ms_plain": ev_plain,
+            "event_kernel_overhead": ev / ev_plain - 1.0 if ev_plain > 0 else None,
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+            "fold_cols": shape["fold_cols"]}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -513,6 +558,9 @@ def main():
         torch.cuda.synchronize()
         reps.append((time.perf_counter() - t1) / args.steps * 1e3)
 
+    obs_leg = observable_leg(args, make, Wn, N, min(reps), st["event"]) \
+        if args.workload in OBS_BINNING else None
+
     ms_ev, n_ev = st["event"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
     roof = roofline(args.workload, args.precision, N, avg_ev)
@@ -554,6 +602,7 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
         "roofline": roof,
         "histogram_stage": hist_stage,
+        "observable": obs_leg,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters,

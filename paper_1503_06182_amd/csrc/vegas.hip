@@ -426,11 +426,13 @@ struct FinArgs {
 __device__ __forceinline__ void refine_dim(bool active, bool preloaded, int n, double alpha, const double* hist,
                                            const double* e_in, double* e_out, double* sm);
 
+// OBS: an observable histogram is set (f.nobs > 0); the plain variant carries none of its code
+template <bool OBS>
 __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* smem) {
   __shared__ double s12[2];
   const DevBufs& b = f.b;
   const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol_h = 3 * (2 + nslot);
-  const int ncol = ncol_h + obs_cols(f.nobs);
+  const int ncol = ncol_h + (OBS ? obs_cols(f.nobs) : 0);
   const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
   const unsigned long long nz = b.cnt[0], nnf = b.cnt[1];
   const int Ec1 = fx_exponent(wmax), Ec2 = fx_exponent(wmax * wmax);
@@ -465,7 +467,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
         const uint32_t word = b.rec_bins[(d >> 2) * f.stride_rec + i];
         acc_hist(acc, 3 * (2 + d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), h0, h1, h2);
       }
-      if (f.nobs) acc_obs(acc, ncol_h + 6 * static_cast<int>(b.rec_obs[i]), d0, d1, d2, h0, h1, h2);
+      if constexpr (OBS) acc_obs(acc, ncol_h + 6 * static_cast<int>(b.rec_obs[i]), d0, d1, d2, h0, h1, h2);
     }
     acc_sums_to_lds(ls, acc);
     __syncthreads();
@@ -474,13 +476,23 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
   // observable bins: slot nslot + 2 + 2k holds sum w of bin k (scale E1), the next
   // one sum w^2 (scale E2); their values go to osm
   double* osm = reinterpret_cast<double*>(smem + f.obs_lds);
-  const int nslot_all = nslot + 2 + (f.nobs ? 2 * (f.nobs + 2) : 0);
-  // the combination so far (read before the barrier that precedes its update)
-  const double ws_old = f.nobs ? b.obs_acc[3 * kObsLd] : 0.0;
-  const double zc_old = f.nobs ? b.obs_acc[3 * kObsLd + 1] : 0.0;
+  const int nslot_all = nslot + 2 + (OBS ? 2 * (f.nobs + 2) : 0);
+  // the combination so far, one bin per thread (nobs + 2 <= 256 <= blockDim.x), read
+  // before the barrier that precedes its update
+  double ws_old = 0.0, zc_old = 0.0, aw = 0.0, av = 0.0, az = 0.0;
+  const int kb = threadIdx.x;
+  if constexpr (OBS) {
+    ws_old = b.obs_acc[3 * kObsLd];
+    zc_old = b.obs_acc[3 * kObsLd + 1];
+    if (kb < f.nobs + 2) {
+      aw = b.obs_acc[kb];
+      av = b.obs_acc[kObsLd + kb];
+      az = b.obs_acc[2 * kObsLd + kb];
+    }
+  }
   for (int slot = threadIdx.x; slot < nslot_all; slot += blockDim.x) {
     const long long* t = tot + 3 * slot;
-    if (slot >= nslot + 2) {
+    if (OBS && slot >= nslot + 2) {
       const int so = slot - (nslot + 2);
       osm[so] = fx_value(t[0], t[1], t[2], (so & 1) ? E2 : E1);
       continue;
@@ -512,7 +524,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     b.cnt[0] = 0ull;
     b.cnt[1] = 0ull;
   }
-  if (f.nobs) {
+  if constexpr (OBS) {
     // per bin: H = S1_b / N and var_b = (S2_b / N - H^2) / (N - 1), as for the
     // integral; iterations from obs_first on are combined with the integral's
     // weights 1 / var_j (the plain mean once an iteration has zero variance)
@@ -524,10 +536,10 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     const double wj = pos ? 1.0 / var : 0.0;
     const double ws = on && pos ? ws_old + wj : ws_old;
     const double zc = on && !pos ? zc_old + 1.0 : zc_old;
-    for (int k = threadIdx.x; k < f.nobs + 2; k += blockDim.x) {
+    if (kb < f.nobs + 2) {
+      const int k = kb;
       const double h = osm[2 * k] / N;
       const double v = fma(-h, h, osm[2 * k + 1] / N) / (N - 1.0);
-      double aw = b.obs_acc[k], av = b.obs_acc[kObsLd + k], az = b.obs_acc[2 * kObsLd + k];
       if (on) {
         if (pos) {
           aw += wj * h;
@@ -596,9 +608,10 @@ __global__ void k_accsum(DevBufs b, int ncol, int rows) {
 
 // one block (a separate launch: a grid-wide "last block" hand-off would need a
 // device-scope fence in every block, which costs far more than the launch)
+template <bool OBS>
 __global__ void k_finalize(FinArgs f) {
   extern __shared__ unsigned char smem[];  // fused: [3 (2 + D n)] for a re-fold
-  finalize_block(f, smem);
+  finalize_block<OBS>(f, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1465,8 +1478,12 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     fa.alpha = h->cfg.alpha;
     const int lds = fa.obs_lds + (h->nobs ? static_cast<int>(sizeof(double) * 2 * (h->nobs + 2)) : 0);
     TimedLaunch t(h, 2);
-    hipExtLaunchKernelGGL(k_finalize, dim3(1), dim3(fused || fa.spec ? 1024 : 256), lds, h->stream, t.e0, t.e1, 0,
-                          fa);
+    if (h->nobs)
+      hipExtLaunchKernelGGL(k_finalize<true>, dim3(1), dim3(fused || fa.spec ? 1024 : 256), lds, h->stream, t.e0,
+                            t.e1, 0, fa);
+    else
+      hipExtLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(fused || fa.spec ? 1024 : 256), lds, h->stream, t.e0,
+                            t.e1, 0, fa);
     VG_HIP(t.done());
     h->spec_ready = fa.spec != 0;
   }
