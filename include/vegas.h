@@ -165,8 +165,9 @@ int vegas_result_from(vegas_handle h, int32_t first, double *integral, double *e
                       double *chi2_dof, int32_t *n_iter);
 
 /* Histogram of the process's observable, filled by the same events and weights
- * as the integral (Sec. 2.1: every event of an iteration serves all of its
- * outputs; the timing runs of Sec. 3.2 fill observables alongside the total).
+ * as the integral (Sec. 2.1: the integrator returns cross sections and
+ * distributions of kinematic variables; Sec. 3.2 shows such distributions, the
+ * di-jet mass, from production runs, while its timing runs fill no histograms).
  * The observable: x_0 (GAUSS, GENZ), cos(theta) of the mu- (EEMUMU), the
  * lepton-pair mass (DY_Z), the e+ transverse momentum, taken before the cuts
  * (W_PLUS), the e+ nu mass (WW_4L).  nbins (0..VEGAS_MAX_OBS_BINS; 0 turns it

@@ -2,8 +2,9 @@
 
 A histogram bin of an observable is the integral of the same weight restricted
 to the events whose observable falls in the bin, so every bin is estimated by
-the same events and the same weights as the total (Sec. 2.1: all events of an
-iteration serve every output).  The pins: the bins add up to the integral and
+the same events and the same weights as the total (Sec. 2.1: the integrator
+yields cross sections and distributions of kinematic variables; Sec. 3.2 shows
+a di-jet mass distribution).  The pins: the bins add up to the integral and
 their variances to its variance (exact identities), brute-force counting on a
 constant integrand, closed forms for the e+e- angular distribution and the
 Gaussian marginal, and quadrature for the Drell-Yan mass and W+ lepton p_T
