@@ -613,6 +613,30 @@ static double f_ww(const double *par, const double *x, double *obs) {
   return P.conv * (1.0 / (2.0 * shat)) * avg * me * jac;
 }
 
+/* Hadronic W+W- (10 dims): the partonic integrand above at sqrt(shat) = sqrt(tau S),
+ * folded with the parton luminosity.  x_8 -> ln tau uniform on [ln tau_lo, ln tau_hi]
+ * (sqrt(shat) between MLO and MHI, MHI <= 0 meaning sqrt(S)), x_9 -> ln x1 = x_9 ln tau,
+ * x2 = tau / x1.  sigma = sum over beams of int dx1 dx2 f(x1) f(x2) sigmahat: with one
+ * density for quarks and antiquarks the quark comes from either beam with the same
+ * weight, and the orderings give the same integral (they differ by a rotation of the
+ * whole final state), so the weight is twice the quark-from-beam-1 term:
+ *   w = 2 |d tau/d x_8| (-ln tau) f(x1) f(x2) f_ww(x_0..7; tau S). */
+static double f_ww_had(const double *par, const double *x, double *obs) {
+  phys P = unpack(par);
+  double S = P.sqrts * P.sqrts;
+  double rlo = P.mlo, rhi = P.mhi > 0 ? P.mhi : P.sqrts;
+  double Llo = log(rlo * rlo / S), Lhi = log(rhi * rhi / S);
+  double L = Lhi + x[8] * (Llo - Lhi);
+  double tau = exp(L);
+  double l1 = x[9] * L, l2 = L - l1;
+  double jtau = tau * (Lhi - Llo);
+  double lum = 2.0 * jtau * (-L) * pdf(&P, l1, -expm1(l1)) * pdf(&P, l2, -expm1(l2));
+  double pp[ORA_NPHYS];
+  memcpy(pp, par, sizeof(pp));
+  pp[ORA_P_SQRTS] = sqrt(tau * S);
+  return lum * f_ww(pp, x, obs);
+}
+
 /* On-shell q qbar -> W+ W- with explicit polarisation vectors, for the gauge
  * cancellation and narrow-width tests.  pol: 0 = longitudinal, 1 = +, 2 = -.
  * W+ at (theta, phi) in the CM frame; outgoing bosons take eps*. */
@@ -664,6 +688,7 @@ int ora_ndim(int process, int ndim_requested) {
     case ORA_DY_Z: return 3;
     case ORA_W_PLUS: return 4;
     case ORA_WW_4L: return 8;
+    case ORA_WW_HAD: return 10;
     default: return -1;
   }
 }
@@ -690,6 +715,7 @@ static double integrand_obs(int process, int ndim, const double *params, const d
     case ORA_DY_Z: return f_dy(params, x, obs);
     case ORA_W_PLUS: return f_w(params, x, obs);
     case ORA_WW_4L: return f_ww(params, x, obs);
+    case ORA_WW_HAD: return f_ww_had(params, x, obs);
     default: return NAN;
   }
 }

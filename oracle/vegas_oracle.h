@@ -37,7 +37,8 @@ enum {
   ORA_EEMUMU = 2,    /* e+e- -> mu+mu- (QED, fixed s), ndim 2                */
   ORA_DY_Z = 3,      /* q qbar -> photon/Z -> l+l-, hadronic, ndim 3         */
   ORA_W_PLUS = 4,    /* u dbar -> W+ -> e+ nu, hadronic with cuts, ndim 4     */
-  ORA_WW_4L = 5      /* q qbar -> W+W- -> e+ nu mu- nubar, partonic, ndim 8   */
+  ORA_WW_4L = 5,     /* q qbar -> W+W- -> e+ nu mu- nubar, partonic, ndim 8   */
+  ORA_WW_HAD = 6     /* the same folded with the parton luminosity, ndim 10   */
 };
 
 /* physics parameter vector layout (restated; see design notes) */

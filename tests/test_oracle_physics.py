@@ -328,3 +328,73 @@ def test_ww_narrow_width_limit():
     r = v.result()
     pred = sig_ww * BR ** 2
     assert abs(r["I"] / pred - 1) < 4 * r["sigma"] / r["I"] + 2e-3, (r, pred)
+
+
+# ------------------------------------------------------------ hadronic W+ W- -
+def sigma_ww_onshell(p, shat, nodes=48):
+    """sigma(q qbar -> W+W-), summed over u and d, from the polarisation-summed
+    on-shell amplitude by Gauss-Legendre in cos(theta) (two panels)."""
+    M = p[4]
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    tot = 0.0
+    for lo, hi in ((-1.0, 0.0), (0.0, 1.0)):
+        for c, wc in zip(0.5 * (x + 1) * (hi - lo) + lo, 0.5 * w * (hi - lo)):
+            tot += wc * sum(oracle.ww_onshell_me2(p, shat, c, 0.0, fl, h, a, b)
+                            for fl in (0, 1) for h in (0, 1) for a in range(3) for b in range(3))
+    lam = (shat - 2 * M * M) ** 2 - 4 * M ** 4
+    return p[15] / (2 * shat) / 12 * math.sqrt(lam) / (32 * math.pi ** 2 * shat) * 2 * math.pi * tot
+
+
+def test_ww_hadronic_narrow_width_limit():
+    """The 10-dim hadronic integrand for G_W -> 0 against
+    int dtau 2 L(tau) sigma_WW(tau S) BR^2, L(tau) = int dx1/x1 f(x1) f(tau/x1):
+    the on-shell partonic cross section (the partonic narrow-width pin's) folded
+    by quadrature with the luminosity, over a sqrt(shat) window [150, 400] GeV
+    that contains the W-pair threshold (below it the on-shell term vanishes)."""
+    G = 0.0021
+    p = W.phys_params(13000.0, gw=G, mlo=150.0, mhi=400.0)
+    M, S = p[4], p[6] ** 2
+    lth, lhi = math.log(4 * M * M / S), math.log(400.0 ** 2 / S)
+    xs, ws = gl01(24)
+
+    def lum(L):
+        return sum(wy * (-L) * pdf(math.exp(y * L)) * pdf(math.exp((1 - y) * L)) for y, wy in zip(xs, ws))
+
+    # ln tau = lth + t^2 takes out the square-root threshold of the phase space
+    tmax = math.sqrt(lhi - lth)
+    xg, wg = GL[16]
+    pred = 0.0
+    for a, b in ((0.0, 0.5 * tmax), (0.5 * tmax, tmax)):
+        for t, wt in zip(0.5 * (xg + 1) * (b - a) + a, 0.5 * wg * (b - a)):
+            L = lth + t * t
+            tau = math.exp(L)
+            pred += wt * 2 * t * tau * 2 * lum(L) * sigma_ww_onshell(p, tau * S)
+    g2 = 4 * math.pi * p[0] / p[1]
+    pred *= (g2 * M / (48 * math.pi * G)) ** 2
+    v = oracle.Vegas(W.WW_HAD, 10, 50, 1, 1.5, p)
+    for _ in range(7):
+        v.iterate(60_000)
+        v.refine()
+    r = v.result()
+    assert abs(r["I"] / pred - 1) < 4 * r["sigma"] / r["I"] + 5e-4, (r, pred)
+
+
+def test_ww_hadronic_is_the_partonic_integrand_at_tau_s():
+    """Pointwise: the hadronic weight is the partonic one at sqrt(shat) = sqrt(tau S)
+    times 2 |dtau/dx_8| (-ln tau) f(x1) f(x2), with ln tau on [ln tau_lo, ln tau_hi]
+    and ln x1 = x_9 ln tau; the observable is the partonic one."""
+    p = W.config("ww_had")["params"]
+    S = p[6] ** 2
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        x = rng.uniform(0.02, 0.98, 10)
+        Llo, Lhi = math.log(150.0 ** 2 / S), 0.0
+        L = Lhi + x[8] * (Llo - Lhi)
+        tau = math.exp(L)
+        x1 = math.exp(x[9] * L)
+        pp = p.copy()
+        pp[6] = math.sqrt(tau * S)
+        part = oracle.integrand(W.WW_4L, pp, x[:8])
+        ref = 2 * tau * (Lhi - Llo) * (-L) * pdf(x1) * pdf(tau / x1) * part
+        assert abs(oracle.integrand(W.WW_HAD, p, x) / ref - 1) < 1e-12
+        assert oracle.observable(W.WW_HAD, p, x) == oracle.observable(W.WW_4L, pp, x[:8])

@@ -11,6 +11,7 @@ Parameter-vector layout (physics processes), index: meaning [default]
     6 sqrt(S) hadronic, or sqrt(shat) for the partonic processes
     7 PDF A [1]   8 PDF a [-0.5]   9 PDF b [3]
    10 lower mass of the Breit-Wigner window   11 upper mass (<= 0: sqrt S)
+      (hadronic W+W-: the window of sqrt(shat) instead)
    12 lepton pT cut [20]        13 lepton |eta| cut [2.5]
    14 V_ud [1]                  15 (hbar c)^2 [0.3893794e9 pb GeV^2]
 Test integrands: GAUSS params = (mu, sigma); GENZ params = (family, a[ndim], w[ndim]).
@@ -19,8 +20,8 @@ from __future__ import annotations
 
 import numpy as np
 
-GAUSS, GENZ, EEMUMU, DY_Z, W_PLUS, WW_4L = range(6)
-NDIM = {EEMUMU: 2, DY_Z: 3, W_PLUS: 4, WW_4L: 8}
+GAUSS, GENZ, EEMUMU, DY_Z, W_PLUS, WW_4L, WW_HAD = range(7)
+NDIM = {EEMUMU: 2, DY_Z: 3, W_PLUS: 4, WW_4L: 8, WW_HAD: 10}
 
 MZ, GZ, MW, GW = 91.1876, 2.4952, 80.4, 2.1
 SW2_ONSHELL = 1.0 - (MW / MZ) ** 2
@@ -56,6 +57,10 @@ def config(name: str) -> dict:
         c.update(schedule=[1000] * 4 + [10_000] * 10, discard_first=4,
                  n_iter=14, n_events=10_000)
         return c
+    if name == "ww_had":  # pp -> W+W- -> e+ nu mu- nubar at 13 TeV, 150 GeV < sqrt(shat), 10 dims
+        return dict(process=WW_HAD, ndim=10, nbins=100, seed=1, alpha=1.5,
+                    params=phys_params(13000.0, mlo=150.0),
+                    n_iter=10, n_events=10_000_000)
     if name == "eemumu":
         return dict(process=EEMUMU, ndim=2, nbins=50, seed=1, alpha=1.5,
                     params=phys_params(91.0), n_iter=5, n_events=100_000)
