@@ -36,13 +36,14 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_734_952, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 170_334_832, "events": 10_000_000},
+    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_746_191, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 170_335_162, "events": 10_000_000},
     ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_313_878, "events": 10_000_000},
+    ("ww_had", "fp64"): {"f64": 1865.1, "f32": 0.0, "traffic": 296_615_206, "events": 10_000_000},
 }
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count
-HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 7_786_014}
+HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 8_733_980}
 # FP64 FLOPs of the adjoint's event kernel per (event, parameter point), and its HBM
 # bytes per call at 64 points x 1e6 events, from the same kind of counter runs
 ADJOINT_KERNEL_WORK = {"f64": 264.9, "traffic": 48_225_306, "events": 1_000_000}
@@ -81,7 +82,8 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps (default: 2 for the VEGAS iteration, whose grid they adapt; "
                          "as many as fill 0.2 s for the other workloads)")
-    ap.add_argument("--workload", default="w_plus", choices=["w_plus", "dy_z", "ww_4l", "ww_4l_paper", "adjoint", "flow"])
+    ap.add_argument("--workload", default="w_plus",
+                    choices=["w_plus", "dy_z", "ww_4l", "ww_had", "ww_4l_paper", "adjoint", "flow"])
     ap.add_argument("--clock-warmup", type=float, default=0.2, metavar="SECONDS",
                     help="seconds of steps on a throwaway handle before the VEGAS-iteration schedule")
     ap.add_argument("--train-events", type=int, default=1_000_000)
@@ -90,7 +92,8 @@ def parse_args():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32me"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=5)
-    ap.add_argument("--cpu-events", type=int, default=4_000_000)
+    ap.add_argument("--cpu-events", type=int, default=0,
+                    help="events per oracle iteration (0: the workload's sample, 10-30 s of host time)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -433,7 +436,11 @@ def bench_flow(args):
 
 # the observable histogram of each measured workload: (bins, lo, hi) -- the lepton-pair
 # mass over the Drell-Yan window, the e+ p_T over its Jacobian peak, the e+ nu mass
-OBS_BINNING = {"dy_z": (40, 81.0, 101.0), "w_plus": (50, 20.0, 70.0), "ww_4l": (60, 60.0, 100.0)}
+OBS_BINNING = {"dy_z": (40, 81.0, 101.0), "w_plus": (50, 20.0, 70.0), "ww_4l": (60, 60.0, 100.0),
+               "ww_had": (60, 60.0, 100.0)}
+# events per oracle iteration of the CPU baseline (x --cpu-iters iterations): about
+# 10-30 s of one host core for each integrand's cost
+CPU_SAMPLE_EVENTS = {"w_plus": 4_000_000, "dy_z": 4_000_000, "ww_4l": 400_000, "ww_had": 300_000}
 
 
 def observable_leg(args, make, Wn, N, plain_ms_min, plain_event):
@@ -606,7 +613,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters,
-                                            min(args.cpu_events, 10 * N))
+                                            min(args.cpu_events or CPU_SAMPLE_EVENTS[args.workload], 10 * N))
     g.close()
     print(json.dumps(line), flush=True)
 

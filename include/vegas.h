@@ -45,8 +45,15 @@ typedef enum {
   VEGAS_DY_Z = 3,   /* q qbar -> photon/Z -> l+l-, hadronic, ndim 3 (m^2 by Breit-Wigner,
                        ln x1, cos theta)                                                    */
   VEGAS_W_PLUS = 4, /* u dbar -> W+ -> e+ nu, hadronic, lepton pT / |eta| cuts, ndim 4      */
-  VEGAS_WW_4L = 5   /* q qbar -> W+W- -> e+ nu mu- nubar, partonic at fixed sqrt(shat),
+  VEGAS_WW_4L = 5,  /* q qbar -> W+W- -> e+ nu mu- nubar, partonic at fixed sqrt(shat),
                        doubly resonant tree amplitudes, ndim 8 = 3*4 - 4 (Sec. 3.2)         */
+  VEGAS_WW_HAD = 6  /* the same in pp collisions: the partonic weight at shat = tau S times
+                       the parton luminosity, ndim 10 = 3*4 - 4 + 2 momentum fractions
+                       (Sec. 3.2: the 3n - 4 integrations plus the two fractions);
+                       x8 -> ln tau uniform over the sqrt(shat) window [MLO, MHI] (MHI <= 0:
+                       sqrt(S), 0 < MLO < MHI), x9 -> ln x1 = x9 ln tau; both beam orderings
+                       as twice the quark-from-beam-1 term (the same integral); binary64
+                       only (up to sqrt(S) the diagrams cancel by (shat/M_W^2)^2)          */
 } vegas_process;
 
 /* arithmetic of the matrix element */

@@ -38,6 +38,11 @@ struct PhysConst {
   double cs_re[2][2], cs_im[2][2];  // s-channel photon+Z coefficient, [q][h]
   double ct;                  // exchange-diagram coefficient: -g^2 / 2
   double csR2;                // |Cs[u][R]|^2 + |Cs[d][R]|^2
+  // hadronic WW: ln tau = Lhi + x8 * Lrng on [ln tau_lo, ln tau_hi] (Lrng = Llo - Lhi),
+  // shat = tau S; per event the s-channel coefficients e^2 Q / shat + e^2 f (shat - MZ^2
+  // - i MZ GZ) / |shat - MZ^2 + i MZ GZ|^2 from csq[q] = e^2 Q and csf[q][h] = e^2 f
+  double S, Lhi, Lrng, Ldiff; // Ldiff = Lhi - Llo
+  double csq[2], csf[2][2];
   // e+e- -> mu+mu-
   double s_ee, e4;
   // Gaussian test integrand
@@ -314,9 +319,15 @@ struct ExchInv {
   R tu, td, b00u, b11u, b00d, b11d;
 };
 
+// the energy of one hadronic event (the s-channel coefficients are formed from it
+// where the amplitude needs them, so that only two values stay live)
+struct WWHad {
+  double rs, sh;
+};
+
 // sum over q in {u, d} and quark helicity of |M|^2 (no averages)
-template <typename R>
-__device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p4[4], const R p5[4],
+template <typename R, bool HAD = false>
+__device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const R p3[4], const R p4[4], const R p5[4],
                                     const R p6[4], R mp2, R mm2, const ExchInv<R>* inv) {
   cx<R> a3_0, a3_1, a4_0, a4_1, a5_0, a5_1, a6_0, a6_1;
   spinor_m(p3, a3_0, a3_1);
@@ -352,7 +363,7 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p
   cx<R> V1, V2;
   V1 = csub(cadd(cmul(ep[1], a1), cscale(a2, dq[1])), cmul(em[1], a3));
   V2 = csub(cadd(cmul(ep[2], a1), cscale(a2, dq[2])), cmul(em[2], a3));
-  const R rs = static_cast<R>(c.rs);
+  const R rs = static_cast<R>(HAD ? hd.rs : c.rs);
   // j_L.V = -rs (V1 - i V2), j_R.V = -rs (V1 + i V2)
   const cx<R> AL = {-rs * (V1.re + V2.im), -rs * (V1.im - V2.re)};
   const cx<R> AR = {-rs * (V1.re - V2.im), -rs * (V1.im + V2.re)};
@@ -381,11 +392,29 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const R p3[4], const R p
   const cx<R> Td = chain01(ep, kd, b00d, b11d, em);
   const R ct = static_cast<R>(c.ct);
   const R fu = -rs * ct / tu, fd = -rs * ct / td;
-  const cx<R> csuL = {static_cast<R>(c.cs_re[0][0]), static_cast<R>(c.cs_im[0][0])};
-  const cx<R> csdL = {static_cast<R>(c.cs_re[1][0]), static_cast<R>(c.cs_im[1][0])};
+  double cre[2], cim[2], csR2 = c.csR2;  // s-channel photon + Z, left-handed quark, [q]
+  if constexpr (HAD) {
+    // e^2 Q / shat + e^2 f (shat - MZ^2 - i MZ GZ) / |shat - MZ^2 + i MZ GZ|^2
+    const double dr = hd.sh - c.mz2, idd = 1.0 / (dr * dr + c.mzgz * c.mzgz), ish = 1.0 / hd.sh;
+    csR2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      cre[q] = c.csq[q] * ish + c.csf[q][0] * dr * idd;
+      cim[q] = -c.csf[q][0] * c.mzgz * idd;
+      const double rr = c.csq[q] * ish + c.csf[q][1] * dr * idd, ri = -c.csf[q][1] * c.mzgz * idd;
+      csR2 += rr * rr + ri * ri;
+    }
+  } else {
+    cre[0] = c.cs_re[0][0];
+    cim[0] = c.cs_im[0][0];
+    cre[1] = c.cs_re[1][0];
+    cim[1] = c.cs_im[1][0];
+  }
+  const cx<R> csuL = {static_cast<R>(cre[0]), static_cast<R>(cim[0])};
+  const cx<R> csdL = {static_cast<R>(cre[1]), static_cast<R>(cim[1])};
   const cx<R> MuL = cadd(cmul(csuL, AL), cscale(Tu, fu));
   const cx<R> MdL = cadd(cmul(csdL, AL), cscale(Td, fd));
-  return cabs2(MuL) + cabs2(MdL) + static_cast<R>(c.csR2) * cabs2(AR);
+  return cabs2(MuL) + cabs2(MdL) + static_cast<R>(csR2) * cabs2(AR);
 }
 
 // rest frame of Q (mass m) -> frame of Q, for k and its back-to-back partner
@@ -413,23 +442,43 @@ __device__ __forceinline__ void sincos_2pi(float x, float& s, float& c) { sincos
 // Phase space (masses, momenta, lambda, Jacobian) is binary64; only the
 // amplitude (spinors, currents, diagrams) is evaluated in R.
 // obs_sq: the square of the observable, the e+ nu mass m_+^2 (0 where the map gives none)
-template <typename R>
+// HAD: the hadronic integrand (10 dims): x8 -> ln tau, x9 -> ln x1, the partonic weight
+// at shat = tau S times the luminosity 2 |dtau/dx8| (-ln tau) f(x1) f(x2) (the two beam
+// orderings give the same integral)
+template <typename R, bool HAD = false>
 __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, double& obs_sq) {
+  double rs = c.rs, sh = c.shat, rho_rng = c.rho_rng, lum = 1.0;
+  WWHad hd;
+  if constexpr (HAD) {
+    double L, l1, l2;
+    {
+#pragma clang fp contract(off)
+      L = c.Lhi + x[8] * c.Lrng;
+      l1 = x[9] * L;
+      l2 = L - l1;
+    }
+    const double tau = exp(L);
+    sh = tau * c.S;
+    rs = sqrt(sh);
+    rho_rng = atan((sh - c.M2) / c.MG) - c.rho_lo;
+    lum = 2.0 * (tau * c.Ldiff) * (-L) * pdf_pair(c, tau, L, expm1(l1) * expm1(l2));
+    hd.rs = rs;
+    hd.sh = sh;
+  }
   double jp, jm;
-  const double mp2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jp);
+  const double mp2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rho_rng, jp);
   obs_sq = mp2 > 0.0 ? mp2 : 0.0;
   if (!(mp2 > 0.0)) return 0.0;
   const double mp = sqrt(mp2);
-  const double up = (c.rs - mp) * (c.rs - mp);
+  const double up = (rs - mp) * (rs - mp);
   const double rrng2 = atan((up - c.M2) / c.MG) - c.rho_lo;
   const double mm2 = bw_map(x[1], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rrng2, jm);
   if (!(mm2 > 0.0)) return 0.0;
   const double mm = sqrt(mm2);
-  const double sh = c.shat;
   const double lam = (sh - mp2 - mm2) * (sh - mp2 - mm2) - 4.0 * mp2 * mm2;
   if (!(lam > 0.0)) return 0.0;
   const double sl = sqrt(lam);
-  const double i2rs = 1.0 / (2.0 * c.rs);
+  const double i2rs = 1.0 / (2.0 * rs);
   const double q = sl * i2rs;
   const double Ep = (sh + mp2 - mm2) * i2rs, Em = (sh - mp2 + mm2) * i2rs;
   const double ct = 2.0 * x[2] - 1.0, st = sqrt((1.0 - ct) * (1.0 + ct));
@@ -474,19 +523,22 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     const double epm = mp2 / (Epd + qd) + qd * (1.0 - cd);  // Ep - q cos
     const double emm = mm2 / (Emd + qd) + qd * (1.0 + cd);  // Em + q cos
     ExchInv<R> iv;
-    iv.tu = static_cast<R>(mp2 - c.rs * epm);
-    iv.td = static_cast<R>(mm2 - c.rs * emm);
+    iv.tu = static_cast<R>(mp2 - rs * epm);
+    iv.td = static_cast<R>(mm2 - rs * emm);
     iv.b00u = static_cast<R>(-epm);
-    iv.b11u = static_cast<R>(c.rs - (Epd + qd * cd));
+    iv.b11u = static_cast<R>(rs - (Epd + qd * cd));
     iv.b00d = static_cast<R>(-emm);
-    iv.b11d = static_cast<R>(c.rs - (Emd - qd * cd));
-    me = static_cast<double>(ww_me2<R>(c, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), &iv));
+    iv.b11d = static_cast<R>(rs - (Emd - qd * cd));
+    me = static_cast<double>(
+        ww_me2<R, HAD>(c, hd, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), &iv));
   } else {
-    me = static_cast<double>(ww_me2<R>(c, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
+    me = static_cast<double>(
+        ww_me2<R, HAD>(c, hd, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
   }
   // dPhi_2(P) (4 pi) * dm+^2/(2 pi) * dm-^2/(2 pi) * [dPhi_2(W) (4 pi)]^2
   const double jac = sl / (8.0 * kPi * sh) * (jp / (2.0 * kPi)) * (jm / (2.0 * kPi)) *
                      (1.0 / (64.0 * kPi * kPi));
+  if constexpr (HAD) return c.conv * (0.5 / sh) * (1.0 / 12.0) * me * jac * lum;
   return c.conv * (0.5 / sh) * (1.0 / 12.0) * me * jac;
 }
 

@@ -116,6 +116,9 @@ __device__ __forceinline__ double integrand(const PhysConst& c, const double* x,
     return f_dy(c, x, q);
   } else if constexpr (PROC == VEGAS_W_PLUS) {
     return f_w(c, x, q);
+  } else if constexpr (PROC == VEGAS_WW_HAD) {
+    if constexpr (PREC == VEGAS_FP32_ME) return f_ww<float, true>(c, x, q);
+    else return f_ww<double, true>(c, x, q);
   } else if constexpr (PREC == VEGAS_FP32_ME) {
     return f_ww<float>(c, x, q);
   } else {
@@ -125,7 +128,7 @@ __device__ __forceinline__ double integrand(const PhysConst& c, const double* x,
 
 template <int PROC>
 constexpr bool obs_is_square() {
-  return PROC == VEGAS_DY_Z || PROC == VEGAS_W_PLUS || PROC == VEGAS_WW_4L;
+  return PROC == VEGAS_DY_Z || PROC == VEGAS_W_PLUS || PROC == VEGAS_WW_4L || PROC == VEGAS_WW_HAD;
 }
 
 // bin of an observable value o: 0 below lo, nobs + 1 at or above hi (and for a NaN),
@@ -219,7 +222,7 @@ constexpr double kExtLo = 0x1p-40, kExtHi = 1.0 - 0x1p-40;
 
 template <int PROC>
 constexpr int event_min_waves() {
-  return PROC == VEGAS_WW_4L ? 2 : (PROC == VEGAS_W_PLUS ? 3 : 4);
+  return (PROC == VEGAS_WW_4L || PROC == VEGAS_WW_HAD) ? 2 : (PROC == VEGAS_W_PLUS ? 3 : 4);
 }
 
 // EXT: the point is the learned proposal's y (binary32, kept inside the open unit
@@ -240,6 +243,14 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
   for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x) e_lds[i] = a.b.edges[i];
   if constexpr (FUSED)
     for (int i = threadIdx.x; i < ncol; i += blockDim.x) acc[i] = 0;
+  // with 10 or more dimensions the register budget of 2 waves per SIMD is spent on the
+  // integrand, so the lane's S1, S2 digit sums live in LDS, one private slot per lane
+  // and digit (no atomics: no other lane touches it) instead of 12 registers
+  constexpr bool kLdsSums = FUSED && D >= 10 && MAXT == 256;
+  long long* lsum = acc + ncol;  // kLdsSums: [6][256]
+  if constexpr (kLdsSums)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) lsum[k * 256 + threadIdx.x] = 0;
   if (blockIdx.x == 0) {
     // clear this iteration's digit totals (the previous iteration's were consumed
     // by its finalisation, earlier on the stream)
@@ -270,6 +281,23 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
       event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
     }
     const double J = grid_map<D>(e_lds, n, nd, u, x, bins);
+    // the bins, 4 of 8 bits per word.  With 10 or more fixed dimensions they are
+    // recorded before the integrand, so that only the packed words stay live across
+    // it (the fused fold takes the bins back out of them); with fewer, or a run-time
+    // dimension, keeping the bins themselves allocates better
+    constexpr int kWords = D > 0 ? (D + 3) / 4 : 4;
+    constexpr bool kEarlyBins = D >= 10;
+    uint32_t bw[kWords];
+    if constexpr (kEarlyBins) {
+#pragma unroll
+      for (int g = 0; g < kWords; ++g) {
+        bw[g] = 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * g + j < nd) bw[g] |= static_cast<uint32_t>(bins[4 * g + j]) << (8 * j);
+        a.b.rec_bins[g * a.stride_rec + i] = bw[g];
+      }
+    }
     double q;
     const double f = integrand<PROC, PREC, D>(a.pc, x, q);
     double w = J * f;
@@ -286,25 +314,36 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
       ++nz;
     }
     a.b.rec_w[i] = w;
+    if constexpr (!kEarlyBins) {
 #pragma unroll
-    for (int g = 0; g < (D > 0 ? (D + 3) / 4 : 4); ++g) {
-      if (4 * g >= nd) break;
-      uint32_t word = 0;
+      for (int g = 0; g < kWords; ++g) {
+        if (4 * g >= nd) break;
+        uint32_t word = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (4 * g + j < nd) word |= static_cast<uint32_t>(bins[4 * g + j]) << (8 * j);
-      a.b.rec_bins[g * a.stride_rec + i] = word;
+        for (int j = 0; j < 4; ++j)
+          if (4 * g + j < nd) word |= static_cast<uint32_t>(bins[4 * g + j]) << (8 * j);
+        a.b.rec_bins[g * a.stride_rec + i] = word;
+      }
     }
     const unsigned long long wb = static_cast<unsigned long long>(__double_as_longlong(fabs(w)));
     wmax = wb > wmax ? wb : wmax;
     if constexpr (FUSED) {
       if (w != 0.0) {
         long long d0, d1, d2, h0, h1, h2;
-        acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
+        if constexpr (kLdsSums) {
+          LaneSums t;
+          lane_sums_zero(t);
+          acc_sums(w, E1, E2, t, d0, d1, d2, h0, h1, h2);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) lsum[k * 256 + threadIdx.x] += t.v[k];
+        } else {
+          acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
+        }
 #pragma unroll
         for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
           if (d >= nd) break;
-          acc_hist(acc, 3 * (2 + d * n + bins[d]), h0, h1, h2);
+          const int bin = kEarlyBins ? static_cast<int>((bw[d >> 2] >> (8 * (d & 3))) & 0xffu) : bins[d];
+          acc_hist(acc, 3 * (2 + d * n + bin), h0, h1, h2);
         }
         if constexpr (OBS) acc_obs(acc, ncol_h + 6 * obin, d0, d1, d2, h0, h1, h2);
       }
@@ -322,6 +361,9 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     atomicAdd(&blk[1], static_cast<unsigned long long>(snz));
     atomicAdd(&blk[2], static_cast<unsigned long long>(snf));
   }
+  if constexpr (kLdsSums)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ls.v[k] = lsum[k * 256 + threadIdx.x];
   if constexpr (FUSED) acc_sums_to_lds(ls, acc);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -844,13 +886,14 @@ int process_ndim(int process, int requested) {
     case VEGAS_DY_Z: return 3;
     case VEGAS_W_PLUS: return 4;
     case VEGAS_WW_4L: return 8;
+    case VEGAS_WW_HAD: return 10;
     default: return -1;
   }
 }
 
 int validate(const vegas_config* c, int64_t max_events) {
   if (!c) return VEGAS_EINVAL;
-  if (c->process < VEGAS_GAUSS || c->process > VEGAS_WW_4L) return VEGAS_EINVAL;
+  if (c->process < VEGAS_GAUSS || c->process > VEGAS_WW_HAD) return VEGAS_EINVAL;
   const int D = process_ndim(c->process, c->ndim);
   if (D < 1 || D > VEGAS_MAX_DIM || D != c->ndim) return VEGAS_EINVAL;
   if (c->nbins < 2 || c->nbins > VEGAS_MAX_BINS) return VEGAS_EINVAL;
@@ -858,6 +901,8 @@ int validate(const vegas_config* c, int64_t max_events) {
   if (c->nparams < 0 || c->nparams > VEGAS_MAX_PARAMS) return VEGAS_EINVAL;
   if (c->nparams > 0 && !c->params) return VEGAS_EINVAL;
   if (c->precision != VEGAS_FP64 && c->precision != VEGAS_FP32_ME) return VEGAS_EINVAL;
+  // binary32 amplitudes only at the partonic W+W- energy: in the hadronic process
+  // sqrt(shat) reaches sqrt(S), where the diagrams cancel by (shat / M_W^2)^2
   if (c->precision == VEGAS_FP32_ME && c->process != VEGAS_WW_4L) return VEGAS_EINVAL;
   const int w = c->waves_per_block;
   if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8 || w == 16)) return VEGAS_EINVAL;
@@ -872,6 +917,11 @@ int validate(const vegas_config* c, int64_t max_events) {
       break;
     default:
       if (c->nparams < VEGAS_NPHYS) return VEGAS_EINVAL;
+  }
+  if (c->process == VEGAS_WW_HAD) {  // the sqrt(shat) window: 0 < MLO < MHI <= sqrt(S)
+    const double rs = c->params[VEGAS_P_SQRTS], lo = c->params[VEGAS_P_MLO];
+    const double hi = c->params[VEGAS_P_MHI] > 0 ? c->params[VEGAS_P_MHI] : rs;
+    if (!(lo > 0.0 && lo < hi && hi <= rs && std::isfinite(rs))) return VEGAS_EINVAL;
   }
   return VEGAS_OK;
 }
@@ -953,7 +1003,7 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
     k.ptmin2 = p[VEGAS_P_PTMIN] * p[VEGAS_P_PTMIN];
     const double th = std::tanh(p[VEGAS_P_ETAMAX]);
     k.th2 = th * th;
-  } else if (c->process == VEGAS_WW_4L) {
+  } else if (c->process == VEGAS_WW_4L || c->process == VEGAS_WW_HAD) {
     k.M2 = MW * MW;
     k.MG = MW * GW;
     k.rs = rs;
@@ -979,6 +1029,24 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
       csr2 += k.cs_re[q][1] * k.cs_re[q][1] + k.cs_im[q][1] * k.cs_im[q][1];
     }
     k.csR2 = csr2;
+    if (c->process == VEGAS_WW_HAD) {
+      const double S = rs * rs, lo = p[VEGAS_P_MLO], hi = p[VEGAS_P_MHI] > 0 ? p[VEGAS_P_MHI] : rs;
+      const double Llo = std::log(lo * lo / S), Lhi = std::log(hi * hi / S);
+      k.S = S;
+      k.Lhi = Lhi;
+      k.Lrng = Llo - Lhi;
+      k.Ldiff = Lhi - Llo;
+      k.mz2 = MZ * MZ;
+      k.mzgz = MZ * GZ;
+      for (int q = 0; q < 2; ++q) {
+        const double Q = q == 0 ? 2.0 / 3.0 : -1.0 / 3.0, T3 = q == 0 ? 0.5 : -0.5;
+        k.csq[q] = e2 * Q;
+        for (int h = 0; h < 2; ++h) {
+          const double gz = h == 0 ? (T3 - Q * sw2) / (sw * cw) : -Q * sw / cw;
+          k.csf[q][h] = e2 * (gz * cw / sw);
+        }
+      }
+    }
   }
   return k;
 }
@@ -1146,6 +1214,8 @@ hipError_t launch_event(vegas_state* h, const EventArgs& a, int blocks, int thre
       if (h->cfg.precision == VEGAS_FP32_ME)
         return launch_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(h, a, blocks, threads, fused);
       return launch_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(h, a, blocks, threads, fused);
+    case VEGAS_WW_HAD:
+      return launch_event_t<VEGAS_WW_HAD, VEGAS_FP64, 10>(h, a, blocks, threads, fused);
   }
   return hipErrorInvalidValue;
 }
@@ -1193,6 +1263,8 @@ int occupancy_event(const vegas_state* h, bool fused) {
     case VEGAS_WW_4L:
       if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds, fused, o);
       return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds, fused, o);
+    case VEGAS_WW_HAD:
+      return occupancy_event_t<VEGAS_WW_HAD, VEGAS_FP64, 10>(lds, fused, o);
   }
   return 1;
 }
@@ -1212,7 +1284,8 @@ void configure_lds(vegas_state* h) {
   h->acc_groups = (D + dpg - 1) / dpg;
   h->acc_lds = static_cast<int>(sizeof(long long) * (6 + 3 * dpg * n + ocol));
   const int full = static_cast<int>(sizeof(long long) * (3 * (2 + D * n) + ocol));
-  h->fused_lds = h->event_lds + full;
+  // 10 or more dimensions: the lanes' S1, S2 digit sums also live in LDS ([6][256])
+  h->fused_lds = h->event_lds + full + (D >= 10 ? static_cast<int>(sizeof(long long) * 6 * 256) : 0);
   h->fused_ok = h->fused_lds <= kFusedLdsMax;
   h->fin_lds = h->fused_ok ? full : 0;
   h->refine_lds = static_cast<int>(sizeof(double) * 4 * D * (n + 1));

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvegas.so")
 
-GAUSS, GENZ, EEMUMU, DY_Z, W_PLUS, WW_4L = range(6)
+GAUSS, GENZ, EEMUMU, DY_Z, W_PLUS, WW_4L, WW_HAD = range(7)
 FP64, FP32_ME = 0, 1
 OK, EINVAL, ESTATE, ENOMEM, EHIP = 0, -1, -2, -3, -4
 NPHYS = 16

@@ -41,7 +41,7 @@ def make_pair(P, cfg, max_events, **kw):
 
 def cases():
     out = []
-    for name in ("gauss4", "eemumu", "dy_z", "w_plus", "ww_4l"):
+    for name in ("gauss4", "eemumu", "dy_z", "w_plus", "ww_4l", "ww_had"):
         out.append((name, W.config(name)))
     for fam in (1, 2, 3, 4, 5, 6):
         out.append((f"genz{fam}", dict(process=W.GENZ, ndim=5, nbins=40, seed=9, alpha=1.5,
@@ -81,7 +81,7 @@ def rel(a, b):
 def test_iterations_match_oracle(P, name, cfg):
     """Three iterations (with refinement) at a size that spans many blocks and a
     ragged tail; grid injected into the oracle before each iteration."""
-    n = 6007 if cfg["process"] != W.WW_4L else 4099
+    n = 6007 if cfg["process"] not in (W.WW_4L, W.WW_HAD) else 4099
     g, o = make_pair(P, cfg, n)
     for it in range(3):
         o.set_grid(g.get_grid())
@@ -98,12 +98,23 @@ def test_iterations_match_oracle(P, name, cfg):
         dg, sg = g.get_hist()
         do, so = o.get_hist()
         assert rel(sg, so) < REL_ITER
-        m = do > 0
-        assert np.array_equal(dg > 0, m)
-        assert rel(dg[m], do[m]) < REL_ITER
+        # the exact digit sums resolve each event's w^2 to 2^-62 of the largest (the
+        # fused fold's scale sits 2^32 above the previous iteration's max w^2; 2^-94
+        # in the two-pass fold), so a bin far below the others carries up to
+        # N 2^-62 max w^2 <= 1e-15 S2 of truncation: relative bar plus that floor
+        floor = 1e-14 * so[1]
+        assert np.array_equal(dg[do > floor] > 0, np.ones(int(np.sum(do > floor)), bool))
+        assert np.all(np.abs(dg - do) <= REL_ITER * np.abs(do) + floor), \
+            (name, it, float(np.max(np.abs(dg - do) / np.maximum(np.abs(do), floor))))
         g.refine()
         o.refine()
-        assert np.max(np.abs(g.get_grid() - o.get_grid())) < 1e-12, f"{name} it{it}: grids"
+        # the damped importance ((r - 1)/ln r)^alpha shrinks only logarithmically as
+        # r -> 0, so bins near the digits' floor (a few above it, like the hadronic
+        # integrand's edges where f ~ (1 - x)^3) still move the new edges: there the
+        # grids agree to 1e-7 (measured 1.9e-8), elsewhere to 1e-12
+        near_floor = np.any((do > 0) & (do < 1e6 * floor))
+        gtol = 1e-7 if near_floor else 1e-12
+        assert np.max(np.abs(g.get_grid() - o.get_grid())) < gtol, f"{name} it{it}: grids"
 
 
 @pytest.mark.parametrize("name", ["dy_z", "gauss4"])
@@ -161,7 +172,7 @@ def run_schedule(P, cfg, n, n_iter, **launch):
     return b"".join(blobs)
 
 
-@pytest.mark.parametrize("name", ["w_plus", "ww_4l", "genz2", "gauss16x255"])
+@pytest.mark.parametrize("name", ["w_plus", "ww_4l", "ww_had", "genz2", "gauss16x255"])
 def test_bit_identical_across_launch_configurations(P, name):
     if name == "genz2":
         cfg = dict(process=W.GENZ, ndim=5, nbins=40, seed=9, alpha=1.5,
@@ -170,7 +181,7 @@ def test_bit_identical_across_launch_configurations(P, name):
         cfg = GAUSS_MAX
     else:
         cfg = W.config(name)
-    n = 50_021 if name != "ww_4l" else 20_011
+    n = 50_021 if name not in ("ww_4l", "ww_had") else 20_011
     ref = run_schedule(P, cfg, n, 3)
     for wpb, mb in ((1, 0), (2, 3), (4, 1), (8, 0), (16, 5), (4, 97)):
         assert run_schedule(P, cfg, n, 3, waves_per_block=wpb, max_blocks=mb) == ref, (wpb, mb)
@@ -328,14 +339,14 @@ def test_full_size_sampled_parity_bench_workload(P):
     compare_weights(wg[n - 300:], wt, "w_plus tail")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32me"])
-def test_full_size_sampled_parity_ww(P, prec):
-    """W+W- at its measured size (1e7 events per iteration, default launch) in both
-    matrix-element precisions: every 9973rd event and the launch's last 300
+@pytest.mark.parametrize("name,prec", [("ww_4l", "fp64"), ("ww_4l", "fp32me"), ("ww_had", "fp64")])
+def test_full_size_sampled_parity_ww(P, name, prec):
+    """W+W- (partonic, and hadronic in 10 dims) at the measured size (1e7 events per
+    iteration, default launch): every 9973rd event and the launch's last 300
     recomputed one by one by the oracle at the same grid (bins bit-exact; weights
     to 1e-12 in FP64, to the binary32 bars max 2e-4 / mean 2e-6 in FP32-ME), and
     the iteration's I and var equal to the mean and variance of all 1e7 weights."""
-    cfg = W.config("ww_4l")
+    cfg = W.config(name)
     n = cfg["n_events"]
     g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"],
                      precision=P.FP32_ME if prec == "fp32me" else P.FP64, max_events=n)
@@ -354,7 +365,7 @@ def test_full_size_sampled_parity_ww(P, prec):
         wo[k], bo[k] = w1[0], b1[0]
     assert np.array_equal(bg[idx], bo), "bin indices differ"
     if prec == "fp64":
-        compare_weights(wg[idx], wo, "ww_4l full size")
+        compare_weights(wg[idx], wo, f"{name} full size")
     else:
         m = wo != 0
         e = np.abs(wg[idx][m] - wo[m]) / np.abs(wo[m])
