@@ -80,6 +80,11 @@ def lib():
         L.ora_observable.restype = C.c_double
         L.ora_set_observable.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int]
         L.ora_get_observable.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.ora_set_strata.argtypes = [C.c_void_p, C.c_int]
+        L.ora_strata_cubes.argtypes = [C.c_void_p]
+        L.ora_strata_cubes.restype = C.c_int64
+        L.ora_strata_npc.argtypes = [C.c_void_p]
+        L.ora_strata_npc.restype = C.c_int64
         L.ora_event_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_int64, C.c_int64, _dp, _u8p]
         L.ora_grid_map.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_double),
                                    np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")]
@@ -193,7 +198,10 @@ class Vegas:
         out = np.zeros(4)
         if lib().ora_iterate(self._h, n, out) != 0:
             raise ValueError("oracle iterate failed")
-        return {"I": out[0], "var": out[1], "n_nonzero": int(out[2]), "n_nonfinite": int(out[3])}
+        H = lib().ora_strata_cubes(self._h)
+        used = H * lib().ora_strata_npc(self._h) if H > 0 else n
+        return {"I": out[0], "var": out[1], "n_nonzero": int(out[2]), "n_nonfinite": int(out[3]),
+                "n_events": int(used)}
 
     def refine(self):
         if lib().ora_refine(self._h) != 0:
@@ -204,6 +212,15 @@ class Vegas:
         if lib().ora_result_from(self._h, first, out) != 0:
             raise ValueError("no iteration, or first out of range")
         return {"I": out[0], "sigma": out[1], "chi2_dof": out[2], "n_iter": int(out[3])}
+
+    def set_strata(self, m):
+        """m strata per axis (0: off); an iteration of n events uses m^D floor(n / m^D)."""
+        if lib().ora_set_strata(self._h, m) != 0:
+            raise ValueError("invalid strata count")
+
+    @property
+    def strata_npc(self):
+        return lib().ora_strata_npc(self._h)
 
     def set_observable(self, nbins, lo=0.0, hi=1.0, first=0):
         if lib().ora_set_observable(self._h, nbins, lo, hi, first) != 0:

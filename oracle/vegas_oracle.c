@@ -756,6 +756,10 @@ struct ora_state {
   long double obs_acc_w[ORA_MAX_OBS + 2], obs_acc_v[ORA_MAX_OBS + 2], obs_zacc[ORA_MAX_OBS + 2];
   long double obs_wsum;
   int obs_zcount;
+  /* stratified sampling: m strata per axis (0 = off), npc events per hypercube in the
+   * current (last) iteration */
+  int strata_m;
+  int64_t strata_npc;
 };
 
 ora_state *ora_create(int process, int ndim, int nbins, uint64_t seed, double alpha,
@@ -814,9 +818,24 @@ int ora_grid_map(const ora_state *s, const double *u, double *x, double *jac, in
   return 0;
 }
 
+/* Stratified sampling (Lepage's stratified + importance mode): the unit cube is cut
+ * into m^D equal hypercubes and hypercube h gets events h npc .. (h + 1) npc - 1;
+ * event i lies in h = floor(i / npc), whose coordinates are the base-m digits of h
+ * (dimension 0 the least significant), and its uniforms r are placed inside it:
+ * u_d = (c_d + r_d) / m. */
+static void strata_place(const ora_state *s, uint64_t i, double *u) {
+  uint64_t h = i / (uint64_t)s->strata_npc;
+  for (int d = 0; d < s->ndim; ++d) {
+    uint64_t c = h % (uint64_t)s->strata_m;
+    h /= (uint64_t)s->strata_m;
+    u[d] = ((double)c + u[d]) / (double)s->strata_m;
+  }
+}
+
 static double event_weight_obs(const ora_state *s, uint32_t iter, uint64_t i, int *bins, double *obs) {
   double u[16], x[16], J;
   ora_uniforms(s->seed, iter, i, s->ndim, u);
+  if (s->strata_m > 0 && s->strata_npc > 0) strata_place(s, i, u);
   grid_map(s, u, x, &J, bins);
   double f = integrand_obs(s->process, s->ndim, s->params, x, obs);
   return J * f;
@@ -850,8 +869,40 @@ int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t 
  * d[dim][bin] = sum of w^2 over events in that bin, in long double.
  * Non-finite weights are counted and contribute nothing.
  * I_j = S1 / n, var_j = (S2 / n - I_j^2) / (n - 1). */
-int ora_iterate(ora_state *s, int64_t n, double out[4]) {
-  if (n < 2) return -1;
+int64_t ora_strata_cubes(const ora_state *s) {
+  if (s->strata_m <= 0) return 0;
+  int64_t H = 1;
+  for (int d = 0; d < s->ndim; ++d) {
+    H *= s->strata_m;
+    if (H > 2147483647LL) return -1;
+  }
+  return H;
+}
+
+int ora_set_strata(ora_state *s, int m) {
+  if (m < 0) return -1;
+  int old = s->strata_m;
+  s->strata_m = m;
+  if (ora_strata_cubes(s) < 0) {
+    s->strata_m = old;
+    return -1;
+  }
+  s->strata_npc = 0;
+  return 0;
+}
+
+int64_t ora_strata_npc(const ora_state *s) { return s->strata_npc; }
+
+int ora_iterate(ora_state *s, int64_t n_req, double out[4]) {
+  if (n_req < 2) return -1;
+  /* stratified: npc = floor(n / m^D) >= 2 events in each hypercube, n = m^D npc used */
+  int64_t H = ora_strata_cubes(s), n = n_req;
+  if (H > 0) {
+    if (n_req / H < 2) return -1;
+    s->strata_npc = n_req / H;
+    n = H * s->strata_npc;
+  }
+  double *wrec = H > 0 ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
   int D = s->ndim, nb = s->nbins;
   for (int i = 0; i < D * nb; ++i) s->d[i] = 0.0L;
   long double s1 = 0.0L, s2 = 0.0L;
@@ -862,6 +913,7 @@ int ora_iterate(ora_state *s, int64_t n, double out[4]) {
   for (int64_t i = 0; i < n; ++i) {
     double o = 0.0;
     double w = event_weight_obs(s, s->iter, (uint64_t)i, b, s->nobs ? &o : NULL);
+    if (wrec) wrec[i] = isfinite(w) ? w : 0.0;
     if (!isfinite(w)) { ++nnf; continue; }
     if (w != 0.0) ++nz;
     double w2 = w * w;
@@ -879,6 +931,24 @@ int ora_iterate(ora_state *s, int64_t n, double out[4]) {
   s->have_hist = 1;
   double mean = (double)(s1 / (long double)n);
   double var = (double)((s2 / (long double)n - (long double)mean * (long double)mean) / (long double)(n - 1));
+  if (H > 0) {
+    /* stratified estimate: I = sum_h (1/H) mean_h = S1 / n (equal counts), and
+     * var = sum_h (1/H)^2 sigma_h^2 / npc with the within-hypercube sample variance
+     * sigma_h^2 = sum_{i in h} (w_i - mean_h)^2 / (npc - 1) */
+    int64_t c = s->strata_npc;
+    long double V = 0.0L;
+    for (int64_t h = 0; h < H; ++h) {
+      long double sh = 0.0L;
+      for (int64_t k = 0; k < c; ++k) sh += wrec[h * c + k];
+      long double mh = sh / (long double)c;
+      for (int64_t k = 0; k < c; ++k) {
+        long double dv = (long double)wrec[h * c + k] - mh;
+        V += dv * dv;
+      }
+    }
+    var = (double)(V / ((long double)H * (long double)H * (long double)c * (long double)(c - 1)));
+    free(wrec);
+  }
   if (s->n_iter == s->cap) {
     s->cap *= 2;
     s->Ij = (double *)realloc(s->Ij, sizeof(double) * s->cap);

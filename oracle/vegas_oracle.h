@@ -99,6 +99,12 @@ uint32_t ora_get_iteration(const ora_state *s);
 int ora_set_observable(ora_state *s, int nbins, double lo, double hi, int first);
 int ora_get_observable(const ora_state *s, double *last, double *last_err, double *comb,
                        double *comb_err);
+/* stratified sampling (Lepage's stratified + importance mode): m strata per axis,
+ * 0 = off.  An iteration of n events then uses npc = floor(n / m^D) >= 2 events per
+ * hypercube (n = m^D npc of them), event i in hypercube floor(i / npc). */
+int ora_set_strata(ora_state *s, int m);
+int64_t ora_strata_cubes(const ora_state *s);
+int64_t ora_strata_npc(const ora_state *s);
 /* weights (and bin indices, [n][ndim]) of events [first, first+n) of iteration iter at the current grid */
 int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t n,
                       double *w, uint8_t *bins);
