@@ -91,6 +91,8 @@ def parse_args():
     ap.add_argument("--events", type=int, default=0, help="events per iteration (0: workload's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32me"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--strata", type=int, default=-1,
+                    help="strata per axis of the stratified leg (-1: floor((N/2)^(1/D)), Lepage's choice; 0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=5)
     ap.add_argument("--cpu-events", type=int, default=0,
                     help="events per oracle iteration (0: the workload's sample, 10-30 s of host time)")
@@ -483,6 +485,56 @@ def observable_leg(args, make, Wn, N, plain_ms_min, plain_event):
             "fold_cols": shape["fold_cols"]}
 
 
+def strata_leg(args, make, Wn, N, D, plain_ms_min, plain_hist):
+    """The same steps with stratified sampling (Lepage's stratified + importance mode,
+    m strata per axis): ms per step (min over 10 blocks of K steps), and the timed
+    iterations' combined relative error against the plain path's over the same
+    iteration numbers, as effective events/s 1 / (eps^2 T)."""
+    import torch
+    m = args.strata if args.strata > 0 else int((N / 2) ** (1.0 / D) + 1e-9)
+    H = m ** D
+    g = make()
+    g.set_strata(m)
+    for _ in range(Wn):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    hist = history_from_state(g.get_state(), g.ndim, g.nbins)[Wn:Wn + args.steps]
+    reps = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            g.iterate(N, sync=False)
+            g.refine()
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t1) / args.steps * 1e3)
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    for _ in range(args.steps):
+        g.iterate(N, sync=False)
+        g.refine()
+    torch.cuda.synchronize()
+    st = g.stage_times()
+    g.close()
+    I, sig = combine(hist)
+    Ip, sigp = combine(plain_hist)
+    used = H * (N // H)
+    eff = 1.0 / ((sig / abs(I)) ** 2 * T) if sig > 0 else None
+    return {"strata_per_axis": m, "hypercubes": H, "events_per_hypercube": N // H, "events_used": used,
+            "ms_per_step_min": min(reps), "ms_per_step_min_plain": plain_ms_min,
+            "step_overhead": min(reps) / plain_ms_min - 1.0,
+            "rel_error": sig / abs(I), "rel_error_plain": sigp / abs(Ip),
+            "effective_events_per_s": eff,
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()}}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -567,6 +619,7 @@ def main():
 
     obs_leg = observable_leg(args, make, Wn, N, min(reps), st["event"]) \
         if args.workload in OBS_BINNING else None
+    strata = strata_leg(args, make, Wn, N, cfg["ndim"], min(reps), timed) if args.strata != 0 else None
 
     ms_ev, n_ev = st["event"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
@@ -610,6 +663,7 @@ def main():
         "roofline": roof,
         "histogram_stage": hist_stage,
         "observable": obs_leg,
+        "strata": strata,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters,

@@ -171,6 +171,23 @@ int vegas_result(vegas_handle h, double *integral, double *error, double *chi2_d
 int vegas_result_from(vegas_handle h, int32_t first, double *integral, double *error,
                       double *chi2_dof, int32_t *n_iter);
 
+/* Stratified sampling on top of the importance grid (Lepage's stratified +
+ * importance mode; the paper cites VEGAS (Sec. 2.1) but does not say which mode
+ * MCFM runs): strata_per_axis = m cuts the unit cube of the grid's inputs into
+ * H = m^ndim equal hypercubes (0 turns it off, the default).  An iteration asked
+ * for n events then uses npc = floor(n / H) >= 2 events in every hypercube, so
+ * H npc events in all (reported in n_events; refused with VEGAS_EINVAL if
+ * npc < 2); event i lies in hypercube floor(i / npc), whose coordinates are the
+ * base-m digits of its index (dimension 0 the least significant), and its
+ * uniforms r are placed inside it, u = (c + r) / m, before the grid map.  The
+ * estimate stays the mean of the weights (equal counts per hypercube); its
+ * variance becomes sum_h (1/H)^2 sigma_h^2 / npc with sigma_h^2 the sample
+ * variance of the weights in hypercube h (exact, launch-independent sums).  The
+ * grid histogram is unchanged.  Not with the learned proposal
+ * (vegas_iterate_flow refuses while it is set).  Errors: VEGAS_EINVAL (m < 0,
+ * or m^ndim above 2^31 - 1). */
+int vegas_set_strata(vegas_handle h, int32_t strata_per_axis);
+
 /* Histogram of the process's observable, filled by the same events and weights
  * as the integral (Sec. 2.1: the integrator returns cross sections and
  * distributions of kinematic variables; Sec. 3.2 shows such distributions, the

@@ -49,6 +49,22 @@ __host__ __device__ constexpr int part_ld(int ncol) { return (ncol + 31) & ~31; 
 constexpr int kFusedLdsMax = 48 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
 // observable histogram: bins 1..nobs uniform on [lo, hi), 0 = underflow, nobs + 1 = overflow
 constexpr int kObsLd = VEGAS_MAX_OBS_BINS + 2;
+constexpr int kStrataBlocks = 1024;  // blocks of the hypercube fold (rows of its partials)
+
+// n / d for n < 2^31 by multiply and shift: with l = ceil(log2 d), M = floor(2^(32+l) / d)
+// + 1 < 2^33 gives floor(n M / 2^(32+l)) = floor(n / d) exactly, and n M < 2^64
+struct UDiv {
+  unsigned long long M;
+  int s;
+};
+inline UDiv udiv_magic(uint32_t d) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  return {(1ull << (32 + l)) / d + 1ull, 32 + l};
+}
+__device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv q) {
+  return static_cast<uint32_t>((static_cast<unsigned long long>(n) * q.M) >> q.s);
+}
 __host__ __device__ constexpr int obs_cols(int nobs) { return nobs > 0 ? 6 * (nobs + 2) : 0; }
 
 struct DevBufs {
@@ -66,6 +82,8 @@ struct DevBufs {
   double* obs_acc;               // [3 kObsLd + 2] combination: sum w_j H, sum w_j^2 var, sum H (zero-variance
                                  //   iterations), then sum w_j and the count of zero-variance iterations
   double* obs_out;               // [4][kObsLd] last H, its error, the combination, its error
+  long long* strat_part;         // [kStrataBlocks][4] per-block digits of V = sum_h sum_{i in h}
+                                 //   (w_i - mean_h)^2 (stratified sampling; summed by the finalisation)
   double* history;               // [VEGAS_MAX_ITER][2] I_j, var_j
   double* iter_out;              // [8] I_j, var_j, nz, nnf, N
   double* result;                // [4] I, sigma, chi2/dof, n_iter
@@ -212,6 +230,9 @@ struct EventArgs {
   const float* ext_lq;
   int nobs;             // observable bins (OBS kernels only)
   double obs_lo, obs_hi, obs_scale;
+  int strata_m, strata_npc;  // STRAT kernels: strata per axis, events per hypercube
+  double strata_md;          // strata_m as binary64
+  UDiv div_m, div_npc;       // division by strata_m and by strata_npc
 };
 
 // ---------------------------------------------------------------------------
@@ -232,7 +253,11 @@ constexpr int event_min_waves() {
 // finalisation re-folds from the records if the scales turn out not to fit.
 // OBS: the event's observable bin is recorded (and, fused, its w and w^2 digits
 // go to that bin's six columns after the grid histogram's).
-template <int PROC, int PREC, int D, int MAXT, bool EXT = false, bool FUSED = false, bool OBS = false>
+// STRAT: stratified sampling (Lepage's stratified + importance mode): event i lies in
+// hypercube floor(i / npc) of the m^D equal ones, u = (c + r) / m with c the base-m
+// digits of the hypercube (dimension 0 the least significant).
+template <int PROC, int PREC, int D, int MAXT, bool EXT = false, bool FUSED = false, bool OBS = false,
+          bool STRAT = false>
 __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) void k_event(EventArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.nbins, nd = D > 0 ? D : a.ndim;
@@ -255,6 +280,7 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     // clear this iteration's digit totals (the previous iteration's were consumed
     // by its finalisation, earlier on the stream)
     for (int i = threadIdx.x; i < ncol; i += blockDim.x) a.b.acc_tot[i] = 0;
+
   }
   int E1 = 0, E2 = 0;
   if constexpr (FUSED) {
@@ -279,6 +305,17 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
       }
     } else {
       event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
+      if constexpr (STRAT) {
+        uint32_t hc = udiv(static_cast<uint32_t>(i), a.div_npc);
+        const uint32_t m = static_cast<uint32_t>(a.strata_m);
+#pragma unroll
+        for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
+          if (d >= nd) break;
+          const uint32_t q = udiv(hc, a.div_m);
+          u[d] = (static_cast<double>(hc - q * m) + u[d]) / a.strata_md;
+          hc = q;
+        }
+      }
     }
     const double J = grid_map<D>(e_lds, n, nd, u, x, bins);
     // the bins, 4 of 8 bits per word.  With 10 or more fixed dimensions they are
@@ -385,6 +422,53 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
 constexpr int kColTile = 32, kRowTile = 32;
 
 // ---------------------------------------------------------------------------
+// stratified sampling: per hypercube (its npc events are consecutive records) the
+// mean and then the sum of squared deviations V_h, in binary64 in record order, one
+// thread per hypercube; V = sum_h V_h folded exactly (order-free integer digits) at
+// the scale of npc max w^2, which bounds every V_h.  Each block writes one row of
+// digit sums (no same-address atomics); the finalisation adds the rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int strata_exponent(double wmax, int npc) {
+  return fx_exponent(wmax * wmax * static_cast<double>(npc));
+}
+
+__global__ void k_strata(DevBufs b, int64_t H, int npc) {
+  const int EV = strata_exponent(__longlong_as_double(static_cast<long long>(b.maxw[0])), npc);
+  long long s0 = 0, s1 = 0, s2 = 0;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
+    const double* w = b.rec_w + h * npc;
+    double sum = 0.0;
+    for (int k = 0; k < npc; ++k) sum += w[k];
+    const double mh = sum / static_cast<double>(npc);
+    double V = 0.0;
+    for (int k = 0; k < npc; ++k) {
+      const double dv = w[k] - mh;
+      V = __fma_rn(dv, dv, V);
+    }
+    long long d0, d1, d2;
+    fx_digits_pos(V, EV, d0, d1, d2);
+    s0 += d0;
+    s1 += d1;
+    s2 += d2;
+  }
+  __shared__ long long red[3];
+  if (threadIdx.x < 3) red[threadIdx.x] = 0;
+  __syncthreads();
+  s0 = wave_sum_i64(s0);
+  s1 = wave_sum_i64(s1);
+  s2 = wave_sum_i64(s2);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(red);
+    atomicAdd(p + 0, static_cast<unsigned long long>(s0));
+    atomicAdd(p + 1, static_cast<unsigned long long>(s1));
+    atomicAdd(p + 2, static_cast<unsigned long long>(s2));
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) b.strat_part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
 // K2 (two-pass fold): exact accumulation of S1, S2 and d from the records at the
 // scales of this iteration's own max |w|.  Block (x, y) holds the histogram of
 // dimensions [y dpg, (y + 1) dpg) in LDS (and S1, S2 when y == 0) and writes its
@@ -462,8 +546,30 @@ struct FinArgs {
   int fold_lds;  // bytes of dynamic LDS before the refinement scratch (the re-fold's digits)
   int obs_lds;   // byte offset of the observable scratch [2 (nobs + 2)] doubles
   int nobs, obs_first;
+  int64_t strata_H;  // > 0: stratified, var_j from the hypercubes' V
+  int strata_npc;
+  int strata_blocks;  // rows of the hypercube fold's partials
   double alpha;
 };
+
+// var_j: the plain (S2 / N - I^2) / (N - 1), or, stratified, sum_h (1/H)^2 sigma_h^2 / npc
+// = V / (H^2 npc (npc - 1)) with V from the hypercube fold, whose row sums the block
+// left per wave in sv (wmax: this iteration's max |w|, read by every thread before
+// the finalisation clears it)
+__device__ __forceinline__ double iteration_variance(const FinArgs& f, double S1, double S2, double wmax,
+                                                     const long long (*sv)[3]) {
+  const double N = static_cast<double>(f.nev);
+  if (f.strata_H > 0) {
+    long long t[3] = {0, 0, 0};
+    for (int w = 0; w < static_cast<int>(blockDim.x) / kWave; ++w)
+      for (int k = 0; k < 3; ++k) t[k] += sv[w][k];
+    const double V = fx_value(t[0], t[1], t[2], strata_exponent(wmax, f.strata_npc));
+    const double H = static_cast<double>(f.strata_H), c = static_cast<double>(f.strata_npc);
+    return V / (H * H * c * (c - 1.0));
+  }
+  const double I = S1 / N;
+  return fma(-I, I, S2 / N) / (N - 1.0);
+}
 
 __device__ __forceinline__ void refine_dim(bool active, bool preloaded, int n, double alpha, const double* hist,
                                            const double* e_in, double* e_out, double* sm);
@@ -519,6 +625,24 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
   // one sum w^2 (scale E2); their values go to osm
   double* osm = reinterpret_cast<double*>(smem + f.obs_lds);
   const int nslot_all = nslot + 2 + (OBS ? 2 * (f.nobs + 2) : 0);
+  // stratified: the hypercube fold's row sums, per wave (rows strided over the block)
+  __shared__ long long sv[16][3];
+  if (f.strata_H > 0) {  // block-uniform
+    long long t0 = 0, t1 = 0, t2 = 0;
+    for (int r = threadIdx.x; r < f.strata_blocks; r += blockDim.x) {
+      t0 += b.strat_part[r * 4 + 0];
+      t1 += b.strat_part[r * 4 + 1];
+      t2 += b.strat_part[r * 4 + 2];
+    }
+    t0 = wave_sum_i64(t0);
+    t1 = wave_sum_i64(t1);
+    t2 = wave_sum_i64(t2);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      sv[threadIdx.x / kWave][0] = t0;
+      sv[threadIdx.x / kWave][1] = t1;
+      sv[threadIdx.x / kWave][2] = t2;
+    }
+  }
   // the combination so far, one bin per thread (nobs + 2 <= 256 <= blockDim.x), read
   // before the barrier that precedes its update
   double ws_old = 0.0, zc_old = 0.0, aw = 0.0, av = 0.0, az = 0.0;
@@ -550,7 +674,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     const double S1 = s12[0], S2 = s12[1];
     const double N = static_cast<double>(f.nev);
     const double I = S1 / N;
-    const double var = fma(-I, I, S2 / N) / (N - 1.0);
+    const double var = iteration_variance(f, S1, S2, wmax, sv);
     b.history[2 * f.iter] = I;
     b.history[2 * f.iter + 1] = var;
     b.iter_out[0] = I;
@@ -571,8 +695,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     // integral; iterations from obs_first on are combined with the integral's
     // weights 1 / var_j (the plain mean once an iteration has zero variance)
     const double N = static_cast<double>(f.nev);
-    const double I = s12[0] / N;
-    const double var = fma(-I, I, s12[1] / N) / (N - 1.0);
+    const double var = iteration_variance(f, s12[0], s12[1], wmax, sv);
     const bool on = f.iter >= static_cast<uint32_t>(f.obs_first);
     const bool pos = var > 0.0;
     const double wj = pos ? 1.0 / var : 0.0;
@@ -842,7 +965,7 @@ thread_local std::string g_last_hip_error;
 
 struct Layout {
   size_t edges, edges_alt, rec_w, rec_bins, rec_obs, maxw, cnt, fxs, part_acc, acc_tot, hist, obs_acc, obs_out,
-      history, iter_out, result, total;
+      strat_acc, history, iter_out, result, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -871,6 +994,7 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.hist = take(sizeof(double) * (D * n + 2));
   L.obs_acc = take(sizeof(double) * (3 * kObsLd + 2));
   L.obs_out = take(sizeof(double) * 4 * kObsLd);
+  L.strat_acc = take(sizeof(long long) * 4 * kStrataBlocks);
   L.history = take(sizeof(double) * 2 * VEGAS_MAX_ITER);
   L.iter_out = take(sizeof(double) * 8);
   L.result = take(sizeof(double) * 4);
@@ -1079,6 +1203,7 @@ struct vegas_state {
   int nobs, obs_first;          // observable histogram: bins (0 = off) and first combined iteration
   double obs_lo, obs_hi;
   bool obs_have;                // an iteration ran since the observable was set
+  int strata_m;                 // stratified sampling: strata per axis (0 = off)
   size_t smem_max;              // LDS per block the launches may use
   int refine_lds;               // LDS of the refinement scratch: D * 4 (n + 1) doubles
   bool scale_valid;             // the device holds scales from a previous iteration (b.fxs)
@@ -1178,23 +1303,31 @@ void stage_collect(vegas_state* h) {
   h->ev_pending.clear();
 }
 
-template <int PROC, int PREC, int D, bool EXT, bool FUSED, bool OBS>
+template <int PROC, int PREC, int D, bool EXT, bool FUSED, bool OBS, bool STRAT>
 hipError_t launch_event_tfo(vegas_state* h, const EventArgs& a, int blocks, int threads) {
   TimedLaunch t(h, 0);
   const int lds = FUSED ? h->fused_lds : h->event_lds;
   if (EXT || threads <= 256)
-    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 256, EXT, FUSED, OBS>), dim3(blocks), dim3(EXT ? 256 : threads),
-                          lds, h->stream, t.e0, t.e1, 0, a);
+    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 256, EXT, FUSED, OBS, STRAT>), dim3(blocks),
+                          dim3(EXT ? 256 : threads), lds, h->stream, t.e0, t.e1, 0, a);
   else
-    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 1024, false, FUSED, OBS>), dim3(blocks), dim3(threads), lds,
+    hipExtLaunchKernelGGL((k_event<PROC, PREC, D, 1024, false, FUSED, OBS, STRAT>), dim3(blocks), dim3(threads), lds,
                           h->stream, t.e0, t.e1, 0, a);
   return t.done();
 }
 
+// the learned proposal replaces the stratified placement, so EXT kernels have no STRAT variant
+template <int PROC, int PREC, int D, bool EXT, bool FUSED, bool OBS>
+hipError_t launch_event_tfs(vegas_state* h, const EventArgs& a, int blocks, int threads) {
+  if constexpr (!EXT)
+    if (a.strata_m > 0) return launch_event_tfo<PROC, PREC, D, EXT, FUSED, OBS, true>(h, a, blocks, threads);
+  return launch_event_tfo<PROC, PREC, D, EXT, FUSED, OBS, false>(h, a, blocks, threads);
+}
+
 template <int PROC, int PREC, int D, bool EXT, bool FUSED>
 hipError_t launch_event_tf(vegas_state* h, const EventArgs& a, int blocks, int threads) {
-  return a.nobs > 0 ? launch_event_tfo<PROC, PREC, D, EXT, FUSED, true>(h, a, blocks, threads)
-                    : launch_event_tfo<PROC, PREC, D, EXT, FUSED, false>(h, a, blocks, threads);
+  return a.nobs > 0 ? launch_event_tfs<PROC, PREC, D, EXT, FUSED, true>(h, a, blocks, threads)
+                    : launch_event_tfs<PROC, PREC, D, EXT, FUSED, false>(h, a, blocks, threads);
 }
 
 template <int PROC, int PREC, int D, bool EXT = false>
@@ -1238,14 +1371,19 @@ bool ext_supported(const vegas_state* h) {
   return h->D == 8 && (p == VEGAS_GAUSS || p == VEGAS_GENZ || p == VEGAS_WW_4L);
 }
 
+template <int PROC, int PREC, int D, bool FUSED, bool OBS>
+const void* event_kernel_ptr(bool strat) {
+  return strat ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, FUSED, OBS, true>)
+               : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, FUSED, OBS, false>);
+}
+
 template <int PROC, int PREC, int D>
-int occupancy_event_t(int lds, bool fused, bool obs) {
+int occupancy_event_t(int lds, bool fused, bool obs, bool strat) {
   int nb = 0;
-  const void* k =
-      fused ? (obs ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, true, true>)
-                   : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, true>))
-            : (obs ? reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256, false, false, true>)
-                   : reinterpret_cast<const void*>(&k_event<PROC, PREC, D, 256>));
+  const void* k = fused ? (obs ? event_kernel_ptr<PROC, PREC, D, true, true>(strat)
+                               : event_kernel_ptr<PROC, PREC, D, true, false>(strat))
+                        : (obs ? event_kernel_ptr<PROC, PREC, D, false, true>(strat)
+                               : event_kernel_ptr<PROC, PREC, D, false, false>(strat));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, lds) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -1253,18 +1391,19 @@ int occupancy_event_t(int lds, bool fused, bool obs) {
 
 int occupancy_event(const vegas_state* h, bool fused) {
   const int lds = fused ? h->fused_lds : h->event_lds;
-  const bool o = h->nobs > 0;
+  const bool o = h->nobs > 0, st = h->strata_m > 0;
   switch (h->cfg.process) {
-    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds, fused, o);
-    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds, fused, o);
-    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds, fused, o);
-    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds, fused, o);
-    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds, fused, o);
+    case VEGAS_GAUSS: return occupancy_event_t<VEGAS_GAUSS, VEGAS_FP64, 0>(lds, fused, o, st);
+    case VEGAS_GENZ: return occupancy_event_t<VEGAS_GENZ, VEGAS_FP64, 0>(lds, fused, o, st);
+    case VEGAS_EEMUMU: return occupancy_event_t<VEGAS_EEMUMU, VEGAS_FP64, 2>(lds, fused, o, st);
+    case VEGAS_DY_Z: return occupancy_event_t<VEGAS_DY_Z, VEGAS_FP64, 3>(lds, fused, o, st);
+    case VEGAS_W_PLUS: return occupancy_event_t<VEGAS_W_PLUS, VEGAS_FP64, 4>(lds, fused, o, st);
     case VEGAS_WW_4L:
-      if (h->cfg.precision == VEGAS_FP32_ME) return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds, fused, o);
-      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds, fused, o);
+      if (h->cfg.precision == VEGAS_FP32_ME)
+        return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP32_ME, 8>(lds, fused, o, st);
+      return occupancy_event_t<VEGAS_WW_4L, VEGAS_FP64, 8>(lds, fused, o, st);
     case VEGAS_WW_HAD:
-      return occupancy_event_t<VEGAS_WW_HAD, VEGAS_FP64, 10>(lds, fused, o);
+      return occupancy_event_t<VEGAS_WW_HAD, VEGAS_FP64, 10>(lds, fused, o, st);
   }
   return 1;
 }
@@ -1375,6 +1514,7 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   h->b.rec_obs = reinterpret_cast<uint8_t*>(B + L.rec_obs);
   h->b.obs_acc = reinterpret_cast<double*>(B + L.obs_acc);
   h->b.obs_out = reinterpret_cast<double*>(B + L.obs_out);
+  h->b.strat_part = reinterpret_cast<long long*>(B + L.strat_acc);
   h->b.history = reinterpret_cast<double*>(B + L.history);
   h->b.iter_out = reinterpret_cast<double*>(B + L.iter_out);
   h->b.result = reinterpret_cast<double*>(B + L.result);
@@ -1478,8 +1618,24 @@ namespace {
 
 // one iteration: events (from the counter stream, or from the learned proposal's
 // points when ext_y is given), then the exact accumulation and the combination
-int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const float* ext_lq,
+// hypercubes of the stratified sampling (0: off; < 0: more than 2^31 - 1)
+int64_t strata_cubes(const vegas_state* h) {
+  if (h->strata_m <= 0) return 0;
+  int64_t H = 1;
+  for (int d = 0; d < h->D; ++d) {
+    H *= h->strata_m;
+    if (H > 2147483647LL) return -1;
+  }
+  return H;
+}
+
+int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float* ext_lq,
                   vegas_iter_result* out) {
+  // stratified: npc = floor(n / H) events in each of the H hypercubes, n = H npc used
+  const int64_t H = ext_y ? 0 : strata_cubes(h);
+  const int64_t npc = H > 0 ? n_req / H : 0;
+  if (H < 0 || (H > 0 && npc < 2)) return VEGAS_EINVAL;
+  const int64_t n_events = H > 0 ? H * npc : n_req;
   const int threads = ext_y ? 256 : pick_threads(h);
   const int nslot = h->D * h->n;
   EventArgs ea;
@@ -1497,6 +1653,11 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
   ea.obs_lo = h->obs_lo;
   ea.obs_hi = h->obs_hi;
   ea.obs_scale = h->nobs ? static_cast<double>(h->nobs) / (h->obs_hi - h->obs_lo) : 0.0;
+  ea.strata_m = H > 0 ? h->strata_m : 0;
+  ea.strata_npc = static_cast<int>(npc);
+  ea.strata_md = static_cast<double>(h->strata_m);
+  ea.div_m = udiv_magic(static_cast<uint32_t>(h->strata_m > 0 ? h->strata_m : 1));
+  ea.div_npc = udiv_magic(static_cast<uint32_t>(npc > 0 ? npc : 1));
   // fused fold (digits added by the event kernel at the previous iteration's scales)
   // whenever such scales exist and the digits fit in LDS; the choice depends on
   // the history and the configuration only, never on the launch shape
@@ -1530,6 +1691,13 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
                           dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
     VG_HIP(t.done());
   }
+  const int strata_blocks = H > 0 ? static_cast<int>(std::min<int64_t>((H + 255) / 256, kStrataBlocks)) : 0;
+  if (H > 0) {
+    TimedLaunch t(h, 1);
+    hipExtLaunchKernelGGL(k_strata, dim3(strata_blocks), dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, H,
+                          static_cast<int>(npc));
+    VG_HIP(t.done());
+  }
   h->last_launch[0] = ev_blocks;
   h->last_launch[1] = threads;
   h->last_launch[2] = rows;
@@ -1548,6 +1716,9 @@ int run_iteration(vegas_handle h, int64_t n_events, const float* ext_y, const fl
     fa.obs_lds = fa.fold_lds + (fa.spec ? h->refine_lds : 0);
     fa.nobs = h->nobs;
     fa.obs_first = h->obs_first;
+    fa.strata_H = H;
+    fa.strata_npc = static_cast<int>(npc);
+    fa.strata_blocks = strata_blocks;
     fa.alpha = h->cfg.alpha;
     const int lds = fa.obs_lds + (h->nobs ? static_cast<int>(sizeof(double) * 2 * (h->nobs + 2)) : 0);
     TimedLaunch t(h, 2);
@@ -1596,7 +1767,7 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result* out) {
 
 int vegas_iterate_flow(vegas_handle h, vegas_flow f, int64_t n_events, vegas_iter_result* out) {
   if (!h || !f) return VEGAS_EINVAL;
-  if (!ext_supported(h) || n_events < 2 || n_events > h->maxN) return VEGAS_EINVAL;
+  if (!ext_supported(h) || n_events < 2 || n_events > h->maxN || h->strata_m > 0) return VEGAS_EINVAL;
   if (h->iter >= VEGAS_MAX_ITER) return VEGAS_ESTATE;
   const float *y = nullptr, *lq = nullptr;
   int rc = flow_sample_events(f, h->stream, h->cfg.seed, h->iter, n_events, &y, &lq);
@@ -1671,6 +1842,18 @@ int vegas_set_observable(vegas_handle h, int32_t nbins, double lo, double hi, in
   hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, h->stream,
                      reinterpret_cast<unsigned long long*>(h->b.obs_acc), static_cast<int64_t>(3 * kObsLd + 2));
   VG_HIP(hipGetLastError());
+  return VEGAS_OK;
+}
+
+int vegas_set_strata(vegas_handle h, int32_t strata_per_axis) {
+  if (!h || strata_per_axis < 0) return VEGAS_EINVAL;
+  const int old = h->strata_m;
+  h->strata_m = strata_per_axis;
+  if (strata_cubes(h) < 0) {
+    h->strata_m = old;
+    return VEGAS_EINVAL;
+  }
+  configure_lds(h);  // occupancy of the stratified event kernels
   return VEGAS_OK;
 }
 

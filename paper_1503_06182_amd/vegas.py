@@ -23,7 +23,7 @@ MAX_ITER = 4096
 MAX_OBS_BINS = 254
 
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
-           "vegas_result_from", "vegas_set_observable", "vegas_get_observable",
+           "vegas_result_from", "vegas_set_observable", "vegas_get_observable", "vegas_set_strata",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
            "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_last_launch",
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH):
     L.vegas_result.argtypes = [vp, dp, dp, dp, C.POINTER(i32)]
     L.vegas_result_from.argtypes = [vp, i32, dp, dp, dp, C.POINTER(i32)]
     L.vegas_set_observable.argtypes = [vp, i32, C.c_double, C.c_double, i32]
+    L.vegas_set_strata.argtypes = [vp, i32]
     L.vegas_get_observable.argtypes = [vp, vp, vp, vp, vp]
     L.vegas_get_grid.argtypes = [vp, vp]
     L.vegas_set_grid.argtypes = [vp, vp]
@@ -198,6 +199,10 @@ class Integrator:
         _check(self._L.vegas_result_from(self._h, first, C.byref(I), C.byref(e), C.byref(c), C.byref(n)),
                "vegas_result_from")
         return {"I": I.value, "sigma": e.value, "chi2_dof": c.value, "n_iter": n.value}
+
+    def set_strata(self, m):
+        """m strata per axis (0: off): iterations then use m^ndim floor(n / m^ndim) events."""
+        _check(self._L.vegas_set_strata(self._h, m), "vegas_set_strata")
 
     def set_observable(self, nbins, lo=0.0, hi=1.0, first=0):
         """Histogram the process's observable in nbins uniform bins on [lo, hi)

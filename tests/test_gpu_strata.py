@@ -1,0 +1,168 @@
+"""GPU parity of the stratified sampling (Lepage's stratified + importance mode)
+against the oracle, through the C ABI.
+
+Bars as for the plain iteration: per-event weights within 1e-12, bins exact, the
+iteration's integral and stratified variance within 1e-10 with the grid injected
+into the oracle, the same event count, byte-identical results for every launch
+configuration and for every fold.
+"""
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+GAUSS_MAX = dict(process=W.GAUSS, ndim=16, nbins=255, seed=5, alpha=1.5, params=[0.5, 0.3])
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1503_06182_amd as P
+    P.load()
+    return P
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+# (name, config, strata per axis, events asked for)
+CASES = [("gauss4", W.config("gauss4"), 4, 6007),
+         ("eemumu", W.config("eemumu"), 8, 6007),
+         ("dy_z", W.config("dy_z"), 6, 6007),
+         ("w_plus", W.config("w_plus"), 5, 6007),
+         ("ww_4l", W.config("ww_4l"), 2, 4099),
+         ("ww_had", W.config("ww_had"), 2, 4099),
+         ("gauss16x255", GAUSS_MAX, 2, 131_101)]
+
+
+def pair(P, cfg, n, m):
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"], max_events=n)
+    o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
+    g.set_strata(m)
+    o.set_strata(m)
+    return g, o
+
+
+@pytest.mark.parametrize("name,cfg,m,n", CASES, ids=[c[0] for c in CASES])
+def test_stratified_iterations_match_oracle(P, name, cfg, m, n):
+    g, o = pair(P, cfg, n, m)
+    H = m ** cfg["ndim"]
+    used = H * (n // H)
+    for it in range(3):
+        o.set_grid(g.get_grid())
+        o.iteration = it
+        rg, ro = g.iterate(n), o.iterate(n)
+        assert rg["n_events"] == ro["n_events"] == used
+        wg, bg = g.get_weights(0, used)
+        wo, bo = o.event_weights(it, 0, used)
+        assert np.array_equal(bg, bo), f"{name} it{it}: bins"
+        nz = wo != 0
+        assert np.array_equal(wg != 0, nz), f"{name} it{it}: cut flips"
+        assert np.all(np.abs(wg - wo) <= 1e-12 * np.abs(wo) + 1e-14 * np.mean(np.abs(wo))), name
+        assert rel(rg["I"], ro["I"]) < REL, (name, it, rg, ro)
+        assert rel(rg["var"], ro["var"]) < REL, (name, it, rg, ro)
+        g.refine()
+        o.refine()
+
+
+def test_one_stratum_is_the_plain_iteration(P):
+    cfg = W.config("w_plus")
+    n = 50_000
+    a = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+    b = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+    b.set_strata(1)
+    for _ in range(3):
+        ra, rb = a.iterate(n), b.iterate(n)
+        assert ra["I"] == rb["I"] and rel(rb["var"], ra["var"]) < 1e-12
+        a.refine()
+        b.refine()
+
+
+def run_schedule(P, cfg, n, m, **kw):
+    g = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"], max_events=n, **kw)
+    g.set_strata(m)
+    out = []
+    for _ in range(3):
+        r = g.iterate(n)
+        out.append(np.array([r["I"], r["var"]]).tobytes() + g.get_grid().tobytes())
+        g.refine()
+    return b"".join(out)
+
+
+@pytest.mark.parametrize("name,m", [("w_plus", 6), ("gauss16x255", 2)])
+def test_stratified_bit_identical_across_launch_configurations(P, name, m):
+    cfg = GAUSS_MAX if name == "gauss16x255" else W.config(name)
+    n = 200_003 if name == "gauss16x255" else 50_021
+    ref = run_schedule(P, cfg, n, m)
+    for wpb, mb in ((1, 0), (2, 3), (8, 0), (16, 5), (4, 97)):
+        assert run_schedule(P, cfg, n, m, waves_per_block=wpb, max_blocks=mb) == ref, (wpb, mb)
+
+
+def test_stratified_variance_is_the_same_for_every_fold(P):
+    """The hypercube fold reads the records, so the two-pass fold, the fused fold and
+    both forced re-folds give the same variance bits."""
+    cfg = W.config("w_plus")
+    n = 50_000
+
+    def mk():
+        g = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+        g.set_strata(5)
+        return g
+
+    a = mk()
+    a.iterate(n)
+    a.refine()
+    blob = a.get_state()
+    off = struct.calcsize("<Q3iIQ")
+    e1 = struct.unpack_from("<2i", blob, off)[1]
+    r1 = a.iterate(n)
+    assert r1["fold"] == 1
+    for v, e in ((0, 0), (1, e1 - 30), (1, e1 + 100)):
+        b = mk()
+        b.set_state(blob[:off] + struct.pack("<4i", v, e, 2 * e, 0) + blob[off + 16:])
+        r = b.iterate(n)
+        assert r["fold"] == (0 if v == 0 else 2)
+        assert r["var"] == r1["var"] and abs(r["I"] / r1["I"] - 1) < 1e-15
+
+
+def test_full_size_w_plus_against_oracle(P):
+    """10^6 events in 10^4 hypercubes (10 strata per axis, 100 events each), the
+    bench workload's size: integral and stratified variance against the oracle."""
+    cfg = W.config("w_plus")
+    n = cfg["n_events"]
+    g, o = pair(P, cfg, n, 10)
+    for it in range(2):
+        o.set_grid(g.get_grid())
+        o.iteration = it
+        rg, ro = g.iterate(n), o.iterate(n)
+        assert rg["n_events"] == ro["n_events"] == n
+        assert rel(rg["I"], ro["I"]) < REL and rel(rg["var"], ro["var"]) < REL, (it, rg, ro)
+        g.refine()
+        o.refine()
+
+
+def test_strata_refusals(P):
+    cfg = W.config("gauss4")
+    g = P.Integrator(cfg["process"], 4, 50, 7, 1.5, cfg["params"], max_events=2000)
+    with pytest.raises(P.VegasError):
+        g.set_strata(-1)
+    with pytest.raises(P.VegasError):
+        g.set_strata(300)                    # 300^4 hypercubes
+    g.set_strata(5)                          # 625 hypercubes
+    with pytest.raises(P.VegasError):
+        g.iterate(1249)
+    assert g.iterate(1250)["n_events"] == 1250
+    assert g.iterate(1999)["n_events"] == 1875
+    g.set_strata(0)
+    assert g.iterate(1249)["n_events"] == 1249
