@@ -166,3 +166,52 @@ def test_strata_refusals(P):
     assert g.iterate(1999)["n_events"] == 1875
     g.set_strata(0)
     assert g.iterate(1249)["n_events"] == 1249
+
+
+@pytest.mark.parametrize("name,m,obs", [("w_plus", 5, (50, 20.0, 70.0)), ("ww_4l", 2, (60, 60.0, 100.0))])
+def test_stratified_with_observable_matches_oracle(P, name, m, obs):
+    """Both switches at once (the event kernels with the observable and the stratified
+    placement): weights, integral, stratified variance and every observable bin
+    against the oracle; the bins combine with the stratified var_j's weights."""
+    cfg = W.config(name)
+    n = 6007 if name == "w_plus" else 4099
+    g, o = pair(P, cfg, n, m)
+    g.set_observable(*obs, first=1)
+    o.set_observable(*obs, first=1)
+    used = m ** cfg["ndim"] * (n // m ** cfg["ndim"])
+    for it in range(3):
+        o.set_grid(g.get_grid())
+        o.iteration = it
+        rg, ro = g.iterate(n), o.iterate(n)
+        assert rg["n_events"] == ro["n_events"] == used
+        assert rel(rg["I"], ro["I"]) < REL and rel(rg["var"], ro["var"]) < REL, (it, rg, ro)
+        G, O = g.get_observable(), o.get_observable()
+        for k in range(4):
+            a, b = G[k], O[k]
+            assert np.array_equal(a == 0, b == 0)
+            assert np.all(np.abs(a - b) <= REL * np.abs(b) + 1e-12 * np.max(np.abs(b))), (it, k)
+        g.refine()
+        o.refine()
+
+
+def test_stratified_checkpoint_resume_is_bit_identical(P):
+    cfg = W.config("w_plus")
+    n = 40_000
+    mk = lambda: P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n)
+    a = mk()
+    a.set_strata(6)
+    for _ in range(2):
+        a.iterate(n)
+        a.refine()
+    blob = a.get_state()
+    for _ in range(2):
+        a.iterate(n)
+        a.refine()
+    b = mk()
+    b.set_strata(6)
+    b.set_state(blob)
+    for _ in range(2):
+        b.iterate(n)
+        b.refine()
+    assert a.result() == b.result()
+    assert np.array_equal(a.get_grid(), b.get_grid())
