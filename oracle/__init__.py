@@ -85,6 +85,10 @@ def lib():
         L.ora_strata_cubes.restype = C.c_int64
         L.ora_strata_npc.argtypes = [C.c_void_p]
         L.ora_strata_npc.restype = C.c_int64
+        _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        L.ora_set_strata_beta.argtypes = [C.c_void_p, C.c_double]
+        L.ora_get_strata_counts.argtypes = [C.c_void_p, _i64p]
+        L.ora_inject_strata_counts.argtypes = [C.c_void_p, _i64p]
         L.ora_event_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_int64, C.c_int64, _dp, _u8p]
         L.ora_grid_map.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_double),
                                    np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")]
@@ -199,7 +203,7 @@ class Vegas:
         if lib().ora_iterate(self._h, n, out) != 0:
             raise ValueError("oracle iterate failed")
         H = lib().ora_strata_cubes(self._h)
-        used = H * lib().ora_strata_npc(self._h) if H > 0 else n
+        used = H * lib().ora_strata_npc(self._h) if H > 0 and not getattr(self, "_adaptive", False) else n
         return {"I": out[0], "var": out[1], "n_nonzero": int(out[2]), "n_nonfinite": int(out[3]),
                 "n_events": int(used)}
 
@@ -217,6 +221,22 @@ class Vegas:
         """m strata per axis (0: off); an iteration of n events uses m^D floor(n / m^D)."""
         if lib().ora_set_strata(self._h, m) != 0:
             raise ValueError("invalid strata count")
+
+    def set_strata_beta(self, beta):
+        if lib().ora_set_strata_beta(self._h, beta) != 0:
+            raise ValueError("invalid beta")
+        self._adaptive = beta > 0
+
+    def strata_counts(self):
+        H = lib().ora_strata_cubes(self._h)
+        c = np.zeros(max(H, 0), dtype=np.int64)
+        if lib().ora_get_strata_counts(self._h, c) != 0:
+            raise RuntimeError("no stratified iteration yet")
+        return c
+
+    def inject_strata_counts(self, counts):
+        if lib().ora_inject_strata_counts(self._h, np.ascontiguousarray(counts, dtype=np.int64)) != 0:
+            raise ValueError("counts need adaptive strata")
 
     @property
     def strata_npc(self):

@@ -760,6 +760,14 @@ struct ora_state {
    * current (last) iteration */
   int strata_m;
   int64_t strata_npc;
+  /* adaptive allocation (beta > 0): counts and offsets of the current (last)
+   * iteration, the within-hypercube deviation sigma_h of the weight from the last
+   * stratified iteration (have_sig), and counts injected for the next iteration */
+  double strata_beta;
+  int64_t *scount, *soff;
+  double *ssig;
+  int have_sig, have_inject;
+  int64_t *sinject;
 };
 
 ora_state *ora_create(int process, int ndim, int nbins, uint64_t seed, double alpha,
@@ -785,8 +793,11 @@ ora_state *ora_create(int process, int ndim, int nbins, uint64_t seed, double al
   return s;
 }
 
+static void strata_free(ora_state *s);
+
 void ora_destroy(ora_state *s) {
   if (!s) return;
+  strata_free(s);
   free(s->edges);
   free(s->d);
   free(s->Ij);
@@ -823,8 +834,20 @@ int ora_grid_map(const ora_state *s, const double *u, double *x, double *jac, in
  * event i lies in h = floor(i / npc), whose coordinates are the base-m digits of h
  * (dimension 0 the least significant), and its uniforms r are placed inside it:
  * u_d = (c_d + r_d) / m. */
+/* hypercube of event i: floor(i / npc) with equal counts, else the one whose
+ * offset range holds i (binary search over the offsets) */
+static uint64_t strata_cube(const ora_state *s, uint64_t i) {
+  if (s->strata_beta <= 0.0) return i / (uint64_t)s->strata_npc;
+  int64_t lo = 0, hi = ora_strata_cubes(s) - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) / 2;
+    if ((uint64_t)s->soff[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return (uint64_t)lo;
+}
+
 static void strata_place(const ora_state *s, uint64_t i, double *u) {
-  uint64_t h = i / (uint64_t)s->strata_npc;
+  uint64_t h = strata_cube(s, i);
   for (int d = 0; d < s->ndim; ++d) {
     uint64_t c = h % (uint64_t)s->strata_m;
     h /= (uint64_t)s->strata_m;
@@ -838,6 +861,14 @@ static double event_weight_obs(const ora_state *s, uint32_t iter, uint64_t i, in
   if (s->strata_m > 0 && s->strata_npc > 0) strata_place(s, i, u);
   grid_map(s, u, x, &J, bins);
   double f = integrand_obs(s->process, s->ndim, s->params, x, obs);
+  if (s->strata_m > 0 && s->strata_npc > 0 && s->strata_beta > 0.0) {
+    /* unequal counts: each event stands for volume 1 / (H n_h) instead of 1 / N, so
+     * its weight is scaled by c_h = N / (H n_h); the estimate stays sum w / N */
+    int64_t H = ora_strata_cubes(s), h = (int64_t)strata_cube(s, i);
+    double N = (double)(s->soff[H - 1] + s->scount[H - 1]);
+    double c = N / ((double)H * (double)s->scount[h]);
+    return J * f * c;
+  }
   return J * f;
 }
 
@@ -879,6 +910,16 @@ int64_t ora_strata_cubes(const ora_state *s) {
   return H;
 }
 
+static void strata_free(ora_state *s) {
+  free(s->scount);
+  free(s->soff);
+  free(s->ssig);
+  free(s->sinject);
+  s->scount = s->soff = s->sinject = NULL;
+  s->ssig = NULL;
+  s->have_sig = s->have_inject = 0;
+}
+
 int ora_set_strata(ora_state *s, int m) {
   if (m < 0) return -1;
   int old = s->strata_m;
@@ -888,6 +929,93 @@ int ora_set_strata(ora_state *s, int m) {
     return -1;
   }
   s->strata_npc = 0;
+  strata_free(s);
+  return 0;
+}
+
+/* beta > 0: adaptive allocation (VEGAS+ reading): iteration j + 1 gives hypercube h
+ * n_h = 2 + floor((n - 2H) p_h / sum p) events with p_h = sigma_h^beta, sigma_h the
+ * standard deviation of the (unscaled) weight in h in iteration j, the remaining
+ * R = n - 2H - sum floor(...) events one each to hypercubes 0 .. R - 1 (equal counts
+ * before any stratified iteration, if every p_h is 0, or if R came out negative);
+ * beta = 0: equal counts floor(n / H), the rest of n unused. */
+int ora_set_strata_beta(ora_state *s, double beta) {
+  if (!(beta >= 0.0) || !isfinite(beta)) return -1;
+  s->strata_beta = beta;
+  s->have_sig = 0;
+  return 0;
+}
+
+/* counts of the last iteration's hypercubes (H of them) */
+int ora_get_strata_counts(const ora_state *s, int64_t *counts) {
+  int64_t H = ora_strata_cubes(s);
+  if (H <= 0 || s->strata_npc <= 0) return -2;
+  if (s->strata_beta <= 0.0 || !s->scount) {
+    for (int64_t h = 0; h < H; ++h) counts[h] = s->strata_npc;
+    return 0;
+  }
+  memcpy(counts, s->scount, sizeof(int64_t) * (size_t)H);
+  return 0;
+}
+
+/* counts the next (adaptive) iteration uses instead of its own allocation; they
+ * must sum to that iteration's n, each >= 2 */
+int ora_inject_strata_counts(ora_state *s, const int64_t *counts) {
+  int64_t H = ora_strata_cubes(s);
+  if (H <= 0 || s->strata_beta <= 0.0) return -1;
+  free(s->sinject);
+  s->sinject = (int64_t *)malloc(sizeof(int64_t) * (size_t)H);
+  memcpy(s->sinject, counts, sizeof(int64_t) * (size_t)H);
+  s->have_inject = 1;
+  return 0;
+}
+
+/* the allocation of an adaptive iteration of n events over H hypercubes */
+static int strata_allocate(ora_state *s, int64_t H, int64_t n) {
+  if (!s->scount) {
+    s->scount = (int64_t *)malloc(sizeof(int64_t) * (size_t)H);
+    s->soff = (int64_t *)malloc(sizeof(int64_t) * (size_t)H);
+    s->ssig = (double *)calloc((size_t)H, sizeof(double));
+  }
+  int64_t free_ev = n - 2 * H;
+  if (s->have_inject) {
+    int64_t tot = 0;
+    for (int64_t h = 0; h < H; ++h) {
+      if (s->sinject[h] < 2) return -1;
+      tot += s->sinject[h];
+    }
+    if (tot != n) return -1;
+    memcpy(s->scount, s->sinject, sizeof(int64_t) * (size_t)H);
+    s->have_inject = 0;
+  } else {
+    long double A = 0.0L;
+    for (int64_t h = 0; h < H; ++h) A += s->have_sig ? (long double)pow(s->ssig[h], s->strata_beta) : 1.0L;
+    double Ad = (double)A;
+    int64_t F = 0;
+    int equal = !(Ad > 0.0);
+    if (!equal) {
+      for (int64_t h = 0; h < H; ++h) {
+        double p = s->have_sig ? pow(s->ssig[h], s->strata_beta) : 1.0;
+        s->scount[h] = (int64_t)floor((double)free_ev * p / Ad);
+        F += s->scount[h];
+      }
+      if (F > free_ev) equal = 1;
+    }
+    if (equal) {
+      F = 0;
+      for (int64_t h = 0; h < H; ++h) {
+        s->scount[h] = free_ev / H;
+        F += s->scount[h];
+      }
+    }
+    int64_t R = free_ev - F;
+    for (int64_t h = 0; h < H; ++h) s->scount[h] += 2 + (h < R ? 1 : 0);
+  }
+  int64_t o = 0;
+  for (int64_t h = 0; h < H; ++h) {
+    s->soff[h] = o;
+    o += s->scount[h];
+  }
   return 0;
 }
 
@@ -901,6 +1029,10 @@ int ora_iterate(ora_state *s, int64_t n_req, double out[4]) {
     if (n_req / H < 2) return -1;
     s->strata_npc = n_req / H;
     n = H * s->strata_npc;
+    if (s->strata_beta > 0.0) {
+      n = n_req;
+      if (strata_allocate(s, H, n) != 0) return -1;
+    }
   }
   double *wrec = H > 0 ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
   int D = s->ndim, nb = s->nbins;
@@ -935,18 +1067,40 @@ int ora_iterate(ora_state *s, int64_t n_req, double out[4]) {
     /* stratified estimate: I = sum_h (1/H) mean_h = S1 / n (equal counts), and
      * var = sum_h (1/H)^2 sigma_h^2 / npc with the within-hypercube sample variance
      * sigma_h^2 = sum_{i in h} (w_i - mean_h)^2 / (npc - 1) */
-    int64_t c = s->strata_npc;
-    long double V = 0.0L;
-    for (int64_t h = 0; h < H; ++h) {
-      long double sh = 0.0L;
-      for (int64_t k = 0; k < c; ++k) sh += wrec[h * c + k];
-      long double mh = sh / (long double)c;
-      for (int64_t k = 0; k < c; ++k) {
-        long double dv = (long double)wrec[h * c + k] - mh;
-        V += dv * dv;
+    if (s->strata_beta <= 0.0) {
+      int64_t c = s->strata_npc;
+      long double V = 0.0L;
+      for (int64_t h = 0; h < H; ++h) {
+        long double sh = 0.0L;
+        for (int64_t k = 0; k < c; ++k) sh += wrec[h * c + k];
+        long double mh = sh / (long double)c;
+        for (int64_t k = 0; k < c; ++k) {
+          long double dv = (long double)wrec[h * c + k] - mh;
+          V += dv * dv;
+        }
       }
+      var = (double)(V / ((long double)H * (long double)H * (long double)c * (long double)(c - 1)));
+    } else {
+      /* unequal counts: with scaled weights w_s = c_h w, sum_h (1/H)^2 sigma_h^2(w) / n_h
+       * = sum_h n_h sigma_h^2(w_s) / N^2; sigma_h(w) = sigma_h(w_s) / c_h is kept for
+       * the next allocation */
+      long double V = 0.0L;
+      for (int64_t h = 0; h < H; ++h) {
+        int64_t c = s->scount[h], o = s->soff[h];
+        long double sh = 0.0L;
+        for (int64_t k = 0; k < c; ++k) sh += wrec[o + k];
+        long double mh = sh / (long double)c, q = 0.0L;
+        for (int64_t k = 0; k < c; ++k) {
+          long double dv = (long double)wrec[o + k] - mh;
+          q += dv * dv;
+        }
+        V += (long double)c * q / (long double)(c - 1);
+        long double ch = (long double)n / ((long double)H * (long double)c);
+        s->ssig[h] = (double)(sqrtl(q / (long double)(c - 1)) / ch);
+      }
+      var = (double)(V / ((long double)n * (long double)n));
+      s->have_sig = 1;
     }
-    var = (double)(V / ((long double)H * (long double)H * (long double)c * (long double)(c - 1)));
     free(wrec);
   }
   if (s->n_iter == s->cap) {

@@ -7,7 +7,10 @@ sum_h (1/H)^2 sigma_h^2 / n.  The pins: m = 1 is the plain iteration; the
 placement of each event in its hypercube (read back through the grid bins);
 the closed-form variance of the stratified estimator for a 1-D Gaussian on the
 uniform grid, matched both by the mean of the per-iteration variance estimates
-and by the spread of the estimates themselves; pulls over seeds.
+and by the spread of the estimates themselves; pulls over seeds.  Adaptive
+allocation (VEGAS+ reading, n_h following sigma_h^beta): the unequal-count
+variance against its closed form with an injected allocation, and beta = 1
+reaching Neyman's optimum allocation.
 """
 import math
 
@@ -123,3 +126,80 @@ def test_strata_refusals():
     assert v.iterate(1250)["n_events"] == 1250
     v.set_strata(0)
     assert v.iterate(1249)["n_events"] == 1249
+
+
+def stratum_moments_1d(mu, sg, m):
+    """Per stratum h of [0, 1] (width 1/m): Var_h(f) = m int_h f^2 - (m int_h f)^2 for
+    the normal density f (closed forms with erf)."""
+    out = []
+    s2 = sg / math.sqrt(2)
+    for h in range(m):
+        a, b = h / m, (h + 1) / m
+        i1 = phi((b - mu) / sg) - phi((a - mu) / sg)
+        i2 = (phi((b - mu) / s2) - phi((a - mu) / s2)) / (2 * sg * math.sqrt(math.pi))
+        out.append(m * i2 - (m * i1) ** 2)
+    return np.array(out)
+
+
+def test_unequal_counts_variance_matches_closed_form():
+    """Adaptive mode with a fixed, injected allocation n_h: the weights are scaled by
+    N / (H n_h), the estimate stays unbiased and the variance estimate matches
+    sum_h (1/m)^2 Var_h(f) / n_h, both on average and as the spread of the estimates."""
+    mu, sg, m, K = 0.4, 0.15, 8, 400
+    counts = np.array([3, 5, 9, 14, 12, 7, 4, 2], dtype=np.int64)
+    n = int(counts.sum())
+    v = oracle.Vegas(W.GAUSS, 1, 16, 13, 1.5, [mu, sg])
+    v.set_strata(m)
+    v.set_strata_beta(1.0)
+    Is, vs = [], []
+    for _ in range(K):
+        v.inject_strata_counts(counts)
+        r = v.iterate(n)
+        assert np.array_equal(v.strata_counts(), counts)
+        Is.append(r["I"])
+        vs.append(r["var"])
+    true = float(np.sum(stratum_moments_1d(mu, sg, m) / m ** 2 / counts))
+    assert abs(np.mean(vs) / true - 1) < 0.05, (np.mean(vs), true)
+    assert abs(np.var(Is, ddof=1) / true - 1) < 0.2, (np.var(Is, ddof=1), true)
+    exact = phi((1 - mu) / sg) - phi(-mu / sg)
+    assert abs(np.mean(Is) - exact) < 4 * math.sqrt(true / K)
+
+
+def test_adaptive_allocation_approaches_neyman():
+    """beta = 1 gives n_h proportional to sigma_h (Neyman's optimum
+    (sum_h sigma_h / m)^2 / n); the achieved variance beats equal counts and is
+    close to the optimum, and every allocation keeps sum n_h = n, n_h >= 2."""
+    mu, sg, m, n, K = 0.4, 0.1, 10, 400, 60
+    sig = np.sqrt(stratum_moments_1d(mu, sg, m))
+    neyman = float((sig / m).sum() ** 2 / n)
+    equal = float(np.sum(sig ** 2 / m ** 2 / (n // m)))
+    v = oracle.Vegas(W.GAUSS, 1, 20, 17, 1.5, [mu, sg])
+    v.set_strata(m)
+    v.set_strata_beta(1.0)
+    vs = []
+    for it in range(K):
+        r = v.iterate(n)
+        c = v.strata_counts()
+        assert c.sum() == n and c.min() >= 2
+        if it >= 2:
+            vs.append(r["var"])
+    got = np.mean(vs)
+    assert got < 0.6 * equal, (got, equal)          # here Neyman is 0.51 x equal counts
+    assert got < 1.1 * neyman, (got, neyman)        # measured 1.015 x
+
+
+def test_adaptive_first_iteration_and_counts_invariants():
+    c = W.config("gauss4")
+    v = oracle.Vegas(c["process"], 4, 30, 7, 1.5, c["params"])
+    v.set_strata(4)
+    v.set_strata_beta(0.75)
+    r = v.iterate(20_003)                      # first: equal counts, remainder to the first cubes
+    cnt = v.strata_counts()
+    assert r["n_events"] == 20_003 and cnt.sum() == 20_003
+    q, R = divmod(20_003 - 2 * 256, 256)
+    assert np.array_equal(cnt, 2 + q + (np.arange(256) < R))
+    v.iterate(20_003)
+    cnt = v.strata_counts()
+    assert cnt.sum() == 20_003 and cnt.min() >= 2 and cnt.max() > cnt.min()
+    with pytest.raises(ValueError):
+        v.set_strata_beta(-1.0)
