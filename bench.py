@@ -485,16 +485,17 @@ def observable_leg(args, make, Wn, N, plain_ms_min, plain_event):
             "fold_cols": shape["fold_cols"]}
 
 
-def strata_leg(args, make, Wn, N, D, plain_ms_min, plain_hist):
-    """The same steps with stratified sampling (Lepage's stratified + importance mode,
-    m strata per axis): ms per step (min over 10 blocks of K steps), and the timed
-    iterations' combined relative error against the plain path's over the same
-    iteration numbers, as effective events/s 1 / (eps^2 T)."""
+def strata_run(args, make, Wn, N, m, beta, plain_ms_min, plain_hist):
+    """The same steps with stratified sampling (m strata per axis; beta > 0: adaptive
+    counts): ms per step (min over 10 blocks of K steps), and the timed iterations'
+    combined relative error against the plain path's over the same iteration
+    numbers, as effective events/s 1 / (eps^2 T)."""
     import torch
-    m = args.strata if args.strata > 0 else int((N / 2) ** (1.0 / D) + 1e-9)
-    H = m ** D
     g = make()
     g.set_strata(m)
+    if beta > 0:
+        g.set_strata_beta(beta)
+    H = m ** g.ndim
     for _ in range(Wn):
         g.iterate(N, sync=False)
         g.refine()
@@ -522,17 +523,30 @@ def strata_leg(args, make, Wn, N, D, plain_ms_min, plain_hist):
         g.refine()
     torch.cuda.synchronize()
     st = g.stage_times()
+    counts = g.strata_counts()
     g.close()
     I, sig = combine(hist)
     Ip, sigp = combine(plain_hist)
-    used = H * (N // H)
-    eff = 1.0 / ((sig / abs(I)) ** 2 * T) if sig > 0 else None
-    return {"strata_per_axis": m, "hypercubes": H, "events_per_hypercube": N // H, "events_used": used,
+    return {"strata_per_axis": m, "beta": beta, "hypercubes": H,
+            "events_per_hypercube": {"min": int(counts.min()), "max": int(counts.max()),
+                                     "mean": float(counts.mean())},
+            "events_used": int(counts.sum()),
             "ms_per_step_min": min(reps), "ms_per_step_min_plain": plain_ms_min,
             "step_overhead": min(reps) / plain_ms_min - 1.0,
             "rel_error": sig / abs(I), "rel_error_plain": sigp / abs(Ip),
-            "effective_events_per_s": eff,
+            "effective_events_per_s": 1.0 / ((sig / abs(I)) ** 2 * T) if sig > 0 else None,
             "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()}}
+
+
+def strata_leg(args, make, Wn, N, D, plain_ms_min, plain_hist):
+    """Lepage's stratified + importance mode with his m = floor((N/2)^(1/D)) (two
+    events per hypercube), and the adaptive allocation with beta = 0.75 over
+    m = floor((N/8)^(1/D)) strata per axis (about eight events per hypercube, room
+    for the counts to follow sigma_h)."""
+    m = args.strata if args.strata > 0 else int((N / 2) ** (1.0 / D) + 1e-9)
+    ma = args.strata if args.strata > 0 else int((N / 8) ** (1.0 / D) + 1e-9)
+    return {"classic": strata_run(args, make, Wn, N, m, 0.0, plain_ms_min, plain_hist),
+            "adaptive": strata_run(args, make, Wn, N, ma, 0.75, plain_ms_min, plain_hist)}
 
 
 def main():

@@ -188,6 +188,27 @@ int vegas_result_from(vegas_handle h, int32_t first, double *integral, double *e
  * or m^ndim above 2^31 - 1). */
 int vegas_set_strata(vegas_handle h, int32_t strata_per_axis);
 
+/* Adaptive allocation over the hypercubes (a reading of Lepage's VEGAS+ adaptive
+ * stratification): beta > 0 gives each hypercube of an iteration of n events
+ * n_h = 2 + floor((n - 2H) p_h / sum p) events, p_h = sigma_h^beta with sigma_h the
+ * standard deviation of the weight in h in the last stratified iteration (beta = 1:
+ * Neyman's allocation n_h ~ sigma_h), and the remaining R events one each to
+ * hypercubes 0 .. R - 1, so all n events are used (n >= 2H required); equal counts
+ * before any stratified iteration, after vegas_set_strata / vegas_set_state, if
+ * every p_h is 0, or if rounding made the floors exceed n - 2H.  Each weight is then
+ * scaled by N / (H n_h), the volume its event stands for, so the estimate stays the
+ * mean and var_j = sum_h n_h sigma_h^2(scaled) / N^2.  The sums are exact as for
+ * equal counts; the allocation's own sum of p_h is a fixed-order binary64 sum.
+ * beta = 0 (the default) is the equal-count mode of vegas_set_strata.  The
+ * allocation scratch (about 16 bytes per hypercube and 4 per event) is allocated by
+ * the library on first use.  Errors: VEGAS_EINVAL (beta < 0 or not finite). */
+int vegas_set_strata_beta(vegas_handle h, double beta);
+
+/* Events per hypercube of the last stratified iteration, host int32 [m^ndim].
+ * Waits for the stream.  Errors: VEGAS_ESTATE (no stratified iteration since
+ * vegas_set_strata / vegas_set_state). */
+int vegas_get_strata_counts(vegas_handle h, int32_t *counts);
+
 /* Histogram of the process's observable, filled by the same events and weights
  * as the integral (Sec. 2.1: the integrator returns cross sections and
  * distributions of kinematic variables; Sec. 3.2 shows such distributions, the

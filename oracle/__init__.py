@@ -89,6 +89,7 @@ def lib():
         L.ora_set_strata_beta.argtypes = [C.c_void_p, C.c_double]
         L.ora_get_strata_counts.argtypes = [C.c_void_p, _i64p]
         L.ora_inject_strata_counts.argtypes = [C.c_void_p, _i64p]
+        L.ora_strata_next_counts.argtypes = [C.c_void_p, C.c_int64, _i64p]
         L.ora_event_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_int64, C.c_int64, _dp, _u8p]
         L.ora_grid_map.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_double),
                                    np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")]
@@ -232,6 +233,13 @@ class Vegas:
         c = np.zeros(max(H, 0), dtype=np.int64)
         if lib().ora_get_strata_counts(self._h, c) != 0:
             raise RuntimeError("no stratified iteration yet")
+        return c
+
+    def strata_next_counts(self, n):
+        H = lib().ora_strata_cubes(self._h)
+        c = np.zeros(max(H, 0), dtype=np.int64)
+        if lib().ora_strata_next_counts(self._h, n, c) != 0:
+            raise ValueError("needs adaptive strata and n >= 2H")
         return c
 
     def inject_strata_counts(self, counts):

@@ -970,6 +970,42 @@ int ora_inject_strata_counts(ora_state *s, const int64_t *counts) {
   return 0;
 }
 
+/* the counts the allocation rule gives for n events over H hypercubes */
+static void strata_rule(const ora_state *s, int64_t H, int64_t n, int64_t *cnt) {
+  int64_t free_ev = n - 2 * H;
+  int have = s->have_sig && s->ssig;
+  long double A = 0.0L;
+  for (int64_t h = 0; h < H; ++h) A += have ? (long double)pow(s->ssig[h], s->strata_beta) : 1.0L;
+  double Ad = (double)A;
+  int64_t F = 0;
+  int equal = !(Ad > 0.0);
+  if (!equal) {
+    for (int64_t h = 0; h < H; ++h) {
+      double p = have ? pow(s->ssig[h], s->strata_beta) : 1.0;
+      cnt[h] = (int64_t)floor((double)free_ev * p / Ad);
+      F += cnt[h];
+    }
+    if (F > free_ev) equal = 1;
+  }
+  if (equal) {
+    F = 0;
+    for (int64_t h = 0; h < H; ++h) {
+      cnt[h] = free_ev / H;
+      F += cnt[h];
+    }
+  }
+  int64_t R = free_ev - F;
+  for (int64_t h = 0; h < H; ++h) cnt[h] += 2 + (h < R ? 1 : 0);
+}
+
+/* the counts the next adaptive iteration of n events would use (no state change) */
+int ora_strata_next_counts(const ora_state *s, int64_t n, int64_t *counts) {
+  int64_t H = ora_strata_cubes(s);
+  if (H <= 0 || s->strata_beta <= 0.0 || n < 2 * H) return -1;
+  strata_rule(s, H, n, counts);
+  return 0;
+}
+
 /* the allocation of an adaptive iteration of n events over H hypercubes */
 static int strata_allocate(ora_state *s, int64_t H, int64_t n) {
   if (!s->scount) {
@@ -977,7 +1013,6 @@ static int strata_allocate(ora_state *s, int64_t H, int64_t n) {
     s->soff = (int64_t *)malloc(sizeof(int64_t) * (size_t)H);
     s->ssig = (double *)calloc((size_t)H, sizeof(double));
   }
-  int64_t free_ev = n - 2 * H;
   if (s->have_inject) {
     int64_t tot = 0;
     for (int64_t h = 0; h < H; ++h) {
@@ -988,28 +1023,7 @@ static int strata_allocate(ora_state *s, int64_t H, int64_t n) {
     memcpy(s->scount, s->sinject, sizeof(int64_t) * (size_t)H);
     s->have_inject = 0;
   } else {
-    long double A = 0.0L;
-    for (int64_t h = 0; h < H; ++h) A += s->have_sig ? (long double)pow(s->ssig[h], s->strata_beta) : 1.0L;
-    double Ad = (double)A;
-    int64_t F = 0;
-    int equal = !(Ad > 0.0);
-    if (!equal) {
-      for (int64_t h = 0; h < H; ++h) {
-        double p = s->have_sig ? pow(s->ssig[h], s->strata_beta) : 1.0;
-        s->scount[h] = (int64_t)floor((double)free_ev * p / Ad);
-        F += s->scount[h];
-      }
-      if (F > free_ev) equal = 1;
-    }
-    if (equal) {
-      F = 0;
-      for (int64_t h = 0; h < H; ++h) {
-        s->scount[h] = free_ev / H;
-        F += s->scount[h];
-      }
-    }
-    int64_t R = free_ev - F;
-    for (int64_t h = 0; h < H; ++h) s->scount[h] += 2 + (h < R ? 1 : 0);
+    strata_rule(s, H, n, s->scount);
   }
   int64_t o = 0;
   for (int64_t h = 0; h < H; ++h) {

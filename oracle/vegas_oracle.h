@@ -110,6 +110,7 @@ int64_t ora_strata_npc(const ora_state *s);
 int ora_set_strata_beta(ora_state *s, double beta);
 int ora_get_strata_counts(const ora_state *s, int64_t *counts);
 int ora_inject_strata_counts(ora_state *s, const int64_t *counts);
+int ora_strata_next_counts(const ora_state *s, int64_t n, int64_t *counts);
 /* weights (and bin indices, [n][ndim]) of events [first, first+n) of iteration iter at the current grid */
 int ora_event_weights(const ora_state *s, uint32_t iter, int64_t first, int64_t n,
                       double *w, uint8_t *bins);

@@ -233,6 +233,11 @@ struct EventArgs {
   int strata_m, strata_npc;  // STRAT kernels: strata per axis, events per hypercube
   double strata_md;          // strata_m as binary64
   UDiv div_m, div_npc;       // division by strata_m and by strata_npc
+  // adaptive allocation (STRAT kernels, s_cube non-null): the hypercube of each event
+  // and the counts; each weight is scaled by N / (H n_h)
+  const int32_t* s_cube;
+  const int32_t* s_cnt;
+  double s_N, s_Hd;
 };
 
 // ---------------------------------------------------------------------------
@@ -306,7 +311,7 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     } else {
       event_uniforms<D>(a.seed, a.iter, static_cast<uint64_t>(i), nd, u);
       if constexpr (STRAT) {
-        uint32_t hc = udiv(static_cast<uint32_t>(i), a.div_npc);
+        uint32_t hc = a.s_cube ? static_cast<uint32_t>(a.s_cube[i]) : udiv(static_cast<uint32_t>(i), a.div_npc);
         const uint32_t m = static_cast<uint32_t>(a.strata_m);
 #pragma unroll
         for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
@@ -338,6 +343,8 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     double q;
     const double f = integrand<PROC, PREC, D>(a.pc, x, q);
     double w = J * f;
+    if constexpr (STRAT && !EXT)
+      if (a.s_cube) w *= a.s_N / (a.s_Hd * static_cast<double>(a.s_cnt[a.s_cube[i]]));
     int obin = 0;
     if constexpr (OBS) {
       obin = obs_bin(obs_is_square<PROC>() ? sqrt(q) : q, a.obs_lo, a.obs_hi, a.obs_scale, a.nobs);
@@ -432,19 +439,35 @@ __device__ __forceinline__ int strata_exponent(double wmax, int npc) {
   return fx_exponent(wmax * wmax * static_cast<double>(npc));
 }
 
-__global__ void k_strata(DevBufs b, int64_t H, int npc) {
-  const int EV = strata_exponent(__longlong_as_double(static_cast<long long>(b.maxw[0])), npc);
+// adaptive allocation (cnt non-null): hypercube h holds records off[h] .. off[h] +
+// cnt[h] - 1 of the scaled weights w_s = c_h w, c_h = N / (H n_h); the folded term
+// is n_h sum (w_s - mean)^2 / (n_h - 1) (var_j = V / N^2, bounded by 2 N max w_s^2),
+// and sigma_h of the unscaled weight is kept in sig for the next allocation
+__device__ __forceinline__ int strata_exponent_adapt(double wmax, double N) {
+  return fx_exponent(2.0 * N * wmax * wmax);
+}
+
+__global__ void k_strata(DevBufs b, int64_t H, int npc, const int32_t* cnt, const int32_t* off, double* sig,
+                         double N) {
+  const double wmx = __longlong_as_double(static_cast<long long>(b.maxw[0]));
+  const int EV = cnt ? strata_exponent_adapt(wmx, N) : strata_exponent(wmx, npc);
   long long s0 = 0, s1 = 0, s2 = 0;
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
-    const double* w = b.rec_w + h * npc;
+    const int c = cnt ? cnt[h] : npc;
+    const double* w = b.rec_w + (cnt ? static_cast<int64_t>(off[h]) : h * npc);
     double sum = 0.0;
-    for (int k = 0; k < npc; ++k) sum += w[k];
-    const double mh = sum / static_cast<double>(npc);
+    for (int k = 0; k < c; ++k) sum += w[k];
+    const double mh = sum / static_cast<double>(c);
     double V = 0.0;
-    for (int k = 0; k < npc; ++k) {
+    for (int k = 0; k < c; ++k) {
       const double dv = w[k] - mh;
       V = __fma_rn(dv, dv, V);
+    }
+    if (cnt) {
+      const double ch = N / (static_cast<double>(H) * static_cast<double>(c));
+      sig[h] = sqrt(V / static_cast<double>(c - 1)) / ch;
+      V = static_cast<double>(c) * V / static_cast<double>(c - 1);
     }
     long long d0, d1, d2;
     fx_digits_pos(V, EV, d0, d1, d2);
@@ -466,6 +489,137 @@ __global__ void k_strata(DevBufs b, int64_t H, int npc) {
   }
   __syncthreads();
   if (threadIdx.x < 3) b.strat_part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// adaptive allocation over G blocks of kAllocThreads, block b owning the contiguous
+// hypercubes [b C, (b + 1) C) (G and C depend on H only, so every sum below has a
+// fixed order): p_h = sigma_h^beta (1 before any stratified iteration), n_h = 2 +
+// floor((n - 2H) p_h / sum p) with the remaining R events one each to hypercubes
+// 0 .. R - 1 (equal counts if sum p is not positive or the floors overshoot), and
+// the exclusive prefix sum of the counts as offsets
+// ---------------------------------------------------------------------------
+constexpr int kAllocThreads = 256;
+constexpr int kAllocBlocksMax = 1024;
+
+__device__ double block_sum_fixed(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kAllocThreads / 2; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ long long block_sum_int(long long v, long long* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kAllocThreads / 2; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const long long r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// sum of p over all blocks' partials, in the same order in every block
+__device__ double alloc_total(const double* part, int G, double* red) {
+  double a = 0.0;
+  for (int k = threadIdx.x; k < G; k += kAllocThreads) a += part[k];
+  return block_sum_fixed(a, red);
+}
+
+__global__ __launch_bounds__(kAllocThreads) void k_strata_alloc_p(const double* sig, double* p, double* part,
+                                                                   int64_t H, int64_t C, double beta, int have_sig) {
+  __shared__ double red[kAllocThreads];
+  const int64_t h0 = static_cast<int64_t>(blockIdx.x) * C, h1 = min(H, h0 + C);
+  double acc = 0.0;
+  for (int64_t h = h0 + threadIdx.x; h < h1; h += kAllocThreads) {
+    const double v = have_sig ? pow(sig[h], beta) : 1.0;
+    p[h] = v;
+    acc += v;
+  }
+  const double tot = block_sum_fixed(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kAllocThreads) void k_strata_alloc_f(const double* p, int32_t* cnt, const double* part,
+                                                                   long long* partf, int64_t H, int64_t C, int G,
+                                                                   int64_t freev) {
+  __shared__ double red[kAllocThreads];
+  __shared__ long long lred[kAllocThreads];
+  const double A = alloc_total(part, G, red);
+  const int64_t h0 = static_cast<int64_t>(blockIdx.x) * C, h1 = min(H, h0 + C);
+  long long loc = 0;
+  if (A > 0.0)
+    for (int64_t h = h0 + threadIdx.x; h < h1; h += kAllocThreads) {
+      const int32_t f = static_cast<int32_t>(floor(static_cast<double>(freev) * p[h] / A));
+      cnt[h] = f;
+      loc += f;
+    }
+  const long long tot = block_sum_int(loc, lred);
+  if (threadIdx.x == 0) partf[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kAllocThreads) void k_strata_alloc_c(int32_t* cnt, int32_t* off, const double* part,
+                                                                   const long long* partf, int64_t H, int64_t C,
+                                                                   int G, int64_t freev) {
+  __shared__ double red[kAllocThreads];
+  __shared__ long long lred[kAllocThreads];
+  const double A = alloc_total(part, G, red);
+  long long F = 0;
+  for (int k = threadIdx.x; k < G; k += kAllocThreads) F += partf[k];
+  F = block_sum_int(F, lred);
+  const bool equal = !(A > 0.0) || F > freev;
+  const long long q = freev / H;
+  const long long R = freev - (equal ? q * H : F);
+  // events before this block: 2 per hypercube, the floors, and the remainder's ones
+  long long start = 0;
+  for (int k = threadIdx.x; k < static_cast<int>(blockIdx.x); k += kAllocThreads) {
+    const int64_t a0 = static_cast<int64_t>(k) * C, a1 = min(H, a0 + C);
+    start += 2 * (a1 - a0) + (equal ? q * (a1 - a0) : partf[k]) + max<int64_t>(0, min<int64_t>(a1, R) - a0);
+  }
+  start = block_sum_int(start, lred);
+  // final counts and offsets of this block's hypercubes: contiguous sub-chunks per
+  // thread, their sums scanned in thread order
+  const int64_t h0 = static_cast<int64_t>(blockIdx.x) * C, h1 = min(H, h0 + C);
+  const int64_t sub = (h1 - h0 + kAllocThreads - 1) / kAllocThreads;
+  const int64_t s0 = min(h1, h0 + static_cast<int64_t>(threadIdx.x) * sub), s1 = min(h1, s0 + sub);
+  long long loc = 0;
+  for (int64_t h = s0; h < s1; ++h) {
+    const int32_t c = static_cast<int32_t>(2 + (equal ? q : cnt[h]) + (h < R ? 1 : 0));
+    cnt[h] = c;
+    loc += c;
+  }
+  lred[threadIdx.x] = loc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long run = start;
+    for (int k = 0; k < kAllocThreads; ++k) {
+      const long long v = lred[k];
+      lred[k] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  long long o = lred[threadIdx.x];
+  for (int64_t h = s0; h < s1; ++h) {
+    off[h] = static_cast<int32_t>(o);
+    o += cnt[h];
+  }
+}
+
+// the hypercube index of every event: cube[off[h] .. off[h] + cnt[h] - 1] = h
+__global__ void k_strata_expand(const int32_t* cnt, const int32_t* off, int32_t* cube, int64_t H) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
+    const int32_t o = off[h];
+    for (int k = 0; k < cnt[h]; ++k) cube[o + k] = static_cast<int32_t>(h);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -549,6 +703,7 @@ struct FinArgs {
   int64_t strata_H;  // > 0: stratified, var_j from the hypercubes' V
   int strata_npc;
   int strata_blocks;  // rows of the hypercube fold's partials
+  int strata_adapt;   // unequal counts: var_j = V / N^2
   double alpha;
 };
 
@@ -563,6 +718,7 @@ __device__ __forceinline__ double iteration_variance(const FinArgs& f, double S1
     long long t[3] = {0, 0, 0};
     for (int w = 0; w < static_cast<int>(blockDim.x) / kWave; ++w)
       for (int k = 0; k < 3; ++k) t[k] += sv[w][k];
+    if (f.strata_adapt) return fx_value(t[0], t[1], t[2], strata_exponent_adapt(wmax, N)) / (N * N);
     const double V = fx_value(t[0], t[1], t[2], strata_exponent(wmax, f.strata_npc));
     const double H = static_cast<double>(f.strata_H), c = static_cast<double>(f.strata_npc);
     return V / (H * H * c * (c - 1.0));
@@ -1204,6 +1360,19 @@ struct vegas_state {
   double obs_lo, obs_hi;
   bool obs_have;                // an iteration ran since the observable was set
   int strata_m;                 // stratified sampling: strata per axis (0 = off)
+  double strata_beta;           // > 0: adaptive allocation n_h ~ sigma_h^beta
+  // adaptive allocation scratch (library-allocated on first use): sigma_h, p_h, counts
+  // and offsets per hypercube (capacity s_capH), per-block partial sums, the
+  // hypercube of each event [maxN]
+  double* s_sig;
+  double* s_p;
+  double* s_part;
+  long long* s_partf;
+  int32_t *s_cnt, *s_off, *s_cube;
+  int64_t s_capH;
+  bool s_have_sig;              // s_sig holds the last stratified iteration's sigma_h
+  int64_t last_strata_npc;      // last iteration: events per hypercube (equal counts), -1 adaptive,
+                                //   0 not stratified
   size_t smem_max;              // LDS per block the launches may use
   int refine_lds;               // LDS of the refinement scratch: D * 4 (n + 1) doubles
   bool scale_valid;             // the device holds scales from a previous iteration (b.fxs)
@@ -1556,6 +1725,13 @@ int vegas_destroy(vegas_handle h) {
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->gbuf) (void)hipFree(h->gbuf);
+  if (h->s_sig) (void)hipFree(h->s_sig);
+  if (h->s_cnt) (void)hipFree(h->s_cnt);
+  if (h->s_off) (void)hipFree(h->s_off);
+  if (h->s_cube) (void)hipFree(h->s_cube);
+  if (h->s_p) (void)hipFree(h->s_p);
+  if (h->s_part) (void)hipFree(h->s_part);
+  if (h->s_partf) (void)hipFree(h->s_partf);
   if (h->owns) {
     if (hipStreamSynchronize(h->stream) != hipSuccess) rc = VEGAS_EHIP;
     if (hipFree(h->base) != hipSuccess) rc = VEGAS_EHIP;
@@ -1635,7 +1811,45 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
   const int64_t H = ext_y ? 0 : strata_cubes(h);
   const int64_t npc = H > 0 ? n_req / H : 0;
   if (H < 0 || (H > 0 && npc < 2)) return VEGAS_EINVAL;
-  const int64_t n_events = H > 0 ? H * npc : n_req;
+  // adaptive: every requested event is used, n_h from the last iteration's sigma_h
+  const bool adapt = H > 0 && h->strata_beta > 0.0;
+  const int64_t n_events = H > 0 && !adapt ? H * npc : n_req;
+  if (adapt) {
+    if (h->s_capH < H) {  // scratch for the allocation (first use, or more hypercubes)
+      VG_HIP(hipStreamSynchronize(h->stream));
+      if (h->s_sig) VG_HIP(hipFree(h->s_sig));
+      if (h->s_p) VG_HIP(hipFree(h->s_p));
+      if (h->s_cnt) VG_HIP(hipFree(h->s_cnt));
+      if (h->s_off) VG_HIP(hipFree(h->s_off));
+      h->s_sig = h->s_p = nullptr;
+      h->s_cnt = h->s_off = nullptr;
+      h->s_capH = 0;
+      VG_HIP(hipMalloc(&h->s_sig, sizeof(double) * H));
+      VG_HIP(hipMalloc(&h->s_p, sizeof(double) * H));
+      VG_HIP(hipMalloc(&h->s_cnt, sizeof(int32_t) * H));
+      VG_HIP(hipMalloc(&h->s_off, sizeof(int32_t) * H));
+      h->s_capH = H;
+      h->s_have_sig = false;
+    }
+    if (!h->s_cube) VG_HIP(hipMalloc(&h->s_cube, sizeof(int32_t) * h->maxN));
+    if (!h->s_part) VG_HIP(hipMalloc(&h->s_part, sizeof(double) * kAllocBlocksMax));
+    if (!h->s_partf) VG_HIP(hipMalloc(&h->s_partf, sizeof(long long) * kAllocBlocksMax));
+    // G blocks of C hypercubes each (from H alone: the sums' order is fixed)
+    const int G = static_cast<int>(std::min<int64_t>((H + 1023) / 1024, kAllocBlocksMax));
+    const int64_t C = (H + G - 1) / G;
+    const int64_t freev = n_events - 2 * H;
+    hipLaunchKernelGGL(k_strata_alloc_p, dim3(G), dim3(kAllocThreads), 0, h->stream, h->s_sig, h->s_p, h->s_part, H,
+                       C, h->strata_beta, h->s_have_sig ? 1 : 0);
+    hipLaunchKernelGGL(k_strata_alloc_f, dim3(G), dim3(kAllocThreads), 0, h->stream, h->s_p, h->s_cnt, h->s_part,
+                       h->s_partf, H, C, G, freev);
+    hipLaunchKernelGGL(k_strata_alloc_c, dim3(G), dim3(kAllocThreads), 0, h->stream, h->s_cnt, h->s_off, h->s_part,
+                       h->s_partf, H, C, G, freev);
+    VG_HIP(hipGetLastError());
+    const int64_t xb = std::min<int64_t>((H + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_strata_expand, dim3(static_cast<unsigned>(xb)), dim3(256), 0, h->stream, h->s_cnt,
+                       h->s_off, h->s_cube, H);
+    VG_HIP(hipGetLastError());
+  }
   const int threads = ext_y ? 256 : pick_threads(h);
   const int nslot = h->D * h->n;
   EventArgs ea;
@@ -1658,6 +1872,10 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
   ea.strata_md = static_cast<double>(h->strata_m);
   ea.div_m = udiv_magic(static_cast<uint32_t>(h->strata_m > 0 ? h->strata_m : 1));
   ea.div_npc = udiv_magic(static_cast<uint32_t>(npc > 0 ? npc : 1));
+  ea.s_cube = adapt ? h->s_cube : nullptr;
+  ea.s_cnt = adapt ? h->s_cnt : nullptr;
+  ea.s_N = static_cast<double>(n_events);
+  ea.s_Hd = static_cast<double>(H);
   // fused fold (digits added by the event kernel at the previous iteration's scales)
   // whenever such scales exist and the digits fit in LDS; the choice depends on
   // the history and the configuration only, never on the launch shape
@@ -1695,8 +1913,10 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
   if (H > 0) {
     TimedLaunch t(h, 1);
     hipExtLaunchKernelGGL(k_strata, dim3(strata_blocks), dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, H,
-                          static_cast<int>(npc));
+                          static_cast<int>(npc), adapt ? h->s_cnt : nullptr, adapt ? h->s_off : nullptr,
+                          adapt ? h->s_sig : nullptr, static_cast<double>(n_events));
     VG_HIP(t.done());
+    if (adapt) h->s_have_sig = true;
   }
   h->last_launch[0] = ev_blocks;
   h->last_launch[1] = threads;
@@ -1719,6 +1939,7 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
     fa.strata_H = H;
     fa.strata_npc = static_cast<int>(npc);
     fa.strata_blocks = strata_blocks;
+    fa.strata_adapt = adapt ? 1 : 0;
     fa.alpha = h->cfg.alpha;
     const int lds = fa.obs_lds + (h->nobs ? static_cast<int>(sizeof(double) * 2 * (h->nobs + 2)) : 0);
     TimedLaunch t(h, 2);
@@ -1738,6 +1959,7 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
   h->last_flow = ext_y != nullptr;
   h->any_iter = true;
   h->obs_have = h->nobs > 0;
+  h->last_strata_npc = H > 0 ? (adapt ? -1 : npc) : 0;
   h->last_n = n_events;
   if (out) {
     double o[6];
@@ -1853,7 +2075,29 @@ int vegas_set_strata(vegas_handle h, int32_t strata_per_axis) {
     h->strata_m = old;
     return VEGAS_EINVAL;
   }
+  h->s_have_sig = false;
+  h->last_strata_npc = 0;
   configure_lds(h);  // occupancy of the stratified event kernels
+  return VEGAS_OK;
+}
+
+int vegas_set_strata_beta(vegas_handle h, double beta) {
+  if (!h || !(beta >= 0.0) || !std::isfinite(beta)) return VEGAS_EINVAL;
+  h->strata_beta = beta;
+  h->s_have_sig = false;
+  return VEGAS_OK;
+}
+
+int vegas_get_strata_counts(vegas_handle h, int32_t* counts) {
+  if (!h || !counts) return VEGAS_EINVAL;
+  const int64_t H = strata_cubes(h);
+  if (H <= 0 || h->last_strata_npc == 0) return VEGAS_ESTATE;
+  if (h->last_strata_npc > 0) {  // equal counts
+    for (int64_t k = 0; k < H; ++k) counts[k] = static_cast<int32_t>(h->last_strata_npc);
+    return VEGAS_OK;
+  }
+  VG_HIP(hipMemcpyAsync(counts, h->s_cnt, sizeof(int32_t) * H, hipMemcpyDeviceToHost, h->stream));
+  VG_HIP(hipStreamSynchronize(h->stream));
   return VEGAS_OK;
 }
 
@@ -2062,6 +2306,8 @@ int vegas_set_state(vegas_handle h, const void* buf, size_t bytes) {
     VG_HIP(hipGetLastError());
   }
   h->obs_have = false;
+  h->s_have_sig = false;  // the adaptive allocation restarts from equal counts
+  h->last_strata_npc = 0;
   h->iter = hd.iter;
   h->any_iter = hd.iter > 0;
   h->have_hist = false;

@@ -24,6 +24,7 @@ MAX_OBS_BINS = 254
 
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
            "vegas_result_from", "vegas_set_observable", "vegas_get_observable", "vegas_set_strata",
+           "vegas_set_strata_beta", "vegas_get_strata_counts",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
            "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_last_launch",
@@ -72,6 +73,8 @@ def load(path: str = LIB_PATH):
     L.vegas_result_from.argtypes = [vp, i32, dp, dp, dp, C.POINTER(i32)]
     L.vegas_set_observable.argtypes = [vp, i32, C.c_double, C.c_double, i32]
     L.vegas_set_strata.argtypes = [vp, i32]
+    L.vegas_set_strata_beta.argtypes = [vp, C.c_double]
+    L.vegas_get_strata_counts.argtypes = [vp, vp]
     L.vegas_get_observable.argtypes = [vp, vp, vp, vp, vp]
     L.vegas_get_grid.argtypes = [vp, vp]
     L.vegas_set_grid.argtypes = [vp, vp]
@@ -203,6 +206,17 @@ class Integrator:
     def set_strata(self, m):
         """m strata per axis (0: off): iterations then use m^ndim floor(n / m^ndim) events."""
         _check(self._L.vegas_set_strata(self._h, m), "vegas_set_strata")
+        self._strata_H = m ** self.ndim if m > 0 else 0
+
+    def set_strata_beta(self, beta):
+        """beta > 0: adaptive allocation n_h ~ sigma_h^beta over the hypercubes."""
+        _check(self._L.vegas_set_strata_beta(self._h, beta), "vegas_set_strata_beta")
+
+    def strata_counts(self):
+        self._strata_H = getattr(self, "_strata_H", 0)
+        c = np.zeros(self._strata_H, dtype=np.int32)
+        _check(self._L.vegas_get_strata_counts(self._h, c.ctypes.data), "vegas_get_strata_counts")
+        return c
 
     def set_observable(self, nbins, lo=0.0, hi=1.0, first=0):
         """Histogram the process's observable in nbins uniform bins on [lo, hi)

@@ -215,3 +215,80 @@ def test_stratified_checkpoint_resume_is_bit_identical(P):
         b.refine()
     assert a.result() == b.result()
     assert np.array_equal(a.get_grid(), b.get_grid())
+
+
+ADAPT = [("gauss4", W.config("gauss4"), 4, 6007), ("w_plus", W.config("w_plus"), 5, 6007),
+         ("ww_4l", W.config("ww_4l"), 2, 4099)]
+
+
+@pytest.mark.parametrize("name,cfg,m,n", ADAPT, ids=[c[0] for c in ADAPT])
+def test_adaptive_strata_match_oracle(P, name, cfg, m, n):
+    """beta = 1: each iteration the GPU's counts agree with the oracle's own rule
+    (from the oracle's sigma_h of the same events; a count may differ by one where
+    binary64 rounding puts (n - 2H) p_h / sum p at an integer), then, with those
+    counts injected into the oracle and the grid injected, the scaled weights,
+    the integral and the variance agree to the usual bars."""
+    g, o = pair(P, cfg, n, m)
+    g.set_strata_beta(1.0)
+    o.set_strata_beta(1.0)
+    for it in range(4):
+        o.set_grid(g.get_grid())
+        o.iteration = it
+        pred = o.strata_next_counts(n)
+        rg = g.iterate(n)
+        cg = g.strata_counts().astype(np.int64)
+        assert cg.sum() == n and cg.min() >= 2 and rg["n_events"] == n
+        diff = np.abs(cg - pred)
+        assert diff.max() <= 1 and np.mean(diff > 0) <= 1e-3, (name, it, diff.max(), np.mean(diff > 0))
+        o.inject_strata_counts(cg)
+        ro = o.iterate(n)
+        wg, bg = g.get_weights(0, n)
+        wo, bo = o.event_weights(it, 0, n)
+        assert np.array_equal(bg, bo)
+        assert np.all(np.abs(wg - wo) <= 1e-12 * np.abs(wo) + 1e-14 * np.mean(np.abs(wo))), name
+        assert rel(rg["I"], ro["I"]) < REL and rel(rg["var"], ro["var"]) < REL, (name, it, rg, ro)
+        g.refine()
+        o.refine()
+
+
+def test_adaptive_strata_bit_identical_across_launch_configurations(P):
+    cfg = W.config("w_plus")
+    n = 50_021
+
+    def run(**kw):
+        g = P.Integrator(cfg["process"], 4, 100, 1, 1.5, cfg["params"], max_events=n, **kw)
+        g.set_strata(6)
+        g.set_strata_beta(0.75)
+        out = []
+        for _ in range(3):
+            r = g.iterate(n)
+            out.append(np.array([r["I"], r["var"]]).tobytes() + g.strata_counts().tobytes())
+            g.refine()
+        return b"".join(out)
+
+    ref = run()
+    for wpb, mb in ((1, 0), (8, 0), (16, 5), (4, 97)):
+        assert run(waves_per_block=wpb, max_blocks=mb) == ref, (wpb, mb)
+
+
+def test_adaptive_strata_full_size_w_plus(P):
+    """10^6 events over 10^4 hypercubes with beta = 1: counts against the oracle's
+    rule, then integral and variance against the oracle with the counts injected."""
+    cfg = W.config("w_plus")
+    n = cfg["n_events"]
+    g, o = pair(P, cfg, n, 10)
+    g.set_strata_beta(1.0)
+    o.set_strata_beta(1.0)
+    for it in range(3):
+        o.set_grid(g.get_grid())
+        o.iteration = it
+        pred = o.strata_next_counts(n)
+        rg = g.iterate(n)
+        cg = g.strata_counts().astype(np.int64)
+        diff = np.abs(cg - pred)
+        assert diff.max() <= 1 and np.mean(diff > 0) <= 1e-3
+        o.inject_strata_counts(cg)
+        ro = o.iterate(n)
+        assert rel(rg["I"], ro["I"]) < REL and rel(rg["var"], ro["var"]) < REL, (it, rg, ro)
+        g.refine()
+        o.refine()
