@@ -93,7 +93,7 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strata", type=int, default=-1,
                     help="strata per axis of the stratified leg (-1: floor((N/2)^(1/D)), Lepage's choice; 0: skip)")
-    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: the workload's sample)")
     ap.add_argument("--cpu-events", type=int, default=0,
                     help="events per oracle iteration (0: the workload's sample, 10-30 s of host time)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -440,9 +440,10 @@ def bench_flow(args):
 # mass over the Drell-Yan window, the e+ p_T over its Jacobian peak, the e+ nu mass
 OBS_BINNING = {"dy_z": (40, 81.0, 101.0), "w_plus": (50, 20.0, 70.0), "ww_4l": (60, 60.0, 100.0),
                "ww_had": (60, 60.0, 100.0)}
-# events per oracle iteration of the CPU baseline (x --cpu-iters iterations): about
-# 10-30 s of one host core for each integrand's cost
-CPU_SAMPLE_EVENTS = {"w_plus": 4_000_000, "dy_z": 4_000_000, "ww_4l": 400_000, "ww_had": 300_000}
+# the CPU baseline's sample per workload, (iterations, events per iteration), about
+# 10-30 s of one host core: iterations of the workload's own size where it is small
+CPU_SAMPLE = {"w_plus": (6, 10_000_000), "dy_z": (2000, 10_000), "ww_4l": (5, 400_000),
+              "ww_had": (5, 500_000)}
 
 
 def observable_leg(args, make, Wn, N, plain_ms_min, plain_event):
@@ -680,8 +681,8 @@ def main():
         "strata": strata,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters,
-                                            min(args.cpu_events or CPU_SAMPLE_EVENTS[args.workload], 10 * N))
+        it_s, ev_s = CPU_SAMPLE[args.workload]
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or it_s, min(args.cpu_events or ev_s, 10 * N))
     g.close()
     print(json.dumps(line), flush=True)
 
