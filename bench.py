@@ -36,14 +36,14 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_746_191, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 170_335_162, "events": 10_000_000},
+    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_747_691, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 170_328_962, "events": 10_000_000},
     ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_313_878, "events": 10_000_000},
-    ("ww_had", "fp64"): {"f64": 1865.1, "f32": 0.0, "traffic": 296_615_206, "events": 10_000_000},
+    ("ww_had", "fp64"): {"f64": 1865.1, "f32": 0.0, "traffic": 296_468_716, "events": 10_000_000},
 }
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count
-HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 8_733_980}
+HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 8_735_004}
 # FP64 FLOPs of the adjoint's event kernel per (event, parameter point), and its HBM
 # bytes per call at 64 points x 1e6 events, from the same kind of counter runs
 ADJOINT_KERNEL_WORK = {"f64": 264.9, "traffic": 48_225_306, "events": 1_000_000}
