@@ -307,3 +307,25 @@ def test_full_size_sampled_flow_iteration(env):
     _, lqo = OF.sample(z.to(torch.float64), theta, bf16_emulation=True)
     assert_rounding_noise(np.abs(lq64 - lqo.numpy()), "log q at full size")
     assert abs(r["I"] - wg.sum() / n) <= 1e-12 * abs(r["I"])
+
+
+def test_identity_flow_iteration_fills_the_observable(env):
+    """The flow's event kernels with the observable histogram: with the identity flow
+    the bins equal the VEGAS iteration's up to the binary32 rounding of the points,
+    they add up to the flow iteration's estimate, and stratified sampling (which
+    would place the points itself) is refused for flow iterations."""
+    P, torch = env
+    n = 100_000
+    ga = P.Integrator(W.GAUSS, 8, 20, 21, 1.5, [0.5, 0.2], max_events=n)
+    gb = P.Integrator(W.GAUSS, 8, 20, 21, 1.5, [0.5, 0.2], max_events=n)
+    for g in (ga, gb):
+        g.set_observable(10, 0.2, 0.8, first=0)
+    f = P.Flow(max_batch=16, max_sample=n)
+    ra = ga.iterate(n)
+    rb = gb.iterate_flow(f, n)
+    A, B = ga.get_observable()[0], gb.get_observable()[0]
+    assert abs(B.sum() - rb["I"]) <= 1e-13 * np.sum(np.abs(B))
+    assert np.all(np.abs(B - A) <= 1e-4 * np.abs(A) + 1e-12 * np.max(A)), (A, B)
+    gb.set_strata(2)
+    with pytest.raises(P.VegasError):
+        gb.iterate_flow(f, n)
