@@ -249,7 +249,7 @@ def bench_paper_schedule(args):
     }
     if not args.no_cpu_baseline:
         import oracle
-        reps = 10
+        reps = 20                              # about 12 s of one host core
         o_t = 0.0
         for _ in range(reps):
             o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
@@ -319,7 +319,7 @@ def bench_adjoint(args):
         for _ in range(cfg["n_iter"]):
             o.iterate(cfg["n_events"])
             o.refine()
-        pts, ns = W.adjoint_points(64)[::4], 20_000
+        pts, ns = W.adjoint_points(64)[::4], 600_000        # about 10 s of one host core
         t0 = time.perf_counter()
         for th in pts:
             o.dy_grad(5, ns, th)
@@ -419,14 +419,16 @@ def bench_flow(args):
         theta = f.get_params().cpu().to(torch.float64)
         o = oracle.Vegas(cfg["process"], 8, cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
         o.set_grid(g.get_grid())
-        ns, it = 20_000, rf[0]["iteration"]
+        ns, chunk, it = 400_000, 20_000, rf[0]["iteration"]      # about 10 s
         t0 = time.perf_counter()
-        z = torch.tensor(np.array([oracle.uniforms(cfg["seed"], it, i, 8) for i in range(ns)]))
-        yo, lqo = OF.sample(z, theta)
-        yo, lqo = yo.numpy(), lqo.numpy()
-        for k in range(ns):
-            x, J, _ = o.grid_map(np.clip(yo[k], 2.0 ** -40, 1.0 - 2.0 ** -40))
-            J * oracle.integrand(cfg["process"], cfg["params"], x) * math.exp(-lqo[k])
+        for c0 in range(0, ns, chunk):
+            z = torch.tensor(np.array([oracle.uniforms(cfg["seed"], it, i, 8)
+                                       for i in range(c0, c0 + chunk)]))
+            yo, lqo = OF.sample(z, theta)
+            yo, lqo = yo.numpy(), lqo.numpy()
+            for k in range(chunk):
+                x, J, _ = o.grid_map(np.clip(yo[k], 2.0 ** -40, 1.0 - 2.0 ** -40))
+                J * oracle.integrand(cfg["process"], cfg["params"], x) * math.exp(-lqo[k])
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": ns / dt, "unit": "events/s", "cores": torch.get_num_threads(),
                                 "kind": "oracle",
