@@ -439,42 +439,8 @@ __device__ __forceinline__ int strata_exponent(double wmax, int npc) {
   return fx_exponent(wmax * wmax * static_cast<double>(npc));
 }
 
-// adaptive allocation (cnt non-null): hypercube h holds records off[h] .. off[h] +
-// cnt[h] - 1 of the scaled weights w_s = c_h w, c_h = N / (H n_h); the folded term
-// is n_h sum (w_s - mean)^2 / (n_h - 1) (var_j = V / N^2, bounded by 2 N max w_s^2),
-// and sigma_h of the unscaled weight is kept in sig for the next allocation
-__device__ __forceinline__ int strata_exponent_adapt(double wmax, double N) {
-  return fx_exponent(2.0 * N * wmax * wmax);
-}
-
-__global__ void k_strata(DevBufs b, int64_t H, int npc, const int32_t* cnt, const int32_t* off, double* sig,
-                         double N) {
-  const double wmx = __longlong_as_double(static_cast<long long>(b.maxw[0]));
-  const int EV = cnt ? strata_exponent_adapt(wmx, N) : strata_exponent(wmx, npc);
-  long long s0 = 0, s1 = 0, s2 = 0;
-  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
-    const int c = cnt ? cnt[h] : npc;
-    const double* w = b.rec_w + (cnt ? static_cast<int64_t>(off[h]) : h * npc);
-    double sum = 0.0;
-    for (int k = 0; k < c; ++k) sum += w[k];
-    const double mh = sum / static_cast<double>(c);
-    double V = 0.0;
-    for (int k = 0; k < c; ++k) {
-      const double dv = w[k] - mh;
-      V = __fma_rn(dv, dv, V);
-    }
-    if (cnt) {
-      const double ch = N / (static_cast<double>(H) * static_cast<double>(c));
-      sig[h] = sqrt(V / static_cast<double>(c - 1)) / ch;
-      V = static_cast<double>(c) * V / static_cast<double>(c - 1);
-    }
-    long long d0, d1, d2;
-    fx_digits_pos(V, EV, d0, d1, d2);
-    s0 += d0;
-    s1 += d1;
-    s2 += d2;
-  }
+// the block's digit sums -> its row of the partials (call with the whole block)
+__device__ __forceinline__ void strata_row(DevBufs& b, long long s0, long long s1, long long s2) {
   __shared__ long long red[3];
   if (threadIdx.x < 3) red[threadIdx.x] = 0;
   __syncthreads();
@@ -489,6 +455,142 @@ __global__ void k_strata(DevBufs b, int64_t H, int npc, const int32_t* cnt, cons
   }
   __syncthreads();
   if (threadIdx.x < 3) b.strat_part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x];
+}
+
+__global__ void k_strata(DevBufs b, int64_t H, int npc) {
+  const double wmx = __longlong_as_double(static_cast<long long>(b.maxw[0]));
+  const int EV = strata_exponent(wmx, npc);
+  long long s0 = 0, s1 = 0, s2 = 0;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
+    const double* w = b.rec_w + h * npc;
+    double sum = 0.0;
+    for (int k = 0; k < npc; ++k) sum += w[k];
+    const double mh = sum / static_cast<double>(npc);
+    double V = 0.0;
+    for (int k = 0; k < npc; ++k) {
+      const double dv = w[k] - mh;
+      V = __fma_rn(dv, dv, V);
+    }
+    long long d0, d1, d2;
+    fx_digits_pos(V, EV, d0, d1, d2);
+    s0 += d0;
+    s1 += d1;
+    s2 += d2;
+  }
+  strata_row(b, s0, s1, s2);
+}
+
+// ---------------------------------------------------------------------------
+// adaptive allocation: hypercube h holds records off[h] .. off[h] + cnt[h] - 1 of the
+// scaled weights w_s = c_h w, c_h = N / (H n_h); the folded term is
+// n_h sum (w_s - mean)^2 / (n_h - 1) (var_j = V / N^2, bounded by 2 N max w_s^2), and
+// sigma_h of the unscaled weight is kept in sig for the next allocation.
+// The counts span two orders of magnitude, so a thread per hypercube alone would leave
+// most lanes idle behind the largest: small hypercubes are folded by their own lane,
+// large ones by the whole wave.  The order of every sum depends on the counts alone,
+// never on the launch shape.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int strata_exponent_adapt(double wmax, double N) {
+  return fx_exponent(2.0 * N * wmax * wmax);
+}
+
+// sum over the wave by a butterfly: every lane adds the same two values at each stage,
+// so all lanes end with the same bits
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int st = kWave / 2; st > 0; st >>= 1) v += __shfl_xor(v, st, kWave);
+  return v;
+}
+
+// a DPP move of a binary64 value (both halves with the same control); lanes without a
+// source, or in rows the mask leaves out, receive 0
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROW_MASK, 0xf, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROW_MASK, 0xf, BOUND);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// sum over the wave in a fixed order: scans within each row of 16 lanes (row_shr 1, 2,
+// 4, 8), then row 0 into row 1 and row 2 into row 3 (row_bcast:15), then rows 0-1 into
+// rows 2-3 (row_bcast:31); lane 63 holds the total, read out for every lane.  DPP moves
+// stay in the VALU, where the butterfly's cross-lane permutes go through the LDS unit.
+__device__ __forceinline__ double wave_total_f64(double v) {
+  v += dpp_f64<0x111, 0xf, true>(v);
+  v += dpp_f64<0x112, 0xf, true>(v);
+  v += dpp_f64<0x114, 0xf, true>(v);
+  v += dpp_f64<0x118, 0xf, true>(v);
+  v += dpp_f64<0x142, 0xa, false>(v);
+  v += dpp_f64<0x143, 0xc, false>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), kWave - 1);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), kWave - 1);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// counts up to this are folded by the hypercube's own lane; larger ones by the whole
+// wave, one after another (fixed by the counts, so is every summation order)
+constexpr int kStrataLaneMax = 64;
+
+__global__ __launch_bounds__(256) void k_strata_adapt(DevBufs b, int64_t H, const int32_t* cnt, const int32_t* off,
+                                                      double* sig, double N) {
+  const double wmx = __longlong_as_double(static_cast<long long>(b.maxw[0]));
+  const int EV = strata_exponent_adapt(wmx, N);
+  const double Hd = static_cast<double>(H);
+  const double* __restrict__ rw = b.rec_w;
+  long long s0 = 0, s1 = 0, s2 = 0;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  // the loop runs per wave (base uniform), lane l taking hypercube base + l
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x + (threadIdx.x - lane); base < H;
+       base += step) {
+    const int64_t h = base + lane;
+    const bool valid = h < H;
+    const int c = valid ? cnt[h] : 0;
+    const int64_t o = valid ? off[h] : 0;
+    double V = 0.0;
+    if (valid && c <= kStrataLaneMax) {
+      const double* w = rw + o;
+      double sum = 0.0;
+      for (int k = 0; k < c; ++k) sum += w[k];
+      const double mh = sum / static_cast<double>(c);
+      for (int k = 0; k < c; ++k) {
+        const double dv = w[k] - mh;
+        V = __fma_rn(dv, dv, V);
+      }
+    }
+    unsigned long long big = __ballot(valid && c > kStrataLaneMax);
+    while (big) {
+      const int l = __ffsll(static_cast<long long>(big)) - 1;
+      big &= big - 1;
+      const int cl = __shfl(c, l, kWave);
+      const double* w = rw + __shfl(o, l, kWave);
+      double sum = 0.0;
+      for (int k = lane; k < cl; k += kWave) sum += w[k];
+      const double mh = wave_total_f64(sum) / static_cast<double>(cl);
+      double v = 0.0;
+      for (int k = lane; k < cl; k += kWave) {
+        const double dv = w[k] - mh;
+        v = __fma_rn(dv, dv, v);
+      }
+      v = wave_total_f64(v);
+      if (lane == l) V = v;
+    }
+    if (valid) {
+      const double cd = static_cast<double>(c);
+      const double ch = N / (Hd * cd);
+      sig[h] = sqrt(V / (cd - 1.0)) / ch;
+      V = cd * V / (cd - 1.0);
+      long long d0, d1, d2;
+      fx_digits_pos(V, EV, d0, d1, d2);
+      s0 += d0;
+      s1 += d1;
+      s2 += d2;
+    }
+  }
+  strata_row(b, s0, s1, s2);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,12 +715,53 @@ __global__ __launch_bounds__(kAllocThreads) void k_strata_alloc_c(int32_t* cnt, 
   }
 }
 
-// the hypercube index of every event: cube[off[h] .. off[h] + cnt[h] - 1] = h
-__global__ void k_strata_expand(const int32_t* cnt, const int32_t* off, int32_t* cube, int64_t H) {
-  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
-    const int32_t o = off[h];
-    for (int k = 0; k < cnt[h]; ++k) cube[o + k] = static_cast<int32_t>(h);
+// groups of 64 consecutive hypercubes, lane l of a wave owning hypercube 64 g + l; the
+// group's records are contiguous
+constexpr int32_t kNoRecord = 0x7fffffff;
+
+struct StrataGroup {
+  int32_t o, c;  // this lane's hypercube: first record and count (kNoRecord, 0 past H)
+  int64_t B, E;  // the group's records [B, E)
+};
+
+// call with the whole wave (g uniform)
+__device__ __forceinline__ StrataGroup strata_group(const int32_t* cnt, const int32_t* off, int64_t H, int64_t g) {
+  const int64_t h = g * kWave + (threadIdx.x & (kWave - 1));
+  StrataGroup s;
+  s.o = h < H ? off[h] : kNoRecord;
+  s.c = h < H ? cnt[h] : 0;
+  const int last = static_cast<int>(min<int64_t>(H - g * kWave, kWave)) - 1;
+  s.B = __shfl(s.o, 0, kWave);
+  s.E = static_cast<int64_t>(__shfl(s.o + s.c, last, kWave));
+  return s;
+}
+
+// the lane of the group whose hypercube holds record p, B <= p < E: the last lane whose
+// first record is <= p (first records increase strictly, every count being >= 2; past
+// H they are kNoRecord).  Call with the whole wave.
+__device__ __forceinline__ int strata_lane_of(int32_t p, int32_t o) {
+  int j = 0;
+#pragma unroll
+  for (int st = kWave / 2; st > 0; st >>= 1) {
+    const int32_t oc = __shfl(o, j + st, kWave);
+    if (oc <= p) j += st;
+  }
+  return j;
+}
+
+// the hypercube index of every event: cube[off[h] .. off[h] + cnt[h] - 1] = h, one
+// wave per group of 64 hypercubes writing its records 64 at a time
+__global__ __launch_bounds__(256) void k_strata_expand(const int32_t* cnt, const int32_t* off, int32_t* cube,
+                                                       int64_t H) {
+  const int lane = threadIdx.x & (kWave - 1), wpb = blockDim.x / kWave;
+  const int64_t ngroups = (H + kWave - 1) / kWave, gstep = static_cast<int64_t>(gridDim.x) * wpb;
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * wpb + threadIdx.x / kWave; g < ngroups; g += gstep) {
+    const StrataGroup s = strata_group(cnt, off, H, g);
+    for (int64_t cb = s.B; cb < s.E; cb += kWave) {
+      const int64_t p = cb + lane;
+      const int j = strata_lane_of(static_cast<int32_t>(p < s.E ? p : s.E - 1), s.o);
+      if (p < s.E) cube[p] = static_cast<int32_t>(g * kWave + j);
+    }
   }
 }
 
@@ -938,11 +1081,6 @@ __global__ void k_finalize(FinArgs f) {
 // ---------------------------------------------------------------------------
 // K4: grid refinement, one single-wave block per dimension
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Refinement of dimension d by one wave (lane = threadIdx.x % 64) with LDS scratch
 // sm[4 (n + 1)]; every wave of the block calls it the same number of times (its
@@ -1912,9 +2050,12 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
   const int strata_blocks = H > 0 ? static_cast<int>(std::min<int64_t>((H + 255) / 256, kStrataBlocks)) : 0;
   if (H > 0) {
     TimedLaunch t(h, 1);
-    hipExtLaunchKernelGGL(k_strata, dim3(strata_blocks), dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, H,
-                          static_cast<int>(npc), adapt ? h->s_cnt : nullptr, adapt ? h->s_off : nullptr,
-                          adapt ? h->s_sig : nullptr, static_cast<double>(n_events));
+    if (adapt)
+      hipExtLaunchKernelGGL(k_strata_adapt, dim3(strata_blocks), dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, H,
+                            h->s_cnt, h->s_off, h->s_sig, static_cast<double>(n_events));
+    else
+      hipExtLaunchKernelGGL(k_strata, dim3(strata_blocks), dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, H,
+                            static_cast<int>(npc));
     VG_HIP(t.done());
     if (adapt) h->s_have_sig = true;
   }
