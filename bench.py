@@ -36,10 +36,10 @@ sys.path.insert(0, ROOT)
 # x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
 # Measured on the kernels as built; the counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_747_691, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 170_328_962, "events": 10_000_000},
-    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_313_878, "events": 10_000_000},
-    ("ww_had", "fp64"): {"f64": 1865.1, "f32": 0.0, "traffic": 296_468_716, "events": 10_000_000},
+    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_738_472, "events": 1_000_000},
+    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_430_030, "events": 10_000_000},
+    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_309_482, "events": 10_000_000},
+    ("ww_had", "fp64"): {"f64": 1865.1, "f32": 0.0, "traffic": 293_333_428, "events": 10_000_000},
 }
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count

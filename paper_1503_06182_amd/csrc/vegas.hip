@@ -188,23 +188,25 @@ __device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls,
   ls.v[5] += h2;
 }
 
+// the digits are added whether or not they are zero: a branch around each atomic cost
+// more (2 % of the W+ and W+W- event kernels) than the atomics it saved
 __device__ __forceinline__ void acc_hist(long long* acc, int col, long long h0, long long h1, long long h2) {
   unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + col);
-  if (h0) atomicAdd(p + 0, static_cast<unsigned long long>(h0));
-  if (h1) atomicAdd(p + 1, static_cast<unsigned long long>(h1));
-  if (h2) atomicAdd(p + 2, static_cast<unsigned long long>(h2));
+  atomicAdd(p + 0, static_cast<unsigned long long>(h0));
+  atomicAdd(p + 1, static_cast<unsigned long long>(h1));
+  atomicAdd(p + 2, static_cast<unsigned long long>(h2));
 }
 
 // observable bin: the digits of w, then those of w^2
 __device__ __forceinline__ void acc_obs(long long* acc, int col, long long d0, long long d1, long long d2,
                                        long long h0, long long h1, long long h2) {
   unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + col);
-  if (d0) atomicAdd(p + 0, static_cast<unsigned long long>(d0));
-  if (d1) atomicAdd(p + 1, static_cast<unsigned long long>(d1));
-  if (d2) atomicAdd(p + 2, static_cast<unsigned long long>(d2));
-  if (h0) atomicAdd(p + 3, static_cast<unsigned long long>(h0));
-  if (h1) atomicAdd(p + 4, static_cast<unsigned long long>(h1));
-  if (h2) atomicAdd(p + 5, static_cast<unsigned long long>(h2));
+  atomicAdd(p + 0, static_cast<unsigned long long>(d0));
+  atomicAdd(p + 1, static_cast<unsigned long long>(d1));
+  atomicAdd(p + 2, static_cast<unsigned long long>(d2));
+  atomicAdd(p + 3, static_cast<unsigned long long>(h0));
+  atomicAdd(p + 4, static_cast<unsigned long long>(h1));
+  atomicAdd(p + 5, static_cast<unsigned long long>(h2));
 }
 
 // per-lane S1, S2 -> wave butterfly -> LDS columns 0..5 (call with the whole block)
