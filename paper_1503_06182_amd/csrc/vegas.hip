@@ -554,10 +554,14 @@ __global__ __launch_bounds__(256) void k_strata_adapt(DevBufs b, int64_t H, cons
     const int64_t o = valid ? off[h] : 0;
     double V = 0.0;
     if (valid && c <= kStrataLaneMax) {
+      // unrolled so that eight loads are in flight at once (each lane walks its own
+      // cache lines); the additions keep their order
       const double* w = rw + o;
       double sum = 0.0;
+#pragma unroll 8
       for (int k = 0; k < c; ++k) sum += w[k];
       const double mh = sum / static_cast<double>(c);
+#pragma unroll 8
       for (int k = 0; k < c; ++k) {
         const double dv = w[k] - mh;
         V = __fma_rn(dv, dv, V);
