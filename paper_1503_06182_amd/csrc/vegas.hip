@@ -467,9 +467,11 @@ __global__ void k_strata(DevBufs b, int64_t H, int npc) {
   for (int64_t h = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; h < H; h += step) {
     const double* w = b.rec_w + h * npc;
     double sum = 0.0;
+#pragma unroll 8
     for (int k = 0; k < npc; ++k) sum += w[k];
     const double mh = sum / static_cast<double>(npc);
     double V = 0.0;
+#pragma unroll 8
     for (int k = 0; k < npc; ++k) {
       const double dv = w[k] - mh;
       V = __fma_rn(dv, dv, V);
