@@ -1,21 +1,25 @@
 """Benchmark of the per-event VEGAS iteration on one MI355X.
 
-Workload (default): pp -> W+ -> e+ nu at sqrt(S) = 13 TeV, 4 dimensions, 100
-bins per dimension, 1e6 events per iteration, Breit-Wigner mapping, lepton
-pT > 20 GeV and |eta| < 2.5, synthetic PDFs A x^-0.5 (1-x)^3, seed 1.
-One step = one full VEGAS iteration: events -> exact accumulation ->
-finalisation (vegas_iterate) -> grid refinement (vegas_refine).
+Workload (default): q qbar -> W+W- -> e+ nu mu- nubar at sqrt(shat) = 500 GeV,
+tree-level helicity amplitudes, 8 dimensions (two Breit-Wigner masses and the
+sequential two-body decays), 100 bins per dimension, 1e7 events per iteration,
+binary64, seed 1.  One step = one full VEGAS iteration: events -> exact
+accumulation -> finalisation (vegas_iterate) -> grid refinement (vegas_refine;
+the grid adapts over the configuration's 10 iterations and is kept afterwards,
+the same kernels running every step).
 
 Warm-up: 0.2 s of the same steps on a throwaway handle (the clocks settle over the
 first tens of milliseconds of sustained load), then --warmup W (default 2) untimed
-steps on the measured handle and K = --steps (default 10) timed steps: the timed
-iterations are iterations W .. W+K-1 of a fresh integrator, as in the
-configuration's schedule.
+steps on the measured handle and K = --steps (default 10) timed steps.
 
 Prints one JSON line: events/s over the timed steps, the variance-weighted
 effective events/s 1/(eps^2 T) of the timed iterations' combined estimate, the
 roofline of the dominant kernel (timed with HIP events on the library's own
-stream) and the CPU oracle timed on a bounded sample on this host.
+stream), the same measurement with the matrix element in binary32 (fp32_me) and
+with the learned proposal (flow), each with its ratio of effective events/s to
+plain binary64 VEGAS, the serial CPU oracle timed on a bounded sample on this
+host (cpu_baseline) and the paper's threaded CPU scheme on all of this host's
+cores (cpu_baseline_all_cores).
 """
 from __future__ import annotations
 
@@ -82,7 +86,7 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps (default: 2 for the VEGAS iteration, whose grid they adapt; "
                          "as many as fill 0.2 s for the other workloads)")
-    ap.add_argument("--workload", default="w_plus",
+    ap.add_argument("--workload", default="ww_4l",
                     choices=["w_plus", "dy_z", "ww_4l", "ww_had", "ww_4l_paper", "adjoint", "flow"])
     ap.add_argument("--clock-warmup", type=float, default=0.2, metavar="SECONDS",
                     help="seconds of steps on a throwaway handle before the VEGAS-iteration schedule")
@@ -91,6 +95,8 @@ def parse_args():
     ap.add_argument("--events", type=int, default=0, help="events per iteration (0: workload's)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32me"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the headline measurement (no fp32_me, flow, observable or strata legs)")
     ap.add_argument("--strata", type=int, default=-1,
                     help="strata per axis of the stratified leg (-1: floor((N/2)^(1/D)), Lepage's choice; 0: skip)")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations (0: the workload's sample)")
@@ -170,6 +176,34 @@ def history_from_state(blob, ndim, nbins):
     return [(vals[2 * j], vals[2 * j + 1]) for j in range(it)]
 
 
+def host_info():
+    """The host CPU the baselines ran on: model name, logical CPUs, CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_threads():
+    """Threads for the all-core baseline: the CPUs this process may use, at most the
+    OMP_NUM_THREADS the environment grants (the GPU host's share)."""
+    n = host_info()["usable_cpus"] or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
 def cpu_baseline(cfg, iters, events):
     import oracle
     o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
@@ -181,7 +215,36 @@ def cpu_baseline(cfg, iters, events):
     dt = time.perf_counter() - t0
     return {"value": iters * events / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} iterations x {events} events of the same workload, serial "
-                      f"FP64 C oracle on one host core, {dt:.1f} s"}
+                      f"FP64 C oracle on one host core, {dt:.1f} s", **host_info()}
+
+
+def cpu_baseline_all_cores(cfg, iters, events):
+    """The paper's CPU scheme (Sec. 2.2) on all usable host cores: the oracle's event
+    loop split into fixed per-thread chunks, the partial sums added in chunk order."""
+    import oracle
+    T = cpu_threads()
+    o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                     cfg["params"])
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        o.iterate_threads(events, T)
+        o.refine()
+    dt = time.perf_counter() - t0
+    return {"value": iters * events / dt, "unit": "events/s", "cores": T,
+            "kind": "oracle, threaded (fixed chunks, fixed-order combine)",
+            "sample": f"{iters} iterations x {events} events of the same workload, FP64 C oracle "
+                      f"on {T} threads (OpenMP), {dt:.1f} s", **host_info()}
+
+
+# the paper's own timings, as context (other hardware, another integrand: MCFM's
+# pp -> H(-> b bbar) + 2 jets, 104,000 events of the 4 x 1,000 + 10 x 10,000 schedule)
+PAPER_CONTEXT = {
+    "note": "Sec. 3.2, Tables 1-8: H+2 jets, 10 (LO) / 13 (NLO) dims, 104,000 events per run",
+    "lo_best_events_per_s": {"value": 104000 / 0.26, "hardware": "2x Xeon X5650, 12 threads (Table 2)"},
+    "lo_i7_8_threads_events_per_s": {"value": 104000 / 0.32, "hardware": "Core i7-4770, 8 threads (Table 1)"},
+    "lo_phi_best_events_per_s": {"value": 104000 / 1.39, "hardware": "Xeon Phi 5110P, 32 threads (Table 4)"},
+    "nlo_best_events_per_s": {"value": 104000 / 25.36, "hardware": "4x Opteron 6128 HE, 32 threads (Table 7)"},
+}
 
 
 def bench_paper_schedule(args):
@@ -331,11 +394,13 @@ def bench_adjoint(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_flow(args):
+def bench_flow(args, emit=True):
     """Learned proposal on the W+W- integrand: the VEGAS grid converged (10 x 1e7),
     the flow trained on 1e6 events of one more VEGAS iteration (Adam, lr 1e-3, batch
     4096, 20 epochs), then K iterations of 1e7 events with the flow and K with plain
-    VEGAS on the same frozen grid.  One step = one flow iteration."""
+    VEGAS on the same frozen grid.  One step = one flow iteration.  emit=False: no
+    CPU baseline, nothing printed, the line returned (the flow leg of the default
+    benchmark)."""
     import torch
 
     import paper_1503_06182_amd as P
@@ -407,6 +472,10 @@ def bench_flow(args):
             "training": {"seconds": t_train, "steps": steps_train, "loss_first": losses[0][1],
                          "loss_last": losses[-1][1]},
             "roofline": roof}
+    if not emit:
+        g.close()
+        f.close()
+        return line
     if not args.no_cpu_baseline:
         # the oracle's flow iteration on a bounded sample: z from the counter stream,
         # y = F^-1(z) by the float64 flow oracle, w = J f / q by the C oracle
@@ -446,6 +515,9 @@ OBS_BINNING = {"dy_z": (40, 81.0, 101.0), "w_plus": (50, 20.0, 70.0), "ww_4l": (
 # 10-30 s of one host core: iterations of the workload's own size where it is small
 CPU_SAMPLE = {"w_plus": (6, 10_000_000), "dy_z": (2000, 10_000), "ww_4l": (5, 400_000),
               "ww_had": (5, 500_000)}
+# the all-core baseline's sample, about 10 s on 16 threads
+CPU_SAMPLE_ALL_CORES = {"w_plus": (10, 10_000_000), "dy_z": (2000, 10_000), "ww_4l": (4, 2_500_000),
+                        "ww_had": (4, 2_000_000)}
 
 
 def observable_leg(args, make, Wn, N, plain_ms_min, plain_event):
@@ -552,6 +624,76 @@ def strata_leg(args, make, Wn, N, D, plain_ms_min, plain_hist):
             "adaptive": strata_run(args, make, Wn, N, ma, 0.75, plain_ms_min, plain_hist)}
 
 
+def measure_vegas(args, cfg, prec, N):
+    """The VEGAS iteration of one workload at one precision: clock warm-up on a
+    throwaway handle, W untimed and K timed steps on a fresh one (events/s, the timed
+    iterations' combined error), K more with HIP events bound to each kernel (kernel
+    durations), and 10 more blocks of K steps (min / avg / max per step).  The grid is
+    refined after each of the configuration's n_iter iterations and kept afterwards."""
+    import torch
+
+    import paper_1503_06182_amd as P
+    n_adapt = cfg["n_iter"]
+
+    def make():
+        h = P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                         cfg["params"], precision=prec, max_events=N)
+        h.bench_iters = 0
+        return h
+
+    def step(h):
+        h.iterate(N, sync=False)
+        h.bench_iters += 1
+        if h.bench_iters <= n_adapt:
+            h.refine()
+
+    clock_s = clock_warm_up(make, step, args.clock_warmup) if args.clock_warmup > 0 else 0.0
+    g = make()
+    Wn = 2 if args.warmup is None else args.warmup
+    for _ in range(Wn):
+        step(g)
+    torch.cuda.synchronize()
+    # throughput: K steps with nothing between the kernels
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(g)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    hist = history_from_state(g.get_state(), cfg["ndim"], cfg["nbins"])
+    timed = hist[Wn:Wn + args.steps]
+    # kernel durations: K more steps with HIP start/stop events bound to each kernel's
+    # dispatch on the library's stream.  The events cost host time per launch: inside
+    # the throughput pass, even on the event kernel alone, they slowed the W+ step by
+    # 16 % (the host could no longer run ahead of the GPU), so this identical pass
+    # follows the timed region instead
+    g.set_timing(True)
+    g.stage_times(reset=True)
+    for _ in range(args.steps):
+        step(g)
+    torch.cuda.synchronize()
+    st = g.stage_times()
+    g.set_timing(False)
+    # spread over repetitions: 10 more blocks of K steps (ms per step, min / avg / max)
+    reps = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(g)
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t1) / args.steps * 1e3)
+    shape = g.last_launch()
+    g.close()
+    I, sig = combine(timed)
+    eps = sig / abs(I)
+    # Kish effective sample size of each timed iteration, (sum w)^2 / sum w^2 =
+    # N I^2 / (I^2 + (N - 1) var), per second of the timed region
+    kish = sum(N * i * i / (i * i + (N - 1) * v) if (i * i + v) > 0 else 0.0 for i, v in timed)
+    return {"make": make, "Wn": Wn, "T": T, "timed": timed, "st": st, "reps": reps, "shape": shape,
+            "clock_s": clock_s, "I": I, "eps": eps, "events_per_s": args.steps * N / T,
+            "eff": 1.0 / (eps * eps * T), "kish": kish / T}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -580,70 +722,20 @@ def main():
     cfg = W.config(args.workload)
     N = args.events or cfg["n_events"]
     prec = P.FP32_ME if args.precision == "fp32me" else P.FP64
-    def make():
-        return P.Integrator(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
-                            cfg["params"], precision=prec, max_events=N)
+    m = measure_vegas(args, cfg, prec, N)
+    make, Wn, st, reps, timed, shape = m["make"], m["Wn"], m["st"], m["reps"], m["timed"], m["shape"]
 
-    def step(h):
-        h.iterate(N, sync=False)
-        h.refine()
-
-    clock_s = clock_warm_up(make, step, args.clock_warmup) if args.clock_warmup > 0 else 0.0
-    g = make()
-    Wn = 2 if args.warmup is None else args.warmup
-    for _ in range(Wn):
-        step(g)
-    torch.cuda.synchronize()
-    # throughput: K steps with nothing between the kernels
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.iterate(N, sync=False)
-        g.refine()
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    hist = history_from_state(g.get_state(), cfg["ndim"], cfg["nbins"])
-    timed = hist[Wn:Wn + args.steps]
-    # kernel durations: K more steps with HIP start/stop events bound to each kernel's
-    # dispatch on the library's stream.  The events cost host time per launch: inside
-    # the throughput pass, even on the event kernel alone, they slowed the W+ step by
-    # 16 % (the host could no longer run ahead of the GPU), so this identical pass
-    # follows the timed region instead
-    g.set_timing(True)
-    g.stage_times(reset=True)
-    for _ in range(args.steps):
-        g.iterate(N, sync=False)
-        g.refine()
-    torch.cuda.synchronize()
-    st = g.stage_times()
-    g.set_timing(False)
-    I, sig = combine(timed)
-    eps = sig / abs(I)
-    events_per_s = args.steps * N / T
-    eff = 1.0 / (eps * eps * T)
-    # Kish effective sample size of each timed iteration, (sum w)^2 / sum w^2 =
-    # N I^2 / (I^2 + (N - 1) var), per second of the timed region
-    kish = sum(N * i * i / (i * i + (N - 1) * v) if (i * i + v) > 0 else 0.0 for i, v in timed)
-    # spread over repetitions: 10 more blocks of K steps (ms per step, min / avg / max)
-    reps = []
-    for _ in range(10):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            g.iterate(N, sync=False)
-            g.refine()
-        torch.cuda.synchronize()
-        reps.append((time.perf_counter() - t1) / args.steps * 1e3)
-
+    legs = not args.no_legs
     obs_leg = observable_leg(args, make, Wn, N, min(reps), st["event"]) \
-        if args.workload in OBS_BINNING else None
-    strata = strata_leg(args, make, Wn, N, cfg["ndim"], min(reps), timed) if args.strata != 0 else None
+        if legs and args.workload in OBS_BINNING else None
+    strata = strata_leg(args, make, Wn, N, cfg["ndim"], min(reps), timed) \
+        if legs and args.strata != 0 else None
 
     ms_ev, n_ev = st["event"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
     roof = roofline(args.workload, args.precision, N, avg_ev)
     # histogram stage: the column sums of the per-block partial rows (S1, S2 and the
     # per-bin d digits) -- HBM-bound; algorithmic bytes = rows x columns x 8 read
-    shape = g.last_launch()
     ms_fold, n_fold = st["fold"]
     hist_bytes = shape["fold_rows"] * shape["fold_cols"] * 8
     avg_fold = ms_fold / max(n_fold, 1) * 1e-3
@@ -656,36 +748,66 @@ def main():
                   "launch": shape}
     line = {
         "metric": "events/s and effective events/s (1/var) at 1e-3 rel. error, 1 MI355X",
-        "value": events_per_s,
+        "value": m["events_per_s"],
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": Wn,
-        "gpu_clock_warmup_s": round(clock_s, 3),
-        "ms_per_step": T / args.steps * 1e3,
+        "gpu_clock_warmup_s": round(m["clock_s"], 3),
+        "ms_per_step": m["T"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == P.FP64 else "f32-me/f64",
         "data": "synthetic (counter-based Philox stream, seed 1; parametric PDFs)",
         "config": {"workload": args.workload, "events_per_iteration": N, "ndim": cfg["ndim"],
-                   "nbins": cfg["nbins"], "iterations_timed": args.steps},
-        "effective_events_per_s": eff,
-        "time_to_1e-3_s": 1e6 / eff,
-        "kish_ess_per_s": kish / T,
+                   "nbins": cfg["nbins"], "iterations_timed": args.steps,
+                   "grid_adapted_iterations": cfg["n_iter"]},
+        "effective_events_per_s": m["eff"],
+        "time_to_1e-3_s": 1e6 / m["eff"],
+        "kish_ess_per_s": m["kish"],
         "ms_per_step_10_repeats": {"min": min(reps), "avg": sum(reps) / len(reps), "max": max(reps)},
-        "integral_pb": I,
-        "rel_error": eps,
+        "integral_pb": m["I"],
+        "rel_error": m["eps"],
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
         "roofline": roof,
         "histogram_stage": hist_stage,
-        "observable": obs_leg,
-        "strata": strata,
     }
+    # the binary32 matrix element on the same workload (W+W- only), and the learned
+    # proposal: their effective events/s against this line's plain binary64 VEGAS
+    if legs and args.workload == "ww_4l" and prec == P.FP64:
+        m32 = measure_vegas(args, cfg, P.FP32_ME, N)
+        ms32, n32 = m32["st"]["event"]
+        roof32 = roofline(args.workload, "fp32me", N, ms32 / max(n32, 1) * 1e-3)
+        line["fp32_me"] = {
+            "events_per_s": m32["events_per_s"], "effective_events_per_s": m32["eff"],
+            "ms_per_step": m32["T"] / args.steps * 1e3,
+            "ms_per_step_10_repeats": {"min": min(m32["reps"]), "avg": sum(m32["reps"]) / 10,
+                                       "max": max(m32["reps"])},
+            "rel_error": m32["eps"], "integral_pb": m32["I"],
+            "speedup_events_per_s_vs_fp64": m32["events_per_s"] / m["events_per_s"],
+            "speedup_effective_vs_fp64": m32["eff"] / m["eff"],
+            "speedup_min_ms_per_step_vs_fp64": min(reps) / min(m32["reps"]),
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in m32["st"].items()},
+            "roofline": roof32}
+        fl = bench_flow(args, emit=False)
+        line["flow"] = {
+            "events_per_s": fl["value"], "effective_events_per_s": fl["effective_events_per_s"],
+            "ms_per_step": fl["ms_per_step"],
+            "vegas_same_grid_effective_events_per_s": fl["vegas_effective_events_per_s"],
+            "effective_gain_vs_vegas_same_grid": fl["effective_gain_vs_vegas"],
+            "effective_gain_vs_fp64_line": fl["effective_events_per_s"] / m["eff"],
+            "per_event_rel_variance": fl["per_event_rel_variance"], "flow_uses": fl["flow_uses"],
+            "integral_pb": fl["integral_pb"], "training": fl["training"], "config": fl["config"],
+            "roofline": fl["roofline"]}
+    line["observable"] = obs_leg
+    line["strata"] = strata
     if not args.no_cpu_baseline:
         it_s, ev_s = CPU_SAMPLE[args.workload]
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or it_s, min(args.cpu_events or ev_s, 10 * N))
-    g.close()
+        it_a, ev_a = CPU_SAMPLE_ALL_CORES[args.workload]
+        line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(cfg, it_a, min(ev_a, 10 * N))
+        line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
 

@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
     if force or not os.path.exists(LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", LIB_PATH, SRC, "-lm"]
+               "-fno-fast-math", "-fopenmp", "-Wall", "-o", LIB_PATH, SRC, "-lm"]
         subprocess.run(cmd, check=True)
     return LIB_PATH
 
@@ -67,6 +67,7 @@ def lib():
         L.ora_create.restype = C.c_void_p
         L.ora_destroy.argtypes = [C.c_void_p]
         L.ora_iterate.argtypes = [C.c_void_p, C.c_int64, _dp]
+        L.ora_iterate_threads.argtypes = [C.c_void_p, C.c_int64, C.c_int, _dp]
         L.ora_refine.argtypes = [C.c_void_p]
         L.ora_result.argtypes = [C.c_void_p, _dp]
         L.ora_result_from.argtypes = [C.c_void_p, C.c_int, _dp]
@@ -207,6 +208,15 @@ class Vegas:
         used = H * lib().ora_strata_npc(self._h) if H > 0 and not getattr(self, "_adaptive", False) else n
         return {"I": out[0], "var": out[1], "n_nonzero": int(out[2]), "n_nonfinite": int(out[3]),
                 "n_events": int(used)}
+
+    def iterate_threads(self, n, nthreads):
+        """The same iteration over nthreads threads with fixed chunks and the partials
+        added in chunk order (the all-core CPU baseline; plain importance sampling)."""
+        out = np.zeros(4)
+        if lib().ora_iterate_threads(self._h, n, nthreads, out) != 0:
+            raise ValueError("oracle iterate_threads failed")
+        return {"I": out[0], "var": out[1], "n_nonzero": int(out[2]), "n_nonfinite": int(out[3]),
+                "n_events": int(n)}
 
     def refine(self):
         if lib().ora_refine(self._h) != 0:

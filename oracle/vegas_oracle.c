@@ -13,10 +13,10 @@
  * step; the readings used are listed in the design notes and restated in the
  * comment of each function.
  *
- * Parity status: the random-number generator (Philox4x32-10) has no
- * known-answer vector in this repository -- "parity unpinned" against an
- * external truth; it is pinned by statistical tests only.  Everything else is
- * pinned by closed forms, invariants or brute-force quadrature in
+ * Pins: the random-number generator (Philox4x32-10) reproduces the published
+ * known-answer vectors of its authors (tests/golden/philox4x32_10_kat.txt), and
+ * the uniform construction is checked against the first of them; everything
+ * else is pinned by closed forms, invariants or brute-force quadrature in
  * tests/test_oracle_*.py.
  */
 #include "vegas_oracle.h"
@@ -1149,6 +1149,73 @@ int ora_iterate(ora_state *s, int64_t n_req, double out[4]) {
     }
     s->obs_have = 1;
   }
+  s->n_iter++;
+  s->iter++;
+  out[0] = mean;
+  out[1] = var;
+  out[2] = (double)nz;
+  out[3] = (double)nnf;
+  return 0;
+}
+
+/* The CPU scheme of the paper, for the all-core baseline beside the serial
+ * oracle (Sec. 2.2): the event loop split over nthreads threads, thread t
+ * taking the fixed chunk of events [t n / T, (t + 1) n / T) and accumulating
+ * its own long-double S1, S2 and d; the chunks' partials are then added in
+ * chunk order, so the result depends on T only through that fixed split, never
+ * on the scheduling.  Plain importance sampling only (no strata, no observable).
+ * Updates the state exactly as ora_iterate does. */
+int ora_iterate_threads(ora_state *s, int64_t n, int nthreads, double out[4]) {
+  if (n < 2 || nthreads < 1 || s->strata_m > 0 || s->nobs) return -1;
+  const int D = s->ndim, nb = s->nbins, T = nthreads;
+  const size_t row = 2 + (size_t)D * nb;
+  long double *part = (long double *)calloc((size_t)T * row, sizeof(long double));
+  int64_t *cnt = (int64_t *)calloc((size_t)T * 2, sizeof(int64_t));
+  if (!part || !cnt) {
+    free(part);
+    free(cnt);
+    return -1;
+  }
+#pragma omp parallel for schedule(static, 1) num_threads(T)
+  for (int t = 0; t < T; ++t) {
+    long double *p = part + (size_t)t * row;
+    int b[16];
+    const int64_t lo = n * t / T, hi = n * (t + 1) / T;
+    for (int64_t i = lo; i < hi; ++i) {
+      double w = event_weight(s, s->iter, (uint64_t)i, b);
+      if (!isfinite(w)) { ++cnt[2 * t + 1]; continue; }
+      if (w != 0.0) ++cnt[2 * t];
+      double w2 = w * w;
+      p[0] += w;
+      p[1] += w2;
+      for (int d = 0; d < D; ++d) p[2 + d * nb + b[d]] += w2;
+    }
+  }
+  long double s1 = 0.0L, s2 = 0.0L;
+  int64_t nz = 0, nnf = 0;
+  for (int i = 0; i < D * nb; ++i) s->d[i] = 0.0L;
+  for (int t = 0; t < T; ++t) {
+    const long double *p = part + (size_t)t * row;
+    s1 += p[0];
+    s2 += p[1];
+    for (int i = 0; i < D * nb; ++i) s->d[i] += p[2 + i];
+    nz += cnt[2 * t];
+    nnf += cnt[2 * t + 1];
+  }
+  free(part);
+  free(cnt);
+  s->s1 = s1;
+  s->s2 = s2;
+  s->have_hist = 1;
+  double mean = (double)(s1 / (long double)n);
+  double var = (double)((s2 / (long double)n - (long double)mean * (long double)mean) / (long double)(n - 1));
+  if (s->n_iter == s->cap) {
+    s->cap *= 2;
+    s->Ij = (double *)realloc(s->Ij, sizeof(double) * s->cap);
+    s->varj = (double *)realloc(s->varj, sizeof(double) * s->cap);
+  }
+  s->Ij[s->n_iter] = mean;
+  s->varj[s->n_iter] = var;
   s->n_iter++;
   s->iter++;
   out[0] = mean;

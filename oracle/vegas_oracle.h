@@ -82,6 +82,9 @@ ora_state *ora_create(int process, int ndim, int nbins, uint64_t seed, double al
 void ora_destroy(ora_state *s);
 /* one iteration of n events at the current grid; out = {I_j, var_j, n_nonzero, n_nonfinite} */
 int ora_iterate(ora_state *s, int64_t n, double out[4]);
+/* the same iteration over nthreads threads (fixed chunks, partials added in chunk
+ * order; plain importance sampling only): the all-core CPU baseline */
+int ora_iterate_threads(ora_state *s, int64_t n, int nthreads, double out[4]);
 int ora_refine(ora_state *s);
 /* out = {I, sigma, chi2/dof, n_iter} */
 int ora_result(const ora_state *s, double out[4]);

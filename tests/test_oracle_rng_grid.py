@@ -4,14 +4,53 @@ The paper (Sec. 2.1) fixes the structure -- iterations of event sets, a grid
 re-optimised after each iteration from all events -- but prints no formula; the
 pins below are invariants and closed forms of the VEGAS mathematics.
 """
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _philox_kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                v = [int(t, 16) for t in line.split()]
+                rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
 
 # ---------------------------------------------------------------- RNG -------
+def test_philox_known_answer_vectors():
+    """The generator against the published Philox4x32-10 known-answer vectors
+    (Salmon et al., SC'11; the replacement of the paper's per-thread groups of
+    random numbers, Sec. 2.2)."""
+    rows = _philox_kat()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        got = [int(x) for x in oracle.philox(ctr, key)]
+        assert got == want, (ctr, key, [hex(x) for x in got])
+
+
+def test_uniform_construction_from_known_answer():
+    """Event 0 of iteration 0 under seed 0 is counter (0, 0, 0, 0), key (0, 0): its
+    two uniforms are the top 52 bits of output words (1:0) and (3:2) of the first
+    known-answer vector, as (2w + 1) 2^-53, formed here with Python integers."""
+    ctr, key, out = _philox_kat()[0]
+    assert ctr == [0, 0, 0, 0] and key == [0, 0]
+    want = []
+    for hi, lo in ((out[1], out[0]), (out[3], out[2])):
+        w = ((hi << 32) | lo) >> 12
+        want.append((2 * w + 1) / 2.0 ** 53)
+    u = oracle.uniforms(0, 0, 0, 2)
+    assert list(u) == want
+
+
 def test_uniforms_deterministic_and_open_interval():
     a = np.array([oracle.uniforms(1, 3, i, 8) for i in range(2000)])
     b = np.array([oracle.uniforms(1, 3, i, 8) for i in range(2000)])

@@ -197,3 +197,27 @@ def test_two_stage_schedule_pulls_after_dropping_warm_up():
     pulls = np.array(pulls)
     assert abs(pulls.mean()) < 0.5
     assert 0.7 < pulls.std() < 1.35
+
+
+def test_threaded_iteration_matches_serial():
+    """The all-core CPU baseline (the paper's scheme of Sec. 2.2: fixed per-thread
+    chunks, partials added in a fixed order) computes the same iteration as the
+    serial oracle: bit for bit with one thread, to the rounding of the long-double
+    partial sums with several; the refined grids agree likewise."""
+    cfg = W.config("w_plus")
+
+    def mk():
+        return oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"],
+                            cfg["params"])
+
+    a, b, c = mk(), mk(), mk()
+    for _ in range(3):
+        ra, rb, rc = a.iterate(30_000), b.iterate_threads(30_000, 1), c.iterate_threads(30_000, 5)
+        assert ra["I"] == rb["I"] and ra["var"] == rb["var"]
+        assert ra["n_nonzero"] == rc["n_nonzero"] and ra["n_nonfinite"] == rc["n_nonfinite"]
+        assert abs(rc["I"] - ra["I"]) <= 1e-15 * abs(ra["I"])
+        assert abs(rc["var"] - ra["var"]) <= 1e-13 * ra["var"]
+        a.refine(), b.refine(), c.refine()
+    assert np.array_equal(a.get_grid(), b.get_grid())
+    assert np.abs(a.get_grid() - c.get_grid()).max() < 1e-13
+    assert a.result()["I"] == b.result()["I"]
