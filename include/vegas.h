@@ -108,7 +108,8 @@ typedef struct {
                            digits do not fit one block's LDS); 1 = inside the
                            event kernel at the scale fixed by the previous
                            iteration (2^16 above its max |w|); 2 = like 1, but
-                           this iteration's max |w| left [2^-40, 1) of that scale,
+                           this iteration's max |w| left [2^-40, 1) of that scale
+                           (or its max w^2 left [2^-40, 1) of the scale of w^2),
                            so the sums were re-folded from the records at the
                            iteration's own scale.  Any fold gives the same
                            integers for every launch configuration. */
@@ -288,7 +289,9 @@ int vegas_set_timing(vegas_handle h, int32_t stages);
 
 /* Launch shape of the last iteration: info[0] event-kernel blocks, info[1]
  * threads per block, info[2] rows of per-block partials folded, info[3] int64
- * columns per row (3 (2 + ndim nbins)); host array of 4.
+ * columns per row (7 + 4 ndim nbins: three digits of S1, four of S2 and of each
+ * grid-histogram bin; plus seven per observable bin, under- and overflow
+ * included, when an observable histogram is set); host array of 4.
  * Errors: VEGAS_EINVAL, VEGAS_ESTATE (no iteration yet). */
 int vegas_last_launch(vegas_handle h, int64_t *info);
 int vegas_stage_times(vegas_handle h, double *ms, int64_t *launches, int32_t reset);

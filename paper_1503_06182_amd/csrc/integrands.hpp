@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_common.hpp"
+
 namespace vg {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -52,6 +54,53 @@ struct PhysConst {
 };
 
 // ---------------------------------------------------------------------------
+// sin and cos of |y| <= pi/4 by their Taylor series up to y^17 and y^18 (the next
+// terms are below 2^-62 of the sums there)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_taylor(double y, double& sn, double& cs) {
+  const double y2 = y * y;
+  // sin y = y + y^3 sum_k (-1)^(k+1) y^2k / (2k + 3)!, cos y = 1 + y^2 sum_k (-1)^(k+1) y^2k / (2k + 2)!
+  double ps = 1.0 / 355687428096000.0;            // 1/17!
+  ps = __fma_rn(ps, y2, -1.0 / 1307674368000.0);  // 1/15!
+  ps = __fma_rn(ps, y2, 1.0 / 6227020800.0);      // 1/13!
+  ps = __fma_rn(ps, y2, -1.0 / 39916800.0);       // 1/11!
+  ps = __fma_rn(ps, y2, 1.0 / 362880.0);          // 1/9!
+  ps = __fma_rn(ps, y2, -1.0 / 5040.0);           // 1/7!
+  ps = __fma_rn(ps, y2, 1.0 / 120.0);             // 1/5!
+  ps = __fma_rn(ps, y2, -1.0 / 6.0);              // 1/3!
+  double pc = -1.0 / 6402373705728000.0;          // 1/18!
+  pc = __fma_rn(pc, y2, 1.0 / 20922789888000.0);  // 1/16!
+  pc = __fma_rn(pc, y2, -1.0 / 87178291200.0);    // 1/14!
+  pc = __fma_rn(pc, y2, 1.0 / 479001600.0);       // 1/12!
+  pc = __fma_rn(pc, y2, -1.0 / 3628800.0);        // 1/10!
+  pc = __fma_rn(pc, y2, 1.0 / 40320.0);           // 1/8!
+  pc = __fma_rn(pc, y2, -1.0 / 720.0);            // 1/6!
+  pc = __fma_rn(pc, y2, 1.0 / 24.0);              // 1/4!
+  pc = __fma_rn(pc, y2, -0.5);                    // 1/2!
+  sn = __fma_rn(y * y2, ps, y);
+  cs = __fma_rn(y2, pc, 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// tan(x) for |x| < pi/2 (the Breit-Wigner map's arguments): |x| > pi/4 is folded to
+// y = pi/2 - |x| (pi/2 as the sum of two binary64 numbers; the first difference is
+// exact, both being within a factor 2), then tan = sin/cos or cos/sin of y.  A few
+// units in the last place, against half a unit for the library's general tan, at
+// well under half its instructions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double tan_halfpi(double x) {
+  constexpr double kPio4 = 0.78539816339744830962, kPio2Hi = 1.5707963267948966,
+                   kPio2Lo = 6.123233995736766e-17;
+  const double a = fabs(x);
+  const bool big = a > kPio4;
+  const double y = big ? (kPio2Hi - a) + kPio2Lo : a;
+  double sn, cs;
+  sincos_taylor(y, sn, cs);
+  const double t = big ? div_nr(cs, sn) : div_nr(sn, cs);
+  return copysign(t, x);
+}
+
+// ---------------------------------------------------------------------------
 // mappings (rounding kept as in their plain definitions: no contraction)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double bw_map(double r, double M2, double MG, double invMG, double m2lo, double tlo,
@@ -62,8 +111,8 @@ __device__ __forceinline__ double bw_map(double r, double M2, double MG, double 
   // addition theorem), free of the cancellation in M^2 + M G tan(rho) as m^2 -> m2lo;
   // one tangent per event either way (no divergent second call)
   const bool below = rho < 0.0;
-  const double t = tan(below ? r * rrng : rho);
-  const double m2 = below ? m2lo + MG * (1.0 + tlo * tlo) * t / (1.0 - tlo * t) : M2 + MG * t;
+  const double t = tan_halfpi(below ? r * rrng : rho);
+  const double m2 = below ? m2lo + MG * (1.0 + tlo * tlo) * t * rcp_nr(1.0 - tlo * t) : M2 + MG * t;
   const double dm = m2 - M2;
   jac = rrng * (dm * dm + MG * MG) * invMG;
   return m2;
@@ -86,8 +135,8 @@ __device__ __forceinline__ double pdf_pair(const PhysConst& c, double tau, doubl
     const int a2 = c.pdf_a2;
     const int ka = (a2 >= 0 ? a2 : -a2) >> 1;   // |a| rounded down
     double ta = ipow_pos(tau, ka);
-    if (a2 & 1) ta *= sqrt(tau);
-    if (a2 < 0) ta = 1.0 / ta;
+    if (a2 & 1) ta *= sqrt_nr(tau);
+    if (a2 < 0) ta = rcp_nr(ta);
     return c.pdfA * c.pdfA * ta * ipow_pos(P, c.pdf_b);
   }
   return c.pdfA * c.pdfA * exp(c.pdfa * L + c.pdfb * log(P));
@@ -175,9 +224,9 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x, doub
   const double cs = 2.0 * x[2] - 1.0;
   // 1 / (shat - MZ^2 + i MZ GZ)
   const double ds = m2 - c.mz2;
-  const double den = 1.0 / (ds * ds + c.mzgz * c.mzgz);
+  const double den = rcp_nr(ds * ds + c.mzgz * c.mzgz);
   const double pre = ds * den, pim = -c.mzgz * den;
-  const double inv_s = 1.0 / m2;
+  const double inv_s = rcp_nr(m2);
   double sum = 0.0;
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -215,14 +264,14 @@ __device__ __forceinline__ double f_w(const PhysConst& c, const double* x, doubl
   const double em1 = expm1(l1), em2 = expm1(l2);
   const double pt2 = 0.25 * m2 * (1.0 - cs) * (1.0 + cs);
   obs_sq = pt2;
-  const double beta = (em1 - em2) / (2.0 + em1 + em2);
+  const double beta = div_nr(em1 - em2, 2.0 + em1 + em2);
   const double num = cs + beta, dnm = 1.0 + beta * cs;
   const bool pass = (pt2 > c.ptmin2) && (num * num < c.th2 * dnm * dnm);
   if (!pass) return 0.0;
   const double ds = m2 - c.M2;
   const double den = ds * ds + c.MG * c.MG;
   // |M|^2 / (2 shat) = g^4 |V|^2 / 24 * shat^2 (1 + cos^2) / den / (2 shat): one division
-  const double me_flux = c.g4v2_24 * (0.5 * m2) * (1.0 + cs * cs) / den;
+  const double me_flux = c.g4v2_24 * (0.5 * m2) * (1.0 + cs * cs) * rcp_nr(den);
   const double ff = pdf_pair(c, m2 * c.invS, L, em1 * em2);
   // conv * J_bw * J_tau * |M|^2 / (2 shat) * (2 * 2 pi)/(32 pi^2)
   return c.conv * jbw * jtau * (1.0 / (8.0 * kPi)) * ff * me_flux;
@@ -254,20 +303,19 @@ __device__ __forceinline__ cx<R> cconjmul(cx<R> a, cx<R> b) {  // conj(a) * b
 template <typename R>
 __device__ __forceinline__ R cabs2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 
-// helicity-minus massless 2-spinor (left-chiral), phase chosen per hemisphere
+// helicity-minus massless 2-spinor (left-chiral), phase chosen per hemisphere: with
+// r = sqrt(p0 + |p3|), (-(p1 - i p2) / r, r) for p3 >= 0 and (-r, (p1 + i p2) / r) below
+// (the two differ by a phase, so |M|^2 does not depend on the choice; dividing by the
+// larger of p0 +- p3 avoids the cancellation).  One square root and its reciprocal from
+// the same estimate, and selects instead of branches (a wave holds both hemispheres).
 template <typename R>
 __device__ __forceinline__ void spinor_m(const R p[4], cx<R>& s0, cx<R>& s1) {
-  if (p[3] >= R(0)) {
-    const R r = sqrt(p[0] + p[3]);
-    const R ir = R(1) / r;
-    s0 = {-p[1] * ir, p[2] * ir};
-    s1 = {r, R(0)};
-  } else {
-    const R r = sqrt(p[0] - p[3]);
-    const R ir = R(1) / r;
-    s0 = {-r, R(0)};
-    s1 = {p[1] * ir, p[2] * ir};
-  }
+  const bool up = p[3] >= R(0);
+  R r, ir;
+  sqrt_rsqrt_nr(p[0] + fabs(p[3]), r, ir);
+  const R a = p[1] * ir, b = p[2] * ir;
+  s0 = {up ? -a : -r, up ? b : R(0)};
+  s1 = {up ? r : a, up ? R(0) : b};
 }
 
 // J^mu = a^dagger sigma-bar^mu b (contravariant components)
@@ -340,7 +388,7 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const R
   const R MW2 = static_cast<R>(c.M2), MWGW = static_cast<R>(c.MG), gs = static_cast<R>(c.gs);
   // g/sqrt2 / (m^2 - MW^2 + i MW GW)
   const R dp = mp2 - MW2, dm = mm2 - MW2;
-  const R np = gs / (dp * dp + MWGW * MWGW), nm = gs / (dm * dm + MWGW * MWGW);
+  const R np = gs * rcp_nr(dp * dp + MWGW * MWGW), nm = gs * rcp_nr(dm * dm + MWGW * MWGW);
   const cx<R> cp = {dp * np, -MWGW * np}, cm = {dm * nm, -MWGW * nm};
   cx<R> ep[4], em[4];
   R qp[4], qm[4], Ppq[4], Pmq[4], dq[4];
@@ -391,11 +439,12 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const R
   const cx<R> Tu = chain01(em, ku, b00u, b11u, ep);
   const cx<R> Td = chain01(ep, kd, b00d, b11d, em);
   const R ct = static_cast<R>(c.ct);
-  const R fu = -rs * ct / tu, fd = -rs * ct / td;
+  const R rsct = -rs * ct;
+  const R fu = rsct * rcp_nr(tu), fd = rsct * rcp_nr(td);
   double cre[2], cim[2], csR2 = c.csR2;  // s-channel photon + Z, left-handed quark, [q]
   if constexpr (HAD) {
     // e^2 Q / shat + e^2 f (shat - MZ^2 - i MZ GZ) / |shat - MZ^2 + i MZ GZ|^2
-    const double dr = hd.sh - c.mz2, idd = 1.0 / (dr * dr + c.mzgz * c.mzgz), ish = 1.0 / hd.sh;
+    const double dr = hd.sh - c.mz2, idd = rcp_nr(dr * dr + c.mzgz * c.mzgz), ish = rcp_nr(hd.sh);
     csR2 = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -417,11 +466,11 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const R
   return cabs2(MuL) + cabs2(MdL) + static_cast<R>(csR2) * cabs2(AR);
 }
 
-// rest frame of Q (mass m) -> frame of Q, for k and its back-to-back partner
+// rest frame of Q (mass m, im = 1 / m) -> frame of Q, for k and its back-to-back partner
 template <typename R>
-__device__ __forceinline__ void boost_pair(const R Q[4], R m, const R k[4], R a[4], R b[4]) {
+__device__ __forceinline__ void boost_pair(const R Q[4], R m, R im, const R k[4], R a[4], R b[4]) {
   const R qk = Q[1] * k[1] + Q[2] * k[2] + Q[3] * k[3];
-  const R im = R(1) / m, iqm = R(1) / (Q[0] + m);
+  const R iqm = rcp_nr(Q[0] + m);
   const R Ea = (Q[0] * k[0] + qk) * im;
   const R Eb = (Q[0] * k[0] - qk) * im;
   const R fa = (k[0] + Ea) * iqm, fb = (k[0] + Eb) * iqm;
@@ -434,7 +483,19 @@ __device__ __forceinline__ void boost_pair(const R Q[4], R m, const R k[4], R a[
   }
 }
 
-__device__ __forceinline__ void sincos_2pi(double x, double& s, double& c) { sincospi(2.0 * x, &s, &c); }
+// sin and cos of 2 pi x for 0 <= x <= 1: x = q/4 + r with q = rint(4 x) and |r| <= 1/8
+// (r exact: x and q/4 are within a factor 2 of each other when q > 0), y = 2 pi r, then
+// the rotation by q quarter turns
+__device__ __forceinline__ void sincos_2pi(double x, double& s, double& c) {
+  const double q = rint(4.0 * x);
+  const double y = (x - 0.25 * q) * 6.283185307179586477;
+  double sn, cs;
+  sincos_taylor(y, sn, cs);
+  const int qi = static_cast<int>(q) & 3;
+  const double a = (qi & 1) ? cs : sn, b = (qi & 1) ? sn : cs;
+  s = qi >= 2 ? -a : a;
+  c = (qi == 1 || qi == 2) ? -b : b;
+}
 __device__ __forceinline__ void sincos_2pi(float x, float& s, float& c) { sincospif(2.0f * x, &s, &c); }
 
 // WW_4L: x0 -> m+^2 (BW on [0, shat]), x1 -> m-^2 (BW on [0, (rs - m+)^2]),
@@ -459,8 +520,8 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     }
     const double tau = exp(L);
     sh = tau * c.S;
-    rs = sqrt(sh);
-    rho_rng = atan((sh - c.M2) / c.MG) - c.rho_lo;
+    rs = sqrt_nr(sh);
+    rho_rng = atan((sh - c.M2) * c.invMG) - c.rho_lo;
     lum = 2.0 * (tau * c.Ldiff) * (-L) * pdf_pair(c, tau, L, expm1(l1) * expm1(l2));
     hd.rs = rs;
     hd.sh = sh;
@@ -469,39 +530,41 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
   const double mp2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rho_rng, jp);
   obs_sq = mp2 > 0.0 ? mp2 : 0.0;
   if (!(mp2 > 0.0)) return 0.0;
-  const double mp = sqrt(mp2);
+  double mp, imp;
+  sqrt_rsqrt_nr(mp2, mp, imp);
   const double up = (rs - mp) * (rs - mp);
-  const double rrng2 = atan((up - c.M2) / c.MG) - c.rho_lo;
+  const double rrng2 = atan((up - c.M2) * c.invMG) - c.rho_lo;
   const double mm2 = bw_map(x[1], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rrng2, jm);
   if (!(mm2 > 0.0)) return 0.0;
-  const double mm = sqrt(mm2);
+  double mm, imm;
+  sqrt_rsqrt_nr(mm2, mm, imm);
   const double lam = (sh - mp2 - mm2) * (sh - mp2 - mm2) - 4.0 * mp2 * mm2;
   if (!(lam > 0.0)) return 0.0;
-  const double sl = sqrt(lam);
-  const double i2rs = 1.0 / (2.0 * rs);
+  const double sl = sqrt_nr(lam);
+  const double i2rs = HAD ? 0.5 * rcp_nr(rs) : 1.0 / (2.0 * rs);
   const double q = sl * i2rs;
   const double Ep = (sh + mp2 - mm2) * i2rs, Em = (sh - mp2 + mm2) * i2rs;
-  const double ct = 2.0 * x[2] - 1.0, st = sqrt((1.0 - ct) * (1.0 + ct));
+  const double ct = 2.0 * x[2] - 1.0, st = sqrt_nr((1.0 - ct) * (1.0 + ct));
   double sf, cf;
   sincos_2pi(x[3], sf, cf);
   const double qp[4] = {Ep, q * st * cf, q * st * sf, q * ct};
   const double qm[4] = {Em, -qp[1], -qp[2], -qp[3]};
   double d3[4], d4[4], d5[4], d6[4];
   {
-    const double c3 = 2.0 * x[4] - 1.0, s3 = sqrt((1.0 - c3) * (1.0 + c3));
+    const double c3 = 2.0 * x[4] - 1.0, s3 = sqrt_nr((1.0 - c3) * (1.0 + c3));
     double s, cc;
     sincos_2pi(x[5], s, cc);
     const double h = 0.5 * mp;
     const double k[4] = {h, h * s3 * cc, h * s3 * s, h * c3};
-    boost_pair<double>(qp, mp, k, d3, d4);
+    boost_pair<double>(qp, mp, imp, k, d3, d4);
   }
   {
-    const double c5 = 2.0 * x[6] - 1.0, s5 = sqrt((1.0 - c5) * (1.0 + c5));
+    const double c5 = 2.0 * x[6] - 1.0, s5 = sqrt_nr((1.0 - c5) * (1.0 + c5));
     double s, cc;
     sincos_2pi(x[7], s, cc);
     const double h = 0.5 * mm;
     const double k[4] = {h, h * s5 * cc, h * s5 * s, h * c5};
-    boost_pair<double>(qm, mm, k, d5, d6);
+    boost_pair<double>(qm, mm, imm, k, d5, d6);
   }
   R p3[4], p4[4], p5[4], p6[4];
 #pragma unroll
@@ -520,8 +583,8 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     // E -+ q cos = m^2 / (E + q) + q (1 -+ cos) for the W+ (and with cos -> -cos for the W-)
     const double qd = sl * i2rs, Epd = (sh + mp2 - mm2) * i2rs, Emd = (sh - mp2 + mm2) * i2rs;
     const double cd = 2.0 * x[2] - 1.0;
-    const double epm = mp2 / (Epd + qd) + qd * (1.0 - cd);  // Ep - q cos
-    const double emm = mm2 / (Emd + qd) + qd * (1.0 + cd);  // Em + q cos
+    const double epm = div_nr(mp2, Epd + qd) + qd * (1.0 - cd);  // Ep - q cos
+    const double emm = div_nr(mm2, Emd + qd) + qd * (1.0 + cd);  // Em + q cos
     ExchInv<R> iv;
     iv.tu = static_cast<R>(mp2 - rs * epm);
     iv.td = static_cast<R>(mm2 - rs * emm);
@@ -535,11 +598,13 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     me = static_cast<double>(
         ww_me2<R, HAD>(c, hd, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
   }
-  // dPhi_2(P) (4 pi) * dm+^2/(2 pi) * dm-^2/(2 pi) * [dPhi_2(W) (4 pi)]^2
-  const double jac = sl / (8.0 * kPi * sh) * (jp / (2.0 * kPi)) * (jm / (2.0 * kPi)) *
-                     (1.0 / (64.0 * kPi * kPi));
-  if constexpr (HAD) return c.conv * (0.5 / sh) * (1.0 / 12.0) * me * jac * lum;
-  return c.conv * (0.5 / sh) * (1.0 / 12.0) * me * jac;
+  // dPhi_2(P) (4 pi) = sl / (8 pi shat), dm+^2/(2 pi), dm-^2/(2 pi), [dPhi_2(W) (4 pi)]^2 =
+  // 1 / (64 pi^2), flux 1 / (2 shat), colour and spin average 1/12: one constant over shat^2
+  constexpr double kPS = 0.5 / (12.0 * 8.0 * kPi * 4.0 * kPi * kPi * 64.0 * kPi * kPi);
+  const double ish = HAD ? rcp_nr(sh) : 1.0 / sh;
+  const double w = (c.conv * kPS) * (ish * ish) * (sl * me) * (jp * jm);
+  if constexpr (HAD) return w * lum;
+  return w;
 }
 
 }  // namespace vg

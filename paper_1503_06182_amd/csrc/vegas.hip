@@ -42,11 +42,18 @@ constexpr int kWave = 64;
 constexpr int kMaxRowsEvent = 1 << 16;  // cap on event-kernel blocks
 constexpr int kMaxRowsAcc = 1024;       // cap on accumulation blocks (rows of the digit partials)
 
-// row stride of the digit partials: the ncol = 3 (2 + D n) columns padded to a whole
+// digit columns of an iteration's exact sums: S1 = sum w in kD1 digits, then S2 = sum
+// w^2 and each grid-histogram slot (dimension d, bin b: slot d n + b) in kD2 digits
+constexpr int kD1 = 3, kD2 = 4;
+constexpr int kColS2 = kD1;             // first column of S2
+constexpr int kColHist = kD1 + kD2;     // first column of the grid histogram
+__host__ __device__ constexpr int hist_col(int slot) { return kColHist + kD2 * slot; }
+__host__ __device__ constexpr int hist_cols(int nslot) { return kColHist + kD2 * nslot; }
+// row stride of the digit partials: the ncol = 7 + 4 D n columns padded to a whole
 // number of 32-column (256-byte) tiles, so that every tile the column reduction reads
 // is aligned to the 128-byte lines it is fetched in
 __host__ __device__ constexpr int part_ld(int ncol) { return (ncol + 31) & ~31; }
-constexpr int kFusedLdsMax = 48 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
+constexpr int kFusedLdsMax = 64 * 1024; // LDS of an event block (grid + digits) that allows the fused fold
 // observable histogram: bins 1..nobs uniform on [lo, hi), 0 = underflow, nobs + 1 = overflow
 constexpr int kObsLd = VEGAS_MAX_OBS_BINS + 2;
 constexpr int kStrataBlocks = 1024;  // blocks of the hypercube fold (rows of its partials)
@@ -65,7 +72,9 @@ inline UDiv udiv_magic(uint32_t d) {
 __device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv q) {
   return static_cast<uint32_t>((static_cast<unsigned long long>(n) * q.M) >> q.s);
 }
-__host__ __device__ constexpr int obs_cols(int nobs) { return nobs > 0 ? 6 * (nobs + 2) : 0; }
+// observable bin k: the digits of sum w at column 7 k, those of sum w^2 at 7 k + 3
+constexpr int kObsW = kD1 + kD2;
+__host__ __device__ constexpr int obs_cols(int nobs) { return nobs > 0 ? kObsW * (nobs + 2) : 0; }
 
 struct DevBufs {
   double* edges;                 // [D][n+1] current grid
@@ -162,61 +171,76 @@ __device__ __forceinline__ int obs_bin(double o, double lo, double hi, double sc
 
 // ---------------------------------------------------------------------------
 // exact accumulation of one event: S1 = sum w and S2 = sum w^2 in per-lane
-// registers, d[dim][bin] = sum w^2 in LDS (3 integer digits per slot); the
+// registers, d[dim][bin] = sum w^2 in LDS (4 integer digits per slot); the
 // digits are taken at scales fixed for the whole iteration, so every partition
 // of the events gives the same integer totals
 // ---------------------------------------------------------------------------
+constexpr int kLane = kD1 + kD2;  // per-lane digit sums: S1, then S2
 struct LaneSums {
-  long long v[6];
+  long long v[kLane];
 };
 
 __device__ __forceinline__ void lane_sums_zero(LaneSums& ls) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) ls.v[k] = 0;
+  for (int k = 0; k < kLane; ++k) ls.v[k] = 0;
 }
 
-// S1, S2 digits of w; returns the digits of w (d) and of w^2 (h) for the histograms
-__device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls, long long& d0, long long& d1,
-                                         long long& d2, long long& h0, long long& h1, long long& h2) {
-  fx_digits(w, E1, d0, d1, d2);
-  ls.v[0] += d0;
-  ls.v[1] += d1;
-  ls.v[2] += d2;
-  fx_digits_pos(w * w, E2, h0, h1, h2);  // w^2 of a finite weight: >= 0
-  ls.v[3] += h0;
-  ls.v[4] += h1;
-  ls.v[5] += h2;
+// the digits of one event: w (d, kD1) and w^2 (h, kD2)
+struct EvDigits {
+  long long d[kD1], h[kD2];
+};
+
+// S1, S2 digits of w; returns the digits of w and of w^2 for the histograms.
+// NONNEG: the process's weights are never negative (cross sections, the Gaussian), so the
+// digits of w need no sign handling
+template <bool NONNEG>
+__device__ __forceinline__ void acc_sums(double w, int E1, int E2, LaneSums& ls, EvDigits& g) {
+  if constexpr (NONNEG) fx_digits_pos(w, E1, g.d[0], g.d[1], g.d[2]);
+  else fx_digits(w, E1, g.d[0], g.d[1], g.d[2]);
+  fx2_digits(w * w, E2, g.h);  // w^2 of a finite weight: >= 0
+#pragma unroll
+  for (int k = 0; k < kD1; ++k) ls.v[k] += g.d[k];
+#pragma unroll
+  for (int k = 0; k < kD2; ++k) ls.v[kD1 + k] += g.h[k];
 }
 
-// the digits are added whether or not they are zero: a branch around each atomic cost
-// more (2 % of the W+ and W+W- event kernels) than the atomics it saved
-__device__ __forceinline__ void acc_hist(long long* acc, int col, long long h0, long long h1, long long h2) {
-  unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + col);
-  atomicAdd(p + 0, static_cast<unsigned long long>(h0));
-  atomicAdd(p + 1, static_cast<unsigned long long>(h1));
-  atomicAdd(p + 2, static_cast<unsigned long long>(h2));
+// the top digit of w^2 is zero unless this iteration's w^2 came within 2^-32 of the
+// scale (the scale sits 2^32 above the previous iteration's largest): the histogram
+// adds it only when some active lane of the wave has it (a wave-uniform test; adding
+// zero changes nothing, so the totals are the same either way)
+__device__ __forceinline__ bool top_digit_needed(const EvDigits& g) { return __ballot(g.h[3] != 0) != 0ull; }
+
+// the digits are added whether or not they are zero (but the top digit, see
+// top_digit_needed): a branch around each atomic cost more (2 % of the W+ and W+W- event
+// kernels) than the atomics it saved.  The LDS byte offset is formed in 32 bits
+__device__ __forceinline__ unsigned long long* lds_col(long long* acc, int col) {
+  return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(acc) + static_cast<uint32_t>(col) * 8u);
+}
+
+__device__ __forceinline__ void acc_hist(long long* acc, int col, const EvDigits& g, bool top) {
+  unsigned long long* p = lds_col(acc, col);
+  atomicAdd(p + 0, static_cast<unsigned long long>(g.h[0]));
+  atomicAdd(p + 1, static_cast<unsigned long long>(g.h[1]));
+  atomicAdd(p + 2, static_cast<unsigned long long>(g.h[2]));
+  if (top) atomicAdd(p + 3, static_cast<unsigned long long>(g.h[3]));
 }
 
 // observable bin: the digits of w, then those of w^2
-__device__ __forceinline__ void acc_obs(long long* acc, int col, long long d0, long long d1, long long d2,
-                                       long long h0, long long h1, long long h2) {
-  unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + col);
-  atomicAdd(p + 0, static_cast<unsigned long long>(d0));
-  atomicAdd(p + 1, static_cast<unsigned long long>(d1));
-  atomicAdd(p + 2, static_cast<unsigned long long>(d2));
-  atomicAdd(p + 3, static_cast<unsigned long long>(h0));
-  atomicAdd(p + 4, static_cast<unsigned long long>(h1));
-  atomicAdd(p + 5, static_cast<unsigned long long>(h2));
+__device__ __forceinline__ void acc_obs(long long* acc, int col, const EvDigits& g, bool top) {
+  unsigned long long* p = lds_col(acc, col);
+#pragma unroll
+  for (int k = 0; k < kD1; ++k) atomicAdd(p + k, static_cast<unsigned long long>(g.d[k]));
+  acc_hist(acc, col + kD1, g, top);
 }
 
-// per-lane S1, S2 -> wave butterfly -> LDS columns 0..5 (call with the whole block)
+// per-lane S1, S2 -> wave butterfly -> LDS columns 0 .. kLane - 1 (call with the whole block)
 __device__ __forceinline__ void acc_sums_to_lds(LaneSums& ls, long long* acc) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) ls.v[k] = wave_sum_i64(ls.v[k]);
+  for (int k = 0; k < kLane; ++k) ls.v[k] = wave_sum_i64(ls.v[k]);
   if ((threadIdx.x & 63) == 0) {
     unsigned long long* p = reinterpret_cast<unsigned long long*>(acc);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) atomicAdd(p + k, static_cast<unsigned long long>(ls.v[k]));
+    for (int k = 0; k < kLane; ++k) atomicAdd(p + k, static_cast<unsigned long long>(ls.v[k]));
   }
 }
 
@@ -268,7 +292,7 @@ template <int PROC, int PREC, int D, int MAXT, bool EXT = false, bool FUSED = fa
 __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) void k_event(EventArgs a) {
   extern __shared__ unsigned char smem[];
   const int n = a.nbins, nd = D > 0 ? D : a.ndim;
-  const int ncol_h = 3 * (2 + nd * n);
+  const int ncol_h = hist_cols(nd * n);
   const int ncol = ncol_h + (OBS ? obs_cols(a.nobs) : 0);
   double* e_lds = reinterpret_cast<double*>(smem);
   long long* acc = reinterpret_cast<long long*>(e_lds + nd * (n + 1));  // FUSED: [ncol]
@@ -279,10 +303,10 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
   // integrand, so the lane's S1, S2 digit sums live in LDS, one private slot per lane
   // and digit (no atomics: no other lane touches it) instead of 12 registers
   constexpr bool kLdsSums = FUSED && D >= 10 && MAXT == 256;
-  long long* lsum = acc + ncol;  // kLdsSums: [6][256]
+  long long* lsum = acc + ncol;  // kLdsSums: [kLane][256]
   if constexpr (kLdsSums)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) lsum[k * 256 + threadIdx.x] = 0;
+    for (int k = 0; k < kLane; ++k) lsum[k * 256 + threadIdx.x] = 0;
   if (blockIdx.x == 0) {
     // clear this iteration's digit totals (the previous iteration's were consumed
     // by its finalisation, earlier on the stream)
@@ -375,23 +399,24 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
     wmax = wb > wmax ? wb : wmax;
     if constexpr (FUSED) {
       if (w != 0.0) {
-        long long d0, d1, d2, h0, h1, h2;
+        EvDigits g;
         if constexpr (kLdsSums) {
           LaneSums t;
           lane_sums_zero(t);
-          acc_sums(w, E1, E2, t, d0, d1, d2, h0, h1, h2);
+          acc_sums<PROC != VEGAS_GENZ>(w, E1, E2, t, g);
 #pragma unroll
-          for (int k = 0; k < 6; ++k) lsum[k * 256 + threadIdx.x] += t.v[k];
+          for (int k = 0; k < kLane; ++k) lsum[k * 256 + threadIdx.x] += t.v[k];
         } else {
-          acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
+          acc_sums<PROC != VEGAS_GENZ>(w, E1, E2, ls, g);
         }
+        const bool top = top_digit_needed(g);
 #pragma unroll
         for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
           if (d >= nd) break;
           const int bin = kEarlyBins ? static_cast<int>((bw[d >> 2] >> (8 * (d & 3))) & 0xffu) : bins[d];
-          acc_hist(acc, 3 * (2 + d * n + bin), h0, h1, h2);
+          acc_hist(acc, hist_col(d * n + bin), g, top);
         }
-        if constexpr (OBS) acc_obs(acc, ncol_h + 6 * obin, d0, d1, d2, h0, h1, h2);
+        if constexpr (OBS) acc_obs(acc, ncol_h + kObsW * obin, g, top);
       }
     }
   }
@@ -409,7 +434,7 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
   }
   if constexpr (kLdsSums)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ls.v[k] = lsum[k * 256 + threadIdx.x];
+    for (int k = 0; k < kLane; ++k) ls.v[k] = lsum[k * 256 + threadIdx.x];
   if constexpr (FUSED) acc_sums_to_lds(ls, acc);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -790,16 +815,17 @@ struct AccArgs {
 
 __global__ void k_accum(AccArgs a) {
   extern __shared__ unsigned char smem[];
-  const int n = a.nbins, nd = a.ndim, ncol_h = 3 * (2 + nd * n);
+  const int n = a.nbins, nd = a.ndim, ncol_h = hist_cols(nd * n);
   const int ncol = ncol_h + obs_cols(a.nobs);
   const int dlo = blockIdx.y * a.dims_per_group;
   const int dhi = min(nd, dlo + a.dims_per_group);
-  const int lcol = 3 * (2 + (dhi - dlo) * n);
+  const int lcol = hist_cols((dhi - dlo) * n);
   const int ocol = blockIdx.y == 0 ? obs_cols(a.nobs) : 0;  // block-uniform
   // [lcol]: S1, S2, d of the group's dimensions; then [ocol]: the observable's bins
   long long* acc = reinterpret_cast<long long*>(smem);
   for (int i = threadIdx.x; i < lcol + ocol; i += blockDim.x) acc[i] = 0;
-  // one scale per quantity: 2^(94 - E) with |w| < 2^E1 and w^2 < 2^E2 for every event
+  // one scale per quantity: 2^(94 - E1) for w and 2^(126 - E2) for w^2, with |w| < 2^E1
+  // and w^2 < 2^E2 for every event
   const double wmax = __longlong_as_double(static_cast<long long>(a.b.maxw[0]));
   const int E1 = fx_exponent(wmax);
   const int E2 = fx_exponent(wmax * wmax);
@@ -811,35 +837,36 @@ __global__ void k_accum(AccArgs a) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
     const double w = a.b.rec_w[i];
     if (w == 0.0) continue;
-    long long d0, d1, d2, h0, h1, h2;
-    acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
+    EvDigits g;
+    acc_sums<false>(w, E1, E2, ls, g);
     // the same digits of w^2 go to the event's bin in every dimension
     for (int d = dlo; d < dhi; ++d) {
       const uint32_t word = a.b.rec_bins[(d >> 2) * a.stride_rec + i];
       const int bin = static_cast<int>((word >> (8 * (d & 3))) & 0xffu);
-      acc_hist(acc, 3 * (2 + (d - dlo) * n + bin), h0, h1, h2);
+      acc_hist(acc, hist_col((d - dlo) * n + bin), g, true);
     }
-    if (ocol) acc_obs(acc, lcol + 6 * static_cast<int>(a.b.rec_obs[i]), d0, d1, d2, h0, h1, h2);
+    if (ocol) acc_obs(acc, lcol + kObsW * static_cast<int>(a.b.rec_obs[i]), g, true);
   }
   acc_sums_to_lds(ls, acc);
   __syncthreads();
   long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * part_ld(ncol);
   if (blockIdx.y == 0)
-    for (int i = threadIdx.x; i < 6; i += blockDim.x) row[i] = acc[i];
-  for (int i = threadIdx.x; i < lcol - 6; i += blockDim.x) row[3 * (2 + dlo * n) + i] = acc[6 + i];
+    for (int i = threadIdx.x; i < kColHist; i += blockDim.x) row[i] = acc[i];
+  for (int i = threadIdx.x; i < lcol - kColHist; i += blockDim.x) row[hist_col(dlo * n) + i] = acc[kColHist + i];
   for (int i = threadIdx.x; i < ocol; i += blockDim.x) row[ncol_h + i] = acc[lcol + i];
 }
 
 // ---------------------------------------------------------------------------
 // K3: digit totals -> doubles (d, S1, S2), then I_j and var_j.  One block.
 // After a fused fold, the scales of the previous iteration are kept only while
-// this iteration's max |w| lies in [2^(E1 - kFxLow), 2^E1); otherwise the block
+// this iteration's max |w| lies in [2^(E1 - kFxLow), 2^E1) and its max w^2 in
+// [2^(E2 - kFxLow), 2^E2); otherwise the block
 // re-folds every record at this iteration's own scales (same totals as the
 // two-pass fold).  It then fixes the next iteration's scales and clears the
 // iteration's max |w| and counters.
 // ---------------------------------------------------------------------------
 constexpr int kFxHead = 16;  // next scale: 2^16 above this iteration's max |w|
-constexpr int kFxLow = 40;   // the fused scale is kept down to 2^-40 of itself (>= 54 bits per event)
+constexpr int kFxLow = 40;   // the fused scales are kept down to 2^-40 of themselves (>= 54 bits per event)
 
 struct FinArgs {
   DevBufs b;
@@ -886,15 +913,18 @@ template <bool OBS>
 __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* smem) {
   __shared__ double s12[2];
   const DevBufs& b = f.b;
-  const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol_h = 3 * (2 + nslot);
+  const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol_h = hist_cols(nslot);
   const int ncol = ncol_h + (OBS ? obs_cols(f.nobs) : 0);
   const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
   const unsigned long long nz = b.cnt[0], nnf = b.cnt[1];
   const int Ec1 = fx_exponent(wmax), Ec2 = fx_exponent(wmax * wmax);
   int E1 = Ec1, E2 = Ec2, fold = 0;
   if (f.fused) {
-    const int Ef = b.fxs[1];
-    if (Ec1 > Ef || Ec1 < Ef - kFxLow) {
+    // the scales are kept while this iteration's max |w| is below 2^Ef and neither w nor
+    // w^2 lost more than kFxLow bits of headroom: w^2 is folded at 2 Ef, so its headroom
+    // shrinks twice as fast as that of w
+    const int Ef = b.fxs[1], E2f = b.fxs[2];
+    if (Ec1 > Ef || Ec1 < Ef - kFxLow || Ec2 < E2f - kFxLow) {
       fold = 2;
     } else {
       fold = 1;
@@ -916,20 +946,20 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     for (int64_t i = threadIdx.x; i < f.nev; i += blockDim.x) {
       const double w = b.rec_w[i];
       if (w == 0.0) continue;
-      long long d0, d1, d2, h0, h1, h2;
-      acc_sums(w, E1, E2, ls, d0, d1, d2, h0, h1, h2);
+      EvDigits g;
+      acc_sums<false>(w, E1, E2, ls, g);
       for (int d = 0; d < nd; ++d) {
         const uint32_t word = b.rec_bins[(d >> 2) * f.stride_rec + i];
-        acc_hist(acc, 3 * (2 + d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), h0, h1, h2);
+        acc_hist(acc, hist_col(d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), g, true);
       }
-      if constexpr (OBS) acc_obs(acc, ncol_h + 6 * static_cast<int>(b.rec_obs[i]), d0, d1, d2, h0, h1, h2);
+      if constexpr (OBS) acc_obs(acc, ncol_h + kObsW * static_cast<int>(b.rec_obs[i]), g, true);
     }
     acc_sums_to_lds(ls, acc);
     __syncthreads();
     tot = acc;
   }
-  // observable bins: slot nslot + 2 + 2k holds sum w of bin k (scale E1), the next
-  // one sum w^2 (scale E2); their values go to osm
+  // observable bins: value nslot + 2 + 2k is sum w of bin k (scale E1), the next one
+  // sum w^2 (scale E2); their values go to osm
   double* osm = reinterpret_cast<double*>(smem + f.obs_lds);
   const int nslot_all = nslot + 2 + (OBS ? 2 * (f.nobs + 2) : 0);
   // stratified: the hypercube fold's row sums, per wave (rows strided over the block)
@@ -964,13 +994,14 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     }
   }
   for (int slot = threadIdx.x; slot < nslot_all; slot += blockDim.x) {
-    const long long* t = tot + 3 * slot;
     if (OBS && slot >= nslot + 2) {
       const int so = slot - (nslot + 2);
-      osm[so] = fx_value(t[0], t[1], t[2], (so & 1) ? E2 : E1);
+      const long long* t = tot + ncol_h + kObsW * (so >> 1);
+      osm[so] = (so & 1) ? fx2_value(t[kD1], t[kD1 + 1], t[kD1 + 2], t[kD1 + 3], E2) : fx_value(t[0], t[1], t[2], E1);
       continue;
     }
-    const double v = fx_value(t[0], t[1], t[2], slot == 0 ? E1 : E2);
+    const long long* t = tot + (slot == 0 ? 0 : slot == 1 ? kColS2 : hist_col(slot - 2));
+    const double v = slot == 0 ? fx_value(t[0], t[1], t[2], E1) : fx2_value(t[0], t[1], t[2], t[3], E2);
     const int h = slot < 2 ? nslot + slot : slot - 2;
     b.hist[h] = v;
     if (slot < 2) s12[slot] = v;
@@ -1290,7 +1321,7 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.cnt = take(sizeof(unsigned long long) * 2);
   L.fxs = take(sizeof(int) * 4);
   // digit columns for the largest observable histogram
-  const int ncol_max = 3 * (2 + D * n) + obs_cols(VEGAS_MAX_OBS_BINS);
+  const int ncol_max = hist_cols(D * n) + obs_cols(VEGAS_MAX_OBS_BINS);
   L.part_acc = take(sizeof(long long) * kMaxRowsAcc * part_ld(ncol_max));
   L.acc_tot = take(sizeof(long long) * ncol_max);
   L.hist = take(sizeof(double) * (D * n + 2));
@@ -1731,15 +1762,15 @@ void configure_lds(vegas_state* h) {
   const int ocol = obs_cols(h->nobs);
   // histogram dimensions per k_accum block: as many as fit in the block's LDS
   // (the y == 0 blocks also hold S1, S2 and the observable's bins)
-  const size_t per_dim = sizeof(long long) * 3 * n;
-  int dpg = static_cast<int>((smem - sizeof(long long) * (6 + ocol)) / per_dim);
+  const size_t per_dim = sizeof(long long) * kD2 * n;
+  int dpg = static_cast<int>((smem - sizeof(long long) * (kColHist + ocol)) / per_dim);
   dpg = dpg < 1 ? 1 : (dpg > D ? D : dpg);
   h->acc_dpg = dpg;
   h->acc_groups = (D + dpg - 1) / dpg;
-  h->acc_lds = static_cast<int>(sizeof(long long) * (6 + 3 * dpg * n + ocol));
-  const int full = static_cast<int>(sizeof(long long) * (3 * (2 + D * n) + ocol));
-  // 10 or more dimensions: the lanes' S1, S2 digit sums also live in LDS ([6][256])
-  h->fused_lds = h->event_lds + full + (D >= 10 ? static_cast<int>(sizeof(long long) * 6 * 256) : 0);
+  h->acc_lds = static_cast<int>(sizeof(long long) * (hist_cols(dpg * n) + ocol));
+  const int full = static_cast<int>(sizeof(long long) * (hist_cols(D * n) + ocol));
+  // 10 or more dimensions: the lanes' S1, S2 digit sums also live in LDS ([7][256])
+  h->fused_lds = h->event_lds + full + (D >= 10 ? static_cast<int>(sizeof(long long) * kLane * 256) : 0);
   h->fused_ok = h->fused_lds <= kFusedLdsMax;
   h->fin_lds = h->fused_ok ? full : 0;
   h->refine_lds = static_cast<int>(sizeof(double) * 4 * D * (n + 1));
@@ -2048,7 +2079,7 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
                           aa);
     VG_HIP(t.done());
   }
-  const int ncol = 3 * (2 + nslot) + obs_cols(h->nobs);
+  const int ncol = hist_cols(nslot) + obs_cols(h->nobs);
   {
     TimedLaunch t(h, 1);
     hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
@@ -2323,28 +2354,30 @@ int vegas_get_weights(vegas_handle h, int64_t first, int64_t n, double* w, uint8
   return VEGAS_OK;
 }
 
-int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_events, uint32_t iteration,
-               double* sigma_dev, double* dsigma_dev) {
+namespace {
+// doubles of adjoint scratch a call needs: the per-tile partials ([ceil(n/64)][6][B]) and
+// the first level of the fixed tree over them
+size_t grad_scratch_doubles(int32_t B, int64_t n_events) {
+  const int64_t ntiles = (n_events + 63) / 64;
+  const int64_t lvl1 = (ntiles + kTreeRows - 1) / kTreeRows;
+  return static_cast<size_t>((ntiles + lvl1) * kGradVals * B);
+}
+
+int grad_check(vegas_handle h, const double* params_dev, int32_t B, int64_t n_events, double* sigma_dev,
+               double* dsigma_dev) {
   if (!h || !params_dev || !sigma_dev || !dsigma_dev) return VEGAS_EINVAL;
   if (h->cfg.process != VEGAS_DY_Z) return VEGAS_EINVAL;
   if (B < 1 || B > kGradMaxPoints || n_events < 1 || n_events >= (int64_t(1) << 31)) return VEGAS_EINVAL;
+  return VEGAS_OK;
+}
+
+// the adjoint's launches with the scratch at buf (>= grad_scratch_doubles(B, n) doubles)
+int grad_launch(vegas_handle h, const double* params_dev, int32_t B, int64_t n_events, uint32_t iteration,
+                double* sigma_dev, double* dsigma_dev, double* buf) {
   const int64_t ntiles = (n_events + 63) / 64;
   const int cols = kGradVals * B;
-  const int64_t lvl1 = (ntiles + kTreeRows - 1) / kTreeRows;
-  const size_t need = static_cast<size_t>((ntiles + lvl1) * cols);
-  if (h->gbuf_doubles < need) {
-    VG_HIP(hipStreamSynchronize(h->stream));
-    if (h->gbuf) VG_HIP(hipFree(h->gbuf));
-    h->gbuf = nullptr;
-    h->gbuf_doubles = 0;
-    if (hipMalloc(&h->gbuf, need * sizeof(double)) != hipSuccess) {
-      h->gbuf = nullptr;
-      return VEGAS_ENOMEM;
-    }
-    h->gbuf_doubles = need;
-  }
-  double* tiles = h->gbuf;
-  double* lvl = h->gbuf + ntiles * cols;
+  double* tiles = buf;
+  double* lvl = buf + ntiles * cols;
   GradArgs ga;
   ga.pc = h->pc;
   ga.edges = h->b.edges;
@@ -2397,6 +2430,26 @@ int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_ev
   }
   return VEGAS_OK;
 }
+}  // namespace
+
+int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_events, uint32_t iteration,
+               double* sigma_dev, double* dsigma_dev) {
+  const int v = grad_check(h, params_dev, B, n_events, sigma_dev, dsigma_dev);
+  if (v != VEGAS_OK) return v;
+  const size_t need = grad_scratch_doubles(B, n_events);
+  if (h->gbuf_doubles < need) {
+    VG_HIP(hipStreamSynchronize(h->stream));
+    if (h->gbuf) VG_HIP(hipFree(h->gbuf));
+    h->gbuf = nullptr;
+    h->gbuf_doubles = 0;
+    if (hipMalloc(&h->gbuf, need * sizeof(double)) != hipSuccess) {
+      h->gbuf = nullptr;
+      return VEGAS_ENOMEM;
+    }
+    h->gbuf_doubles = need;
+  }
+  return grad_launch(h, params_dev, B, n_events, iteration, sigma_dev, dsigma_dev, h->gbuf);
+}
 
 // checkpoint layout: header {magic, process, ndim, nbins, iter, seed} then edges, history
 namespace {
@@ -2442,6 +2495,8 @@ int vegas_set_state(vegas_handle h, const void* buf, size_t bytes) {
   if (bytes != sizeof(CkptHeader) + sizeof(double) * (ne + nh)) return VEGAS_EINVAL;
   const double* e = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(hd));
   if (hd.fxs[0] != 0 && hd.fxs[0] != 1) return VEGAS_EINVAL;
+  // the scale of w^2 is always twice that of w (a stored pair that disagrees is refused)
+  if (hd.fxs[0] == 1 && hd.fxs[2] != 2 * hd.fxs[1]) return VEGAS_EINVAL;
   VG_HIP(hipMemcpyAsync(h->b.edges, e, sizeof(double) * ne, hipMemcpyHostToDevice, h->stream));
   if (nh) VG_HIP(hipMemcpyAsync(h->b.history, e + ne, sizeof(double) * nh, hipMemcpyHostToDevice, h->stream));
   VG_HIP(hipMemcpyAsync(h->b.fxs, hd.fxs, sizeof(hd.fxs), hipMemcpyHostToDevice, h->stream));
