@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_dy_grad(GradArgs a) {
           }
         }
         double jbw;
-        m2 = bw_map(xx[0], a.pc.M2, a.pc.MG, a.pc.invMG, a.pc.m2lo, a.pc.tlo, a.pc.rho_lo, a.pc.rho_rng, jbw);
+        m2 = bw_map(a.pc, xx[0], a.pc.rho_rng, jbw);
         double L, l1, l2;
         {
 #pragma clang fp contract(off)

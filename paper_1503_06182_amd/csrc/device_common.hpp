@@ -6,6 +6,13 @@
 
 namespace vg {
 
+// a value held in a scalar register that the compiler must treat as rewritten at this
+// point (so it is not hoisted across it); a host build of these headers that only
+// counts arithmetic defines it away
+#ifndef VG_OPAQUE_SGPR
+#define VG_OPAQUE_SGPR(x) asm volatile("" : "+s"(x))
+#endif
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Every event owns its
 // counter (event index, iteration, call), so the set of events of an iteration
@@ -56,7 +63,8 @@ __device__ __forceinline__ void event_uniforms(uint64_t seed, uint32_t it, uint6
   // the compiler from hoisting the ten round keys out of the event loop (twenty scalar
   // registers held across the integrand, spilled and read back lane by lane); formed
   // here they cost eighteen scalar additions per event, off the vector pipeline
-  asm volatile("" : "+s"(k0), "+s"(k1));
+  VG_OPAQUE_SGPR(k0);
+  VG_OPAQUE_SGPR(k1);
   const int nd = D > 0 ? D : ndim;
 #pragma unroll
   for (int k = 0; k < (D > 0 ? (D + 1) / 2 : 8); ++k) {

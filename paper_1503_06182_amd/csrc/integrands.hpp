@@ -23,6 +23,10 @@ struct PhysConst {
   double conv;                // (hbar c)^2 in pb GeV^2
   // Breit-Wigner mapping of the first resonance: m^2 = M2 + MG tan(rho_lo + x rho_rng)
   double M2, MG, invMG, rho_lo, rho_rng, m2lo, tlo;
+  // uniform products formed once on the host (the same roundings as in the kernels'
+  // expressions), so that no per-thread copy of them takes vector registers: MG^2,
+  // MG (1 + tlo^2), (MZ GZ)^2
+  double MG2, MGt, mzgz2;
   double invS;                // 1 / S (hadronic)
   double pdfA, pdfa, pdfb;
   int pdf_pow;                // 1: a = a2/2 with integer a2 in [-8, 8] and integer b in [0, 16]
@@ -103,18 +107,19 @@ __device__ __forceinline__ double tan_halfpi(double x) {
 // ---------------------------------------------------------------------------
 // mappings (rounding kept as in their plain definitions: no contraction)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double bw_map(double r, double M2, double MG, double invMG, double m2lo, double tlo,
-                                         double rlo, double rrng, double& jac) {
+// m^2 = M^2 + M G tan(rho_lo + r rrng) on the process's window (lower edge m2lo,
+// rho_lo = atan(tlo)); jac = dm^2/dr
+__device__ __forceinline__ double bw_map(const PhysConst& c, double r, double rrng, double& jac) {
 #pragma clang fp contract(off)
-  const double rho = rlo + r * rrng;
+  const double rho = c.rho_lo + r * rrng;
   // below the pole the mass is measured from the window's lower edge (tangent
   // addition theorem), free of the cancellation in M^2 + M G tan(rho) as m^2 -> m2lo;
   // one tangent per event either way (no divergent second call)
   const bool below = rho < 0.0;
   const double t = tan_halfpi(below ? r * rrng : rho);
-  const double m2 = below ? m2lo + MG * (1.0 + tlo * tlo) * t * rcp_nr(1.0 - tlo * t) : M2 + MG * t;
-  const double dm = m2 - M2;
-  jac = rrng * (dm * dm + MG * MG) * invMG;
+  const double m2 = below ? c.m2lo + c.MGt * t * rcp_nr(1.0 - c.tlo * t) : c.M2 + c.MG * t;
+  const double dm = m2 - c.M2;
+  jac = rrng * (dm * dm + c.MG2) * c.invMG;
   return m2;
 }
 
@@ -209,7 +214,7 @@ __device__ __forceinline__ double f_eemumu(const PhysConst& c, const double* x) 
 // obs_sq: the square of the observable, the lepton-pair mass m_ll^2
 __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x, double& obs_sq) {
   double jbw;
-  const double m2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  const double m2 = bw_map(c, x[0], c.rho_rng, jbw);
   obs_sq = m2;
   double L, l1, l2;
   {
@@ -224,7 +229,7 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x, doub
   const double cs = 2.0 * x[2] - 1.0;
   // 1 / (shat - MZ^2 + i MZ GZ)
   const double ds = m2 - c.mz2;
-  const double den = rcp_nr(ds * ds + c.mzgz * c.mzgz);
+  const double den = rcp_nr(ds * ds + c.mzgz2);
   const double pre = ds * den, pim = -c.mzgz * den;
   const double inv_s = rcp_nr(m2);
   double sum = 0.0;
@@ -250,7 +255,7 @@ __device__ __forceinline__ double f_dy(const PhysConst& c, const double* x, doub
 // obs_sq: the square of the observable, the e+ transverse momentum (taken before the cuts)
 __device__ __forceinline__ double f_w(const PhysConst& c, const double* x, double& obs_sq) {
   double jbw;
-  const double m2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, c.rho_rng, jbw);
+  const double m2 = bw_map(c, x[0], c.rho_rng, jbw);
   double L, l1, l2;
   {
 #pragma clang fp contract(off)
@@ -269,7 +274,7 @@ __device__ __forceinline__ double f_w(const PhysConst& c, const double* x, doubl
   const bool pass = (pt2 > c.ptmin2) && (num * num < c.th2 * dnm * dnm);
   if (!pass) return 0.0;
   const double ds = m2 - c.M2;
-  const double den = ds * ds + c.MG * c.MG;
+  const double den = ds * ds + c.MG2;
   // |M|^2 / (2 shat) = g^4 |V|^2 / 24 * shat^2 (1 + cos^2) / den / (2 shat): one division
   const double me_flux = c.g4v2_24 * (0.5 * m2) * (1.0 + cs * cs) * rcp_nr(den);
   const double ff = pdf_pair(c, m2 * c.invS, L, em1 * em2);
@@ -373,31 +378,41 @@ struct WWHad {
   double rs, sh;
 };
 
-// sum over q in {u, d} and quark helicity of |M|^2 (no averages)
+// the lepton current of one W decay, J = a^dagger sigma-bar b with a, b the
+// helicity-minus spinors of pa, pb (formed as soon as the decay momenta are, so that
+// only the current stays live)
+template <typename R>
+__device__ __forceinline__ void lepton_current(const double pa[4], const double pb[4], cx<R> J[4]) {
+  R a[4], b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    a[i] = static_cast<R>(pa[i]);
+    b[i] = static_cast<R>(pb[i]);
+  }
+  cx<R> a0, a1, b0, b1;
+  spinor_m(a, a0, a1);
+  spinor_m(b, b0, b1);
+  current(a0, a1, b0, b1, J);
+}
+
+// sum over q in {u, d} and quark helicity of |M|^2 (no averages), from the lepton
+// currents Jp = ubar(nu) gamma P_L v(e+), Jm = ubar(mu-) gamma P_L v(nubar) and the W
+// momenta qp, qm
 template <typename R, bool HAD = false>
-__device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const R p3[4], const R p4[4], const R p5[4],
-                                    const R p6[4], R mp2, R mm2, const ExchInv<R>* inv) {
-  cx<R> a3_0, a3_1, a4_0, a4_1, a5_0, a5_1, a6_0, a6_1;
-  spinor_m(p3, a3_0, a3_1);
-  spinor_m(p4, a4_0, a4_1);
-  spinor_m(p5, a5_0, a5_1);
-  spinor_m(p6, a6_0, a6_1);
-  cx<R> Jp[4], Jm[4];
-  current(a4_0, a4_1, a3_0, a3_1, Jp);  // ubar(nu) gamma P_L v(e+)
-  current(a5_0, a5_1, a6_0, a6_1, Jm);  // ubar(mu-) gamma P_L v(nubar)
+__device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const cx<R> Jp[4], const cx<R> Jm[4],
+                                    const R qp[4], const R qm[4], R mp2, R mm2, const ExchInv<R>* inv) {
   const R MW2 = static_cast<R>(c.M2), MWGW = static_cast<R>(c.MG), gs = static_cast<R>(c.gs);
   // g/sqrt2 / (m^2 - MW^2 + i MW GW)
   const R dp = mp2 - MW2, dm = mm2 - MW2;
-  const R np = gs * rcp_nr(dp * dp + MWGW * MWGW), nm = gs * rcp_nr(dm * dm + MWGW * MWGW);
+  const R MG2 = static_cast<R>(c.MG2);
+  const R np = gs * rcp_nr(dp * dp + MG2), nm = gs * rcp_nr(dm * dm + MG2);
   const cx<R> cp = {dp * np, -MWGW * np}, cm = {dm * nm, -MWGW * nm};
   cx<R> ep[4], em[4];
-  R qp[4], qm[4], Ppq[4], Pmq[4], dq[4];
+  R Ppq[4], Pmq[4], dq[4];
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     ep[mu] = cmul(Jp[mu], cp);
     em[mu] = cmul(Jm[mu], cm);
-    qp[mu] = p3[mu] + p4[mu];
-    qm[mu] = p5[mu] + p6[mu];
   }
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
@@ -444,7 +459,7 @@ __device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const R
   double cre[2], cim[2], csR2 = c.csR2;  // s-channel photon + Z, left-handed quark, [q]
   if constexpr (HAD) {
     // e^2 Q / shat + e^2 f (shat - MZ^2 - i MZ GZ) / |shat - MZ^2 + i MZ GZ|^2
-    const double dr = hd.sh - c.mz2, idd = rcp_nr(dr * dr + c.mzgz * c.mzgz), ish = rcp_nr(hd.sh);
+    const double dr = hd.sh - c.mz2, idd = rcp_nr(dr * dr + c.mzgz2), ish = rcp_nr(hd.sh);
     csR2 = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -527,14 +542,14 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     hd.sh = sh;
   }
   double jp, jm;
-  const double mp2 = bw_map(x[0], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rho_rng, jp);
+  const double mp2 = bw_map(c, x[0], rho_rng, jp);
   obs_sq = mp2 > 0.0 ? mp2 : 0.0;
   if (!(mp2 > 0.0)) return 0.0;
   double mp, imp;
   sqrt_rsqrt_nr(mp2, mp, imp);
   const double up = (rs - mp) * (rs - mp);
   const double rrng2 = atan((up - c.M2) * c.invMG) - c.rho_lo;
-  const double mm2 = bw_map(x[1], c.M2, c.MG, c.invMG, c.m2lo, c.tlo, c.rho_lo, rrng2, jm);
+  const double mm2 = bw_map(c, x[1], rrng2, jm);
   if (!(mm2 > 0.0)) return 0.0;
   double mm, imm;
   sqrt_rsqrt_nr(mm2, mm, imm);
@@ -549,14 +564,17 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
   sincos_2pi(x[3], sf, cf);
   const double qp[4] = {Ep, q * st * cf, q * st * sf, q * ct};
   const double qm[4] = {Em, -qp[1], -qp[2], -qp[3]};
-  double d3[4], d4[4], d5[4], d6[4];
+  // each W's decay leptons in the CM frame, turned into its lepton current at once
+  cx<R> Jp[4], Jm[4];
   {
     const double c3 = 2.0 * x[4] - 1.0, s3 = sqrt_nr((1.0 - c3) * (1.0 + c3));
     double s, cc;
     sincos_2pi(x[5], s, cc);
     const double h = 0.5 * mp;
     const double k[4] = {h, h * s3 * cc, h * s3 * s, h * c3};
+    double d3[4], d4[4];
     boost_pair<double>(qp, mp, imp, k, d3, d4);
+    lepton_current<R>(d4, d3, Jp);
   }
   {
     const double c5 = 2.0 * x[6] - 1.0, s5 = sqrt_nr((1.0 - c5) * (1.0 + c5));
@@ -564,15 +582,15 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     sincos_2pi(x[7], s, cc);
     const double h = 0.5 * mm;
     const double k[4] = {h, h * s5 * cc, h * s5 * s, h * c5};
+    double d5[4], d6[4];
     boost_pair<double>(qm, mm, imm, k, d5, d6);
+    lepton_current<R>(d5, d6, Jm);
   }
-  R p3[4], p4[4], p5[4], p6[4];
+  R qpr[4], qmr[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    p3[i] = static_cast<R>(d3[i]);
-    p4[i] = static_cast<R>(d4[i]);
-    p5[i] = static_cast<R>(d5[i]);
-    p6[i] = static_cast<R>(d6[i]);
+    qpr[i] = static_cast<R>(qp[i]);
+    qmr[i] = static_cast<R>(qm[i]);
   }
   const double two = 2.0;
   (void)two;
@@ -593,10 +611,10 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     iv.b00d = static_cast<R>(-emm);
     iv.b11d = static_cast<R>(rs - (Emd - qd * cd));
     me = static_cast<double>(
-        ww_me2<R, HAD>(c, hd, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), &iv));
+        ww_me2<R, HAD>(c, hd, Jp, Jm, qpr, qmr, static_cast<R>(mp2), static_cast<R>(mm2), &iv));
   } else {
     me = static_cast<double>(
-        ww_me2<R, HAD>(c, hd, p3, p4, p5, p6, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
+        ww_me2<R, HAD>(c, hd, Jp, Jm, qpr, qmr, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
   }
   // dPhi_2(P) (4 pi) = sl / (8 pi shat), dm+^2/(2 pi), dm-^2/(2 pi), [dPhi_2(W) (4 pi)]^2 =
   // 1 / (64 pi^2), flux 1 / (2 shat), colour and spin average 1/12: one constant over shat^2

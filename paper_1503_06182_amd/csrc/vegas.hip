@@ -43,11 +43,14 @@ constexpr int kMaxRowsEvent = 1 << 16;  // cap on event-kernel blocks
 constexpr int kMaxRowsAcc = 1024;       // cap on accumulation blocks (rows of the digit partials)
 
 // digit columns of an iteration's exact sums: S1 = sum w in kD1 digits, then S2 = sum
-// w^2 and each grid-histogram slot (dimension d, bin b: slot d n + b) in kD2 digits
+// w^2 in kD2 digits, then the grid histogram (dimension d, bin b: slot d n + b of nslot)
+// digit-major -- digit k of slot s in column kColHist + k nslot + s -- so that the LDS
+// atomics of lanes in different bins fall on different banks (slot-major, the four
+// digits of a slot span 32 bytes and every slot's digit k met one of a few banks)
 constexpr int kD1 = 3, kD2 = 4;
 constexpr int kColS2 = kD1;             // first column of S2
 constexpr int kColHist = kD1 + kD2;     // first column of the grid histogram
-__host__ __device__ constexpr int hist_col(int slot) { return kColHist + kD2 * slot; }
+__host__ __device__ constexpr int hist_col(int slot) { return kColHist + slot; }  // digit 0; digit k: + k nslot
 __host__ __device__ constexpr int hist_cols(int nslot) { return kColHist + kD2 * nslot; }
 // row stride of the digit partials: the ncol = 7 + 4 D n columns padded to a whole
 // number of 32-column (256-byte) tiles, so that every tile the column reduction reads
@@ -217,20 +220,21 @@ __device__ __forceinline__ unsigned long long* lds_col(long long* acc, int col) 
   return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(acc) + static_cast<uint32_t>(col) * 8u);
 }
 
-__device__ __forceinline__ void acc_hist(long long* acc, int col, const EvDigits& g, bool top) {
+// the digits of w^2 to columns col, col + stride, col + 2 stride, col + 3 stride
+__device__ __forceinline__ void acc_hist(long long* acc, int col, int stride, const EvDigits& g, bool top) {
   unsigned long long* p = lds_col(acc, col);
-  atomicAdd(p + 0, static_cast<unsigned long long>(g.h[0]));
-  atomicAdd(p + 1, static_cast<unsigned long long>(g.h[1]));
-  atomicAdd(p + 2, static_cast<unsigned long long>(g.h[2]));
-  if (top) atomicAdd(p + 3, static_cast<unsigned long long>(g.h[3]));
+  atomicAdd(p, static_cast<unsigned long long>(g.h[0]));
+  atomicAdd(p + stride, static_cast<unsigned long long>(g.h[1]));
+  atomicAdd(p + 2 * stride, static_cast<unsigned long long>(g.h[2]));
+  if (top) atomicAdd(p + 3 * stride, static_cast<unsigned long long>(g.h[3]));
 }
 
-// observable bin: the digits of w, then those of w^2
+// observable bin (seven consecutive columns): the digits of w, then those of w^2
 __device__ __forceinline__ void acc_obs(long long* acc, int col, const EvDigits& g, bool top) {
   unsigned long long* p = lds_col(acc, col);
 #pragma unroll
   for (int k = 0; k < kD1; ++k) atomicAdd(p + k, static_cast<unsigned long long>(g.d[k]));
-  acc_hist(acc, col + kD1, g, top);
+  acc_hist(acc, col + kD1, 1, g, top);
 }
 
 // per-lane S1, S2 -> wave butterfly -> LDS columns 0 .. kLane - 1 (call with the whole block)
@@ -322,16 +326,20 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
 
   LaneSums ls;
   lane_sums_zero(ls);
-  unsigned long long wmax = 0ull, nz = 0ull, nnf = 0ull;
-  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.nev; i += step) {
+  // per-lane counts fit 32 bits (fewer than 2^31 events per launch), and so does the
+  // event index: both keep registers free for the integrand
+  unsigned long long wmax = 0ull;
+  uint32_t nz = 0u, nnf = 0u;
+  const int32_t step = static_cast<int32_t>(gridDim.x * blockDim.x);
+  const int32_t nev32 = static_cast<int32_t>(a.nev);
+  for (int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x); i < nev32; i += step) {
     double u[D > 0 ? D : VEGAS_MAX_DIM], x[D > 0 ? D : VEGAS_MAX_DIM];
     int bins[D > 0 ? D : VEGAS_MAX_DIM];
     if constexpr (EXT) {
 #pragma unroll
       for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
         if (d >= nd) break;
-        const double v = static_cast<double>(a.ext_y[i * nd + d]);
+        const double v = static_cast<double>(a.ext_y[static_cast<int64_t>(i) * nd + d]);
         u[d] = fmin(fmax(v, kExtLo), kExtHi);
       }
     } else {
@@ -414,7 +422,7 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
         for (int d = 0; d < (D > 0 ? D : VEGAS_MAX_DIM); ++d) {
           if (d >= nd) break;
           const int bin = kEarlyBins ? static_cast<int>((bw[d >> 2] >> (8 * (d & 3))) & 0xffu) : bins[d];
-          acc_hist(acc, hist_col(d * n + bin), g, top);
+          acc_hist(acc, hist_col(d * n + bin), nd * n, g, top);
         }
         if constexpr (OBS) acc_obs(acc, ncol_h + kObsW * obin, g, top);
       }
@@ -819,7 +827,7 @@ __global__ void k_accum(AccArgs a) {
   const int ncol = ncol_h + obs_cols(a.nobs);
   const int dlo = blockIdx.y * a.dims_per_group;
   const int dhi = min(nd, dlo + a.dims_per_group);
-  const int lcol = hist_cols((dhi - dlo) * n);
+  const int lslots = (dhi - dlo) * n, lcol = hist_cols(lslots);
   const int ocol = blockIdx.y == 0 ? obs_cols(a.nobs) : 0;  // block-uniform
   // [lcol]: S1, S2, d of the group's dimensions; then [ocol]: the observable's bins
   long long* acc = reinterpret_cast<long long*>(smem);
@@ -843,7 +851,7 @@ __global__ void k_accum(AccArgs a) {
     for (int d = dlo; d < dhi; ++d) {
       const uint32_t word = a.b.rec_bins[(d >> 2) * a.stride_rec + i];
       const int bin = static_cast<int>((word >> (8 * (d & 3))) & 0xffu);
-      acc_hist(acc, hist_col((d - dlo) * n + bin), g, true);
+      acc_hist(acc, hist_col((d - dlo) * n + bin), lslots, g, true);
     }
     if (ocol) acc_obs(acc, lcol + kObsW * static_cast<int>(a.b.rec_obs[i]), g, true);
   }
@@ -852,7 +860,11 @@ __global__ void k_accum(AccArgs a) {
   long long* row = a.b.part_acc + static_cast<int64_t>(blockIdx.x) * part_ld(ncol);
   if (blockIdx.y == 0)
     for (int i = threadIdx.x; i < kColHist; i += blockDim.x) row[i] = acc[i];
-  for (int i = threadIdx.x; i < lcol - kColHist; i += blockDim.x) row[hist_col(dlo * n) + i] = acc[kColHist + i];
+  // local column kColHist + k lslots + ls -> global kColHist + k nd n + dlo n + ls
+  for (int i = threadIdx.x; i < lcol - kColHist; i += blockDim.x) {
+    const int k = i / lslots, ls = i - k * lslots;
+    row[hist_col(dlo * n + ls) + k * (nd * n)] = acc[kColHist + i];
+  }
   for (int i = threadIdx.x; i < ocol; i += blockDim.x) row[ncol_h + i] = acc[lcol + i];
 }
 
@@ -950,7 +962,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
       acc_sums<false>(w, E1, E2, ls, g);
       for (int d = 0; d < nd; ++d) {
         const uint32_t word = b.rec_bins[(d >> 2) * f.stride_rec + i];
-        acc_hist(acc, hist_col(d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), g, true);
+        acc_hist(acc, hist_col(d * n + static_cast<int>((word >> (8 * (d & 3))) & 0xffu)), nslot, g, true);
       }
       if constexpr (OBS) acc_obs(acc, ncol_h + kObsW * static_cast<int>(b.rec_obs[i]), g, true);
     }
@@ -1000,8 +1012,10 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
       osm[so] = (so & 1) ? fx2_value(t[kD1], t[kD1 + 1], t[kD1 + 2], t[kD1 + 3], E2) : fx_value(t[0], t[1], t[2], E1);
       continue;
     }
+    // S1, S2: consecutive digits; a histogram slot: its digits nslot columns apart
     const long long* t = tot + (slot == 0 ? 0 : slot == 1 ? kColS2 : hist_col(slot - 2));
-    const double v = slot == 0 ? fx_value(t[0], t[1], t[2], E1) : fx2_value(t[0], t[1], t[2], t[3], E2);
+    const int ds = slot < 2 ? 1 : nslot;
+    const double v = slot == 0 ? fx_value(t[0], t[1], t[2], E1) : fx2_value(t[0], t[ds], t[2 * ds], t[3 * ds], E2);
     const int h = slot < 2 ? nslot + slot : slot - 2;
     b.hist[h] = v;
     if (slot < 2) s12[slot] = v;
@@ -1505,6 +1519,10 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
       }
     }
   }
+  // uniform products, with the kernels' roundings (one product each)
+  k.MG2 = k.MG * k.MG;
+  k.MGt = k.MG * (1.0 + k.tlo * k.tlo);
+  k.mzgz2 = k.mzgz * k.mzgz;
   return k;
 }
 
