@@ -34,7 +34,9 @@ typedef enum {
   VEGAS_EINVAL = -1, /* bad configuration or argument                         */
   VEGAS_ESTATE = -2, /* call order (e.g. refine before any iterate)            */
   VEGAS_ENOMEM = -3, /* workspace too small or device allocation failed        */
-  VEGAS_EHIP = -4    /* HIP runtime error; text kept for vegas_strerror         */
+  VEGAS_EHIP = -4,   /* HIP runtime error; text kept for vegas_strerror         */
+  VEGAS_ETOOBIG = -5 /* request larger than the static scratch of an
+                        allocation-free call (VEGAS_SCRATCH_DOUBLES)           */
 } vegas_status;
 
 /* integrands (processes) */
@@ -311,6 +313,22 @@ int vegas_stage_times(vegas_handle h, double *ms, int64_t *launches, int32_t res
  * Errors: VEGAS_EINVAL (other process, B or n out of range, NULL), VEGAS_ENOMEM. */
 int vegas_grad(vegas_handle h, const double *params_dev, int32_t B, int64_t n_events, uint32_t iteration,
                double *sigma_dev, double *dsigma_dev);
+
+/* vegas_grad without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid it.
+ * Same arguments, kernels, results (bit for bit) and errors as vegas_grad, but
+ * the per-tile partials and the tree's first level live in a static device
+ * array of VEGAS_SCRATCH_DOUBLES binary64 values (16 MiB) that the library
+ * holds on each GPU it runs on until the process ends; a call needs
+ * (T + ceil(T / 256)) * 6 * B of them, T = ceil(n_events / 64) (at B = 64 up
+ * to about 3.4e5 events, at B = 8 about 2.7e6).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * handles) race and give wrong results; calls ordered on one stream do not.
+ * Errors: as vegas_grad; VEGAS_ETOOBIG above the scratch size; VEGAS_EHIP if
+ * the array's device address could not be taken when the handle was made. */
+#define VEGAS_SCRATCH_DOUBLES (1u << 21)
+int vegas_grad_noalloc(vegas_handle h, const double *params_dev, int32_t B, int64_t n_events,
+                       uint32_t iteration, double *sigma_dev, double *dsigma_dev);
 
 /* Release the handle (and the buffers the library allocated itself). */
 int vegas_destroy(vegas_handle h);

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -1528,6 +1529,32 @@ PhysConst make_consts(const vegas_config* c, const double* p) {
 
 }  // namespace
 
+// Scratch for the allocation-free adjoint (vegas_grad_noalloc): static device memory,
+// one copy per GPU that loads this library, held until the process ends.  Host code
+// never passes this name to a kernel (on the host it is only a stand-in for the
+// symbol): each device's address is taken once with hipGetSymbolAddress and kept.
+static __device__ __align__(256) double scratch[VEGAS_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// the current device's address of the scratch array (taken on its first use)
+hipError_t scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 struct vegas_state {
   vegas_config cfg;
   double params[VEGAS_MAX_PARAMS];
@@ -1583,6 +1610,8 @@ struct vegas_state {
   // adjoint scratch (library-allocated on first use, grown on demand)
   double* gbuf;
   size_t gbuf_doubles;
+  double* scratch;            // this device's copy of the static scratch array (vegas_grad_noalloc)
+  std::string scratch_error;  // why its address could not be taken, if it could not
 };
 
 #define VG_HIP(call)                                                  \
@@ -1814,6 +1843,7 @@ const char* vegas_strerror(int status) {
     case VEGAS_ESTATE: return "call out of order";
     case VEGAS_ENOMEM: return "workspace too small or device allocation failed";
     case VEGAS_EHIP: return g_last_hip_error.empty() ? "HIP runtime error" : g_last_hip_error.c_str();
+    case VEGAS_ETOOBIG: return "request larger than the allocation-free scratch (VEGAS_SCRATCH_DOUBLES)";
     default: return "unknown status";
   }
 }
@@ -1853,6 +1883,15 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return VEGAS_EHIP;
+  }
+  // this device's scratch array for the allocation-free adjoint; a failure here only
+  // disables that call (it then reports the error)
+  {
+    const hipError_t e = scratch_address(h->device, &h->scratch);
+    if (e != hipSuccess) {
+      h->scratch = nullptr;
+      h->scratch_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    }
   }
   if (workspace) {
     h->base = workspace;
@@ -2467,6 +2506,18 @@ int vegas_grad(vegas_handle h, const double* params_dev, int32_t B, int64_t n_ev
     h->gbuf_doubles = need;
   }
   return grad_launch(h, params_dev, B, n_events, iteration, sigma_dev, dsigma_dev, h->gbuf);
+}
+
+int vegas_grad_noalloc(vegas_handle h, const double* params_dev, int32_t B, int64_t n_events, uint32_t iteration,
+                       double* sigma_dev, double* dsigma_dev) {
+  const int v = grad_check(h, params_dev, B, n_events, sigma_dev, dsigma_dev);
+  if (v != VEGAS_OK) return v;
+  if (grad_scratch_doubles(B, n_events) > VEGAS_SCRATCH_DOUBLES) return VEGAS_ETOOBIG;
+  if (!h->scratch) {
+    g_last_hip_error = h->scratch_error;
+    return VEGAS_EHIP;
+  }
+  return grad_launch(h, params_dev, B, n_events, iteration, sigma_dev, dsigma_dev, h->scratch);
 }
 
 // checkpoint layout: header {magic, process, ndim, nbins, iter, seed} then edges, history

@@ -21,13 +21,15 @@ OK, EINVAL, ESTATE, ENOMEM, EHIP = 0, -1, -2, -3, -4
 NPHYS = 16
 MAX_ITER = 4096
 MAX_OBS_BINS = 254
+SCRATCH_DOUBLES = 1 << 21          # static scratch of the allocation-free calls
+ETOOBIG = -5                       # request larger than that scratch
 
 EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
            "vegas_result_from", "vegas_set_observable", "vegas_get_observable", "vegas_set_strata",
            "vegas_set_strata_beta", "vegas_get_strata_counts",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
            "vegas_get_state", "vegas_set_state", "vegas_set_launch", "vegas_destroy",
-           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_last_launch",
+           "vegas_strerror", "vegas_set_timing", "vegas_stage_times", "vegas_grad", "vegas_grad_noalloc", "vegas_last_launch",
            "vegas_export", "vegas_iterate_flow", "vegas_flow_create", "vegas_flow_destroy",
            "vegas_flow_get_params", "vegas_flow_set_params", "vegas_flow_density",
            "vegas_flow_loss_grad", "vegas_flow_train_step", "vegas_flow_sample"]
@@ -90,6 +92,7 @@ def load(path: str = LIB_PATH):
     L.vegas_strerror.argtypes = [C.c_int]
     L.vegas_strerror.restype = C.c_char_p
     L.vegas_grad.argtypes = [vp, vp, i32, i64, C.c_uint32, vp, vp]
+    L.vegas_grad_noalloc.argtypes = [vp, vp, i32, i64, C.c_uint32, vp, vp]
     L.vegas_export.argtypes = [vp, i64, i64, vp, vp]
     L.vegas_iterate_flow.argtypes = [vp, vp, i64, C.POINTER(IterResult)]
     L.vegas_flow_create.argtypes = [i32, i64, C.c_uint64, vp, C.POINTER(vp)]
@@ -306,6 +309,15 @@ class Integrator:
                                   C.c_void_p(sigma.data_ptr()), C.c_void_p(dsigma.data_ptr())),
                "vegas_grad")
         return sigma, dsigma
+
+    def grad_noalloc(self, theta, sigma, dsigma, n_events, iteration):
+        """vegas_grad_noalloc: the same as grad into caller-allocated float64 CUDA tensors
+        sigma[B] and dsigma[B,5] (theta[B,5] float64, contiguous, on the device), with the
+        library's static scratch instead of any device allocation."""
+        B = theta.shape[0]
+        _check(self._L.vegas_grad_noalloc(self._h, C.c_void_p(theta.data_ptr()), B, n_events, iteration,
+                                          C.c_void_p(sigma.data_ptr()), C.c_void_p(dsigma.data_ptr())),
+               "vegas_grad_noalloc")
 
     def set_launch(self, waves_per_block, max_blocks=0):
         _check(self._L.vegas_set_launch(self._h, waves_per_block, max_blocks), "vegas_set_launch")
