@@ -33,21 +33,39 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Work per event of the event kernel (the dominant kernel): FP64 and FP32 VALU
-# FLOPs (add, mul = 1, fma = 2, transcendental instructions = 1) from the
-# rocprofv3 instruction counters of its launches x 64 lanes / events, and the
-# HBM bytes one launch moves at the workload's default event count (FETCH_SIZE
-# x 2 + WRITE_SIZE x 1, the factors read from a plain 1 GiB device copy).
-# Measured on the kernels as built; the counter summaries are under profiles/.
+# Work per event of the event kernel (the dominant kernel).
+#  algorithmic_f64: the FP64 FLOPs of the kernels' formulation per event, counted on the
+#    host by tests/flopcount/count.cpp (the integrand headers compiled with a counting
+#    scalar: add, sub, mul = 1, fma = 2, each hardware reciprocal / inverse-square-root
+#    estimate 1, each library function at OCML_FLOP_PER_CALL; work on uniform values not
+#    counted), through a grid the oracle adapted for five iterations; plus the grid map,
+#    the uniforms and the accumulation (S1, w^2, S2, one addition per dimension).
+#    tests/test_flop_count.py recounts it.  This is the roofline's numerator.
+#  f64 / f32: the FLOPs the kernel as built executes per event, from the rocprofv3
+#    counter SQ_INSTS_VALU_FLOPS_FP64 (FP32) x 64 lanes / events (add, mul,
+#    transcendental instruction = 1, fma = 2), reported beside it as the VALU
+#    utilisation; it includes the fixed-point fold's digit split and both sides of
+#    selects.
+#  traffic: HBM bytes of one launch at the workload's default event count (FETCH_SIZE
+#    x 2 + WRITE_SIZE x 1 KiB, the factors read from a plain 1 GiB device copy).
+# The counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"f64": 405.0, "f32": 0.0, "traffic": 19_738_472, "events": 1_000_000},
-    ("ww_4l", "fp64"): {"f64": 1519.5, "f32": 0.0, "traffic": 171_430_030, "events": 10_000_000},
-    ("ww_4l", "fp32me"): {"f64": 859.5, "f32": 606.0, "traffic": 170_309_482, "events": 10_000_000},
-    ("ww_had", "fp64"): {"f64": 1865.1, "f32": 0.0, "traffic": 293_333_428, "events": 10_000_000},
+    ("w_plus", "fp64"): {"algorithmic_f64": 326.6, "f64": 345.2, "f32": 0.0, "traffic": 22_179_573,
+                         "events": 1_000_000},
+    ("ww_4l", "fp64"): {"algorithmic_f64": 1135.2, "f64": 1157.4, "f32": 0.0, "traffic": 173_536_818,
+                        "events": 10_000_000},
+    ("ww_4l", "fp32me"): {"algorithmic_f64": None, "f64": 688.4, "f32": 506.0, "traffic": None,
+                          "events": 10_000_000},
+    ("ww_had", "fp64"): {"algorithmic_f64": 1437.2, "f64": 1445.1, "f32": 0.0, "traffic": 228_166_734,
+                         "events": 10_000_000},
 }
+# FP64 FLOPs of one call of the library functions the integrands use, measured on gfx950
+# with tests/flopcount/ocml_price.hip under rocprofv3 (SQ_INSTS_VALU_FLOPS_FP64 x 64 /
+# calls, arguments spread over the ranges the integrands pass)
+OCML_FLOP_PER_CALL = {"atan": 58.0, "log": 79.0, "exp": 27.0, "expm1": 32.0}
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count
-HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 8_735_004}
+HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 10_272_637, ("ww_4l", 10_000_000): 13_875_692}
 # FP64 FLOPs of the adjoint's event kernel per (event, parameter point), and its HBM
 # bytes per call at 64 points x 1e6 events, from the same kind of counter runs
 ADJOINT_KERNEL_WORK = {"f64": 264.9, "traffic": 48_225_306, "events": 1_000_000}
@@ -62,9 +80,10 @@ PEAK_HBM_GBS = 8000.0
 
 
 def roofline(workload, precision, n_events, avg_launch_s):
-    """The event kernel against the VALU peaks: achieved = FLOPs per launch / average
-    launch time; for a mixed FP64/FP32 kernel frac is the sum of the two pipes'
-    fractions of their own peaks."""
+    """The event kernel against the VALU peak: achieved = algorithmic FLOPs per launch /
+    average launch time.  Beside it, the FLOPs the kernel executed (rocprof counters) as
+    the VALU utilisation; for the mixed FP64/FP32 kernel (no algorithmic count) the
+    executed FLOPs are the numerator and frac is the sum of the two pipes' fractions."""
     work = EVENT_KERNEL_WORK.get((workload, precision))
     roof = {"kernel": "k_event", "bound": "alu", "achieved": None, "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_ms": avg_launch_s * 1e3}
@@ -72,9 +91,15 @@ def roofline(workload, precision, n_events, avg_launch_s):
         return roof
     f64 = work["f64"] * n_events / avg_launch_s / 1e12
     f32 = work["f32"] * n_events / avg_launch_s / 1e12
-    roof.update(achieved=f64 + f32, frac=f64 / PEAK_FP64_VALU_TFLOPS + f32 / PEAK_FP32_VALU_TFLOPS,
-                flop_per_event={"f64": work["f64"], "f32": work["f32"]},
-                achieved_f64=f64, achieved_f32=f32)
+    util = f64 / PEAK_FP64_VALU_TFLOPS + f32 / PEAK_FP32_VALU_TFLOPS
+    if work["algorithmic_f64"] is not None:
+        alg = work["algorithmic_f64"] * n_events / avg_launch_s / 1e12
+        roof.update(achieved=alg, frac=alg / PEAK_FP64_VALU_TFLOPS,
+                    flop_per_event={"algorithmic_f64": work["algorithmic_f64"]})
+    else:
+        roof.update(achieved=f64 + f32, frac=util, flop_per_event={})
+    roof["flop_per_event"].update(executed_f64=work["f64"], executed_f32=work["f32"])
+    roof.update(executed_tflops_f64=f64, executed_tflops_f32=f32, valu_flop_utilisation=util)
     if work.get("events") == n_events:
         roof["traffic"] = work["traffic"]
     return roof
@@ -288,7 +313,7 @@ def bench_paper_schedule(args):
     st = g.stage_times()
     g.set_timing(False)
     ms_ev = st["event"][0]
-    flop = EVENT_KERNEL_WORK[("ww_4l", "fp64")]["f64"] * sum(sched)
+    flop = EVENT_KERNEL_WORK[("ww_4l", "fp64")]["algorithmic_f64"] * sum(sched)
     roof = {"kernel": "k_event", "bound": "alu", "achieved": flop / (ms_ev * 1e-3) / 1e12,
             "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": flop / (ms_ev * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS, "traffic": None,

@@ -29,8 +29,8 @@ def derived():
             if line.startswith(prefix):
                 f64 = float(re.search(r"FP64 FLOP/event = ([\d.]+)", line).group(1))
                 m32 = re.search(r"FP32 FLOP/event = ([\d.]+)", line)
-                byt = int(re.search(r"= (\d+) B$", line).group(1))
-                out[key] = (f64, float(m32.group(1)) if m32 else 0.0, byt)
+                mb = re.search(r"= (\d+) B$", line)
+                out[key] = (f64, float(m32.group(1)) if m32 else 0.0, int(mb.group(1)) if mb else None)
     return out, block
 
 
@@ -45,9 +45,11 @@ def test_event_kernel_work_matches_counter_summary():
 
 def test_histogram_stage_traffic_matches_counter_summary():
     _, block = derived()
-    line = [x for x in block.splitlines() if x.startswith("W+ histogram stage")][0]
-    byt = int(re.search(r"= (\d+) B against", line).group(1))
-    assert bench.HIST_STAGE_TRAFFIC[("w_plus", 1_000_000)] == byt
+    for prefix, key in (("W+ histogram stage", ("w_plus", 1_000_000)),
+                        ("W+W- histogram stage", ("ww_4l", 10_000_000))):
+        line = [x for x in block.splitlines() if x.startswith(prefix)][0]
+        byt = int(re.search(r"= (\d+) B$", line).group(1))
+        assert bench.HIST_STAGE_TRAFFIC[key] == byt, (key, byt)
 
 
 def test_adjoint_work_matches_its_summary():

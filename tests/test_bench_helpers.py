@@ -17,8 +17,10 @@ def test_roofline_of_the_event_kernel():
     work = bench.EVENT_KERNEL_WORK[("w_plus", "fp64")]
     r = bench.roofline("w_plus", "fp64", 1_000_000, 33e-6)
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
-    assert abs(r["achieved"] - work["f64"] * 1e6 / 33e-6 / 1e12) < 1e-9
+    # the numerator is the algorithmic count; the executed count is reported beside it
+    assert abs(r["achieved"] - work["algorithmic_f64"] * 1e6 / 33e-6 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-12
+    assert abs(r["valu_flop_utilisation"] - work["f64"] * 1e6 / 33e-6 / 1e12 / 78.6) < 1e-12
     assert r["traffic"] == work["traffic"]
     # the counters were taken at the workload's default size only
     assert bench.roofline("w_plus", "fp64", 500_000, 20e-6)["traffic"] is None
