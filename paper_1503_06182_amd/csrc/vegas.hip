@@ -61,6 +61,8 @@ constexpr int kFusedLdsMax = 64 * 1024; // LDS of an event block (grid + digits)
 // observable histogram: bins 1..nobs uniform on [lo, hi), 0 = underflow, nobs + 1 = overflow
 constexpr int kObsLd = VEGAS_MAX_OBS_BINS + 2;
 constexpr int kStrataBlocks = 1024;  // blocks of the hypercube fold (rows of its partials)
+constexpr int kDirectRowsMax = 64;   // up to this many partial rows the finalisation sums them itself
+constexpr int kFinThreads = 1024;    // finalisation block when it folds or refines (else 256)
 
 // n / d for n < 2^31 by multiply and shift: with l = ceil(log2 d), M = floor(2^(32+l) / d)
 // + 1 < 2^33 gives floor(n M / 2^(32+l)) = floor(n / d) exactly, and n M < 2^64
@@ -85,9 +87,15 @@ struct DevBufs {
   double* edges_alt;             // [D][n+1] the grid refined speculatively by k_finalize
   double* rec_w;                 // [maxN]
   uint32_t* rec_bins;            // [ceil(D/4)][maxN], 4 bins of 8 bits per word
-  unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max, cleared by k_finalize)
-  unsigned long long* cnt;       // [2] n_nonzero, n_nonfinite (atomic, cleared by k_finalize)
-  int* fxs;                      // [4] valid, E1, E2 of the fused fold (set by k_finalize for the next iteration)
+  // per-iteration values in two slots, "this iteration" and "the next": the host swaps the
+  // pointers after each iteration, so the finalisation reads this iteration's slot while
+  // it clears (maxw, cnt) or writes (fxs) the next one, and its blocks never race
+  unsigned long long* maxw;      // [1] bits of max |w| (device-wide atomic max)
+  unsigned long long* cnt;       // [2] n_nonzero, n_nonfinite (atomic)
+  int* fxs;                      // [4] valid, E1, E2 of the fused fold at this iteration's scales
+  unsigned long long* maxw_next;  // the next iteration's slots (cleared / set by k_finalize)
+  unsigned long long* cnt_next;
+  int* fxs_next;
   long long* part_acc;           // [rows][part_ld(3*(2+D*n))] per-block digit sums: S1, S2, d[...]
   long long* acc_tot;            // [3*(2+D*n)] digit sums over all blocks
   double* hist;                  // [D*n + 2] d, S1, S2 of the last iteration
@@ -533,14 +541,6 @@ __device__ __forceinline__ int strata_exponent_adapt(double wmax, double N) {
   return fx_exponent(2.0 * N * wmax * wmax);
 }
 
-// sum over the wave by a butterfly: every lane adds the same two values at each stage,
-// so all lanes end with the same bits
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int st = kWave / 2; st > 0; st >>= 1) v += __shfl_xor(v, st, kWave);
-  return v;
-}
-
 // a DPP move of a binary64 value (both halves with the same control); lanes without a
 // source, or in rows the mask leaves out, receive 0
 template <int CTRL, int ROW_MASK, bool BOUND>
@@ -896,6 +896,8 @@ struct FinArgs {
   int strata_blocks;  // rows of the hypercube fold's partials
   int strata_adapt;   // unequal counts: var_j = V / N^2
   double alpha;
+  int direct_rows;    // > 0: no column-sum launch ran; sum rows [0, direct_rows) of the
+                      // partials here, each block only the columns it converts
 };
 
 // var_j: the plain (S2 / N - I^2) / (N - 1), or, stratified, sum_h (1/H)^2 sigma_h^2 / npc
@@ -928,28 +930,95 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
   const DevBufs& b = f.b;
   const int n = f.nbins, nd = f.ndim, nslot = nd * n, ncol_h = hist_cols(nslot);
   const int ncol = ncol_h + (OBS ? obs_cols(f.nobs) : 0);
+  // few partial rows (small iterations, no column-sum launch): this block sums the
+  // columns it converts -- digit k of its dimensions' slots, and in block 0 S1, S2 and
+  // the observable's -- over rows g, g + R, ... (up to 32 per item, item = (column, g)).
+  // The loads of each thread's first item are issued here, before anything waits on
+  // memory, assuming the per-dimension split; a re-fold discards them.
+  const int dr = f.direct_rows, dsplit = gridDim.x > 1;
+  const int dlo = dsplit ? static_cast<int>(blockIdx.x) : 0, dnh = (dsplit ? 1 : nd) * n;
+  const int dncb = dr > 0 ? kD2 * dnh + (blockIdx.x == 0 ? kColHist + (OBS ? obs_cols(f.nobs) : 0) : 0) : 0;
+  const int dR = (dr + 31) / 32;
+  const int64_t dld = part_ld(ncol);
+  auto dcol_of = [&](int qc) {
+    if (qc < kD2 * dnh) {
+      const int k = qc / dnh;
+      return hist_col(dlo * n + (qc - k * dnh)) + k * nslot;
+    }
+    const int e = qc - kD2 * dnh;
+    return e < kColHist ? e : ncol_h + (e - kColHist);
+  };
+  auto dsum_item = [&](int q, int& col) {
+    const int qc = q % dncb, g = q / dncb;
+    col = dcol_of(qc);
+    long long v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int r = g + dR * k;
+      v[k] = r < dr ? b.part_acc[r * dld + col] : 0;
+    }
+    long long t = 0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) t += v[k];
+    return t;
+  };
+  // this iteration's max |w|, counters and fold scales (read before the row loads wait)
   const double wmax = __longlong_as_double(static_cast<long long>(b.maxw[0]));
   const unsigned long long nz = b.cnt[0], nnf = b.cnt[1];
+  const int Ef = b.fxs[1], E2f = b.fxs[2];
+  // the grid edges the block refines, likewise loaded early (same split assumption)
+  const int ne_early = (dsplit ? 1 : nd) * (n + 1);
+  const bool e_fast = f.spec && ne_early <= kFinThreads;  // a refining finalisation has kFinThreads
+  double e_early = 0.0;
+  if (e_fast && static_cast<int>(threadIdx.x) < ne_early) e_early = b.edges[dlo * (n + 1) + threadIdx.x];
+  long long dsum = 0;
+  int dcol = -1;
+  if (static_cast<int>(threadIdx.x) < dncb * dR) dsum = dsum_item(threadIdx.x, dcol);
   const int Ec1 = fx_exponent(wmax), Ec2 = fx_exponent(wmax * wmax);
   int E1 = Ec1, E2 = Ec2, fold = 0;
   if (f.fused) {
     // the scales are kept while this iteration's max |w| is below 2^Ef and neither w nor
     // w^2 lost more than kFxLow bits of headroom: w^2 is folded at 2 Ef, so its headroom
     // shrinks twice as fast as that of w
-    const int Ef = b.fxs[1], E2f = b.fxs[2];
     if (Ec1 > Ef || Ec1 < Ef - kFxLow || Ec2 < E2f - kFxLow) {
       fold = 2;
     } else {
       fold = 1;
       E1 = Ef;
-      E2 = b.fxs[2];
+      E2 = E2f;
     }
   }
-  double* rsm = reinterpret_cast<double*>(smem + f.fold_lds);  // refinement scratch [D][4 (n + 1)]
-  if (f.spec)  // the grid the refinement starts from, loaded while the totals are converted
-    for (int i = threadIdx.x; i < nd * (n + 1); i += blockDim.x)
-      rsm[(i / (n + 1)) * 4 * (n + 1) + 3 * (n + 1) + i % (n + 1)] = b.edges[i];
+  // one block per dimension (launched so when the refinement is computed here): block d
+  // converts and refines dimension d, block 0 also forms the iteration's results.  A
+  // re-fold needs every record in one block, so then block 0 does everything alone.
+  const bool split = gridDim.x > 1 && fold != 2;  // grid-uniform
+  if (blockIdx.x > 0 && !split) return;
+  const int d_lo = split ? static_cast<int>(blockIdx.x) : 0, d_hi = split ? d_lo + 1 : nd;
+  const bool lead = blockIdx.x == 0;
+  double* rsm = reinterpret_cast<double*>(smem + f.fold_lds);  // refinement scratch [dims][4 (n + 1)]
+  if (f.spec) {  // the grid the refinement starts from
+    if (e_fast && split == (dsplit != 0)) {  // the early loads cover this block's dimensions
+      const int i = threadIdx.x;
+      if (i < ne_early) rsm[(i / (n + 1)) * 4 * (n + 1) + 3 * (n + 1) + i % (n + 1)] = e_early;
+    } else {
+      for (int i = threadIdx.x; i < (d_hi - d_lo) * (n + 1); i += blockDim.x)
+        rsm[(i / (n + 1)) * 4 * (n + 1) + 3 * (n + 1) + i % (n + 1)] = b.edges[d_lo * (n + 1) + i];
+    }
+  }
   const long long* tot = b.acc_tot;
+  if (dr > 0 && fold != 2) {  // block-uniform (fold != 2: the split the loads assumed)
+    long long* acc = reinterpret_cast<long long*>(smem);
+    for (int q = threadIdx.x; q < dncb; q += blockDim.x) acc[dcol_of(q)] = 0;
+    __syncthreads();
+    if (dcol >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(&acc[dcol]), static_cast<unsigned long long>(dsum));
+    for (int q = threadIdx.x + blockDim.x; q < dncb * dR; q += blockDim.x) {
+      int col;
+      const long long t = dsum_item(q, col);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&acc[col]), static_cast<unsigned long long>(t));
+    }
+    __syncthreads();
+    tot = acc;
+  }
   if (fold == 2) {  // block-uniform
     long long* acc = reinterpret_cast<long long*>(smem);
     for (int i = threadIdx.x; i < ncol; i += blockDim.x) acc[i] = 0;
@@ -977,7 +1046,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
   const int nslot_all = nslot + 2 + (OBS ? 2 * (f.nobs + 2) : 0);
   // stratified: the hypercube fold's row sums, per wave (rows strided over the block)
   __shared__ long long sv[16][3];
-  if (f.strata_H > 0) {  // block-uniform
+  if (lead && f.strata_H > 0) {  // block-uniform
     long long t0 = 0, t1 = 0, t2 = 0;
     for (int r = threadIdx.x; r < f.strata_blocks; r += blockDim.x) {
       t0 += b.strat_part[r * 4 + 0];
@@ -1006,7 +1075,20 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
       az = b.obs_acc[2 * kObsLd + kb];
     }
   }
-  for (int slot = threadIdx.x; slot < nslot_all; slot += blockDim.x) {
+  // the values this block converts: S1, S2 and the observable's (block 0), and the
+  // histogram slots of its dimensions
+  const int h_lo = d_lo * n, h_hi = d_hi * n;
+  for (int q = threadIdx.x; q < nslot_all; q += blockDim.x) {
+    int slot = q;
+    if (split) {
+      if (q < 2 || q >= nslot + 2) {
+        if (!lead) continue;
+      } else if (q - 2 >= h_hi - h_lo) {
+        continue;
+      } else {
+        slot = 2 + h_lo + (q - 2);
+      }
+    }
     if (OBS && slot >= nslot + 2) {
       const int so = slot - (nslot + 2);
       const long long* t = tot + ncol_h + kObsW * (so >> 1);
@@ -1020,10 +1102,10 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     const int h = slot < 2 ? nslot + slot : slot - 2;
     b.hist[h] = v;
     if (slot < 2) s12[slot] = v;
-    else if (f.spec) rsm[(h / n) * 4 * (n + 1) + h % n] = v;
+    else if (f.spec) rsm[(h / n - d_lo) * 4 * (n + 1) + h % n] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (lead && threadIdx.x == 0) {
     const double S1 = s12[0], S2 = s12[1];
     const double N = static_cast<double>(f.nev);
     const double I = S1 / N;
@@ -1036,14 +1118,15 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     b.iter_out[3] = static_cast<double>(nnf);
     b.iter_out[4] = N;
     b.iter_out[5] = static_cast<double>(fold);
-    b.fxs[0] = 1;
-    b.fxs[1] = Ec1 + kFxHead;
-    b.fxs[2] = 2 * (Ec1 + kFxHead);
-    b.maxw[0] = 0ull;
-    b.cnt[0] = 0ull;
-    b.cnt[1] = 0ull;
+    // the next iteration's slots: its scales, and its max |w| and counters from zero
+    b.fxs_next[0] = 1;
+    b.fxs_next[1] = Ec1 + kFxHead;
+    b.fxs_next[2] = 2 * (Ec1 + kFxHead);
+    b.maxw_next[0] = 0ull;
+    b.cnt_next[0] = 0ull;
+    b.cnt_next[1] = 0ull;
   }
-  if constexpr (OBS) {
+  if (OBS && lead) {
     // per bin: H = S1_b / N and var_b = (S2_b / N - H^2) / (N - 1), as for the
     // integral; iterations from obs_first on are combined with the integral's
     // weights 1 / var_j (the plain mean once an iteration has zero variance)
@@ -1091,10 +1174,10 @@ __device__ __forceinline__ void finalize_block(const FinArgs& f, unsigned char* 
     // has to swap the grid buffers (the same routine as k_refine: the same bits)
     // (the histogram and the old grid are already in the scratch; refine_dim's first
     // barrier orders those LDS writes before its reads)
-    const int d = threadIdx.x >> 6;
-    const bool active = d < nd;
+    const int d = d_lo + (threadIdx.x >> 6);
+    const bool active = d < d_hi;
     refine_dim(active, true, n, f.alpha, nullptr, nullptr, b.edges_alt + (active ? d : 0) * (n + 1),
-               rsm + (active ? d : 0) * 4 * (n + 1));
+               rsm + (active ? d - d_lo : 0) * 4 * (n + 1));
   }
 }
 
@@ -1128,7 +1211,7 @@ __global__ void k_accsum(DevBufs b, int ncol, int rows) {
 // device-scope fence in every block, which costs far more than the launch)
 template <bool OBS>
 __global__ void k_finalize(FinArgs f) {
-  extern __shared__ unsigned char smem[];  // fused: [3 (2 + D n)] for a re-fold
+  extern __shared__ unsigned char smem[];  // fused: the digit columns, for a re-fold; the refinement scratch
   finalize_block<OBS>(f, smem);
 }
 
@@ -1137,88 +1220,126 @@ __global__ void k_finalize(FinArgs f) {
 // ---------------------------------------------------------------------------
 
 // Refinement of dimension d by one wave (lane = threadIdx.x % 64) with LDS scratch
-// sm[4 (n + 1)]; every wave of the block calls it the same number of times (its
-// barriers are block-wide); active == false only keeps the barriers.  Reads the
-// histogram hist[n] and edges e_in[n + 1] (or finds them already in sm[0..n) and
-// sm[3 (n + 1) ..] when preloaded), writes e_out[n + 1] (may equal e_in).  An empty
-// histogram keeps the dimension's grid.
+// sm[4 (n + 1)]; every wave of the block calls it (its one barrier is block-wide);
+// active == false only keeps the barrier.  Reads the histogram hist[n] and edges
+// e_in[n + 1] (or finds them already in sm[0..n) and sm[3 (n + 1) ..] when preloaded),
+// writes e_out[n + 1] (may equal e_in).  An empty histogram keeps the dimension's grid.
+// Lane l owns the bins [c l, c l + c), c = ceil(n / 64) <= 4: after the barrier the
+// smoothing, the damping, the cumulative importance and the new edges stay in its
+// registers, with wave sums and one wave scan by DPP; each lane places the new edges
+// that fall into its own bins (edge k lies in the old bin j with cm[j] < k stp <= cm[j+1],
+// the same bin a search over cm finds), so no cross-lane search is needed.
+__device__ __forceinline__ double wave_scan_f64(double v) {  // inclusive, lanes 0..63
+  v += dpp_f64<0x111, 0xf, true>(v);
+  v += dpp_f64<0x112, 0xf, true>(v);
+  v += dpp_f64<0x114, 0xf, true>(v);
+  v += dpp_f64<0x118, 0xf, true>(v);
+  v += dpp_f64<0x142, 0xa, false>(v);
+  v += dpp_f64<0x143, 0xc, false>(v);
+  return v;
+}
+
+__device__ __forceinline__ double wave_scan_max_f64(double v) {  // inclusive, for v >= 0
+  v = fmax(v, dpp_f64<0x111, 0xf, true>(v));
+  v = fmax(v, dpp_f64<0x112, 0xf, true>(v));
+  v = fmax(v, dpp_f64<0x114, 0xf, true>(v));
+  v = fmax(v, dpp_f64<0x118, 0xf, true>(v));
+  v = fmax(v, dpp_f64<0x142, 0xa, false>(v));
+  v = fmax(v, dpp_f64<0x143, 0xc, false>(v));
+  return v;
+}
+
+__device__ __forceinline__ double read_lane_f64(double v, int lane) {  // lane wave-uniform
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 __device__ __forceinline__ void refine_dim(bool active, bool preloaded, int n, double alpha, const double* hist,
                                            const double* e_in, double* e_out, double* sm) {
-  double* hs = sm;               // histogram of this dimension
-  double* dm = sm + (n + 1);     // smoothed histogram, then damped importance m
-  double* cm = sm + 2 * (n + 1); // cumulative importance: cm[k] = m_0 + ... + m_{k-1}
-  double* eo = sm + 3 * (n + 1); // old edges
+  double* hs = sm;                // histogram of this dimension
+  double* eo = sm + 3 * (n + 1);  // old edges
   const int lane = threadIdx.x & 63;
   if (active && !preloaded) {
     for (int k = lane; k < n; k += kWave) hs[k] = hist[k];
     for (int k = lane; k <= n; k += kWave) eo[k] = e_in[k];
   }
   __syncthreads();
+  const int c = (n + kWave - 1) / kWave, j0 = c * lane;
+  // smoothed histogram of the lane's bins, and the sums of the raw and smoothed ones
+  double v[4];
   double s = 0.0, sb = 0.0;
-  if (active)
-    for (int k = lane; k < n; k += kWave) {
-      double v;
-      if (k == 0) v = (hs[0] + hs[1]) / 2.0;
-      else if (k == n - 1) v = (hs[n - 2] + hs[n - 1]) / 2.0;
-      else v = (hs[k - 1] + hs[k] + hs[k + 1]) / 3.0;
-      dm[k] = v;
-      s += hs[k];
-      sb += v;
-    }
-  s = wave_sum_f64(s);
-  sb = wave_sum_f64(sb);
-  const bool work = active && s > 0.0;  // wave-uniform
-  __syncthreads();
-  if (work) {
-    const double isb = 1.0 / sb;
-    for (int k = lane; k < n; k += kWave) {
-      const double r = dm[k] * isb;
-      double m;
-      if (r == 0.0) {
-        m = 0.0;
-      } else if (r == 1.0) {
-        m = 1.0;
-      } else {
-        const double y = (r - 1.0) / log(r);
-        m = alpha == 1.5 ? y * sqrt(y) : pow(y, alpha);  // the usual damping exponent without pow
-      }
-      dm[k] = m;
-    }
-  }
-  __syncthreads();
-  if (work) {
-    // inclusive prefix sums: lane l sums bins [4l, 4l+4) in order, then a wave scan
-    double part = 0.0;
-    for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) part += dm[k];
-    double incl = part;
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const double o = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += o;
-    }
-    double run = incl - part;  // exclusive prefix of this lane's chunk
-    if (lane == 0) cm[0] = 0.0;
-    for (int k = 4 * lane; k < 4 * lane + 4 && k < n; ++k) {
-      run += dm[k];
-      cm[k + 1] = run;
+  for (int i = 0; i < 4; ++i) {
+    const int k = j0 + i;
+    v[i] = 0.0;
+    if (active && i < c && k < n) {
+      double t;
+      if (k == 0) t = (hs[0] + hs[1]) / 2.0;
+      else if (k == n - 1) t = (hs[n - 2] + hs[n - 1]) / 2.0;
+      else t = (hs[k - 1] + hs[k] + hs[k + 1]) / 3.0;
+      v[i] = t;
+      s += hs[k];
+      sb += t;
     }
   }
-  __syncthreads();
+  s = wave_total_f64(s);
+  sb = wave_total_f64(sb);
+  const bool work = active && s > 0.0;  // wave-uniform
   if (work) {
-    const double stp = cm[n] / n;
-    // new interior edge k sits in the old bin j with cm[j] < k*stp <= cm[j+1]
-    for (int k = 1 + lane; k < n; k += kWave) {
-      const double target = k * stp;
-      int lo = 0, hi = n - 1;  // largest j in [0, n-1] with cm[j] < target
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cm[mid] < target) lo = mid;
-        else hi = mid - 1;
+    // damped importance m of each bin (the usual damping exponent 1.5 without pow)
+    const double isb = 1.0 / sb;
+    double m[4];
+    double part = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      m[i] = 0.0;
+      if (i < c && j0 + i < n) {
+        const double r = v[i] * isb;
+        if (r == 1.0) {
+          m[i] = 1.0;
+        } else if (r != 0.0) {
+          const double y = (r - 1.0) / log(r);
+          m[i] = alpha == 1.5 ? y * sqrt(y) : pow(y, alpha);
+        }
+        part += m[i];
       }
-      const int j = lo;
-      double frac = dm[j] > 0.0 ? (target - cm[j]) / dm[j] : 0.0;
-      frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
-      e_out[k] = eo[j] + frac * (eo[j + 1] - eo[j]);
+    }
+    // cumulative importance at the lane's bin edges, cm[j0 + i] = cb[i]: the lane's sums
+    // r from the scan's exclusive value, raised to the largest chunk end of the lanes
+    // before it (a maximum is exact, so the lane after this one sees this lane's top
+    // cb[c] as its cb[0], bit for bit): cm is non-decreasing across lanes, and the
+    // bins' intervals (cm[j], cm[j+1]] tile (0, cm[n]] whatever the sums' rounding
+    double r[5];
+    r[0] = wave_scan_f64(part) - part;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i + 1] = (i < c && j0 + i < n) ? r[i] + m[i] : r[i];
+    const double carry = wave_scan_max_f64(dpp_f64<0x138, 0xf, true>(r[4]));  // lanes before (wave_shr:1)
+    double cb[5];
+    cb[0] = carry;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) cb[i] = fmax(r[i], carry);
+    const double stp = read_lane_f64(cb[4], (n - 1) / c) / n;  // cm[n] / n
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = j0 + i;
+      if (i >= c || j >= n) break;
+      const double lo = cb[i], hi = cb[i + 1];
+      // the first interior edge above lo
+      int k = static_cast<int>(lo / stp);
+      k = k < 1 ? 1 : k;
+      while (k > 1 && (k - 1) * stp > lo) --k;
+      while (k < n && k * stp <= lo) ++k;
+      if (k >= n) continue;
+      const double e0 = eo[j], e1 = eo[j + 1];
+      for (; k < n; ++k) {
+        const double target = k * stp;
+        if (j < n - 1 && target > hi) break;  // the last bin takes every remaining edge
+        double frac = m[i] > 0.0 ? (target - lo) / m[i] : 0.0;
+        frac = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+        e_out[k] = e0 + frac * (e1 - e0);
+      }
     }
     if (lane == 0) {
       e_out[0] = 0.0;
@@ -1332,9 +1453,9 @@ Layout make_layout(int D, int n, int64_t maxN) {
   L.rec_w = take(sizeof(double) * maxN);
   L.rec_bins = take(sizeof(uint32_t) * words * maxN);
   L.rec_obs = take(maxN);
-  L.maxw = take(sizeof(unsigned long long) * 2);
-  L.cnt = take(sizeof(unsigned long long) * 2);
-  L.fxs = take(sizeof(int) * 4);
+  L.maxw = take(sizeof(unsigned long long) * 4);
+  L.cnt = take(sizeof(unsigned long long) * 4);
+  L.fxs = take(sizeof(int) * 8);
   // digit columns for the largest observable histogram
   const int ncol_max = hist_cols(D * n) + obs_cols(VEGAS_MAX_OBS_BINS);
   L.part_acc = take(sizeof(long long) * kMaxRowsAcc * part_ld(ncol_max));
@@ -1911,6 +2032,9 @@ int vegas_init(const vegas_config* cfg, int64_t max_events, void* workspace, siz
   h->b.maxw = reinterpret_cast<unsigned long long*>(B + L.maxw);
   h->b.cnt = reinterpret_cast<unsigned long long*>(B + L.cnt);
   h->b.fxs = reinterpret_cast<int*>(B + L.fxs);
+  h->b.maxw_next = h->b.maxw + 2;
+  h->b.cnt_next = h->b.cnt + 2;
+  h->b.fxs_next = h->b.fxs + 4;
   h->b.part_acc = reinterpret_cast<long long*>(B + L.part_acc);
   h->b.acc_tot = reinterpret_cast<long long*>(B + L.acc_tot);
   h->b.hist = reinterpret_cast<double*>(B + L.hist);
@@ -2137,7 +2261,12 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
     VG_HIP(t.done());
   }
   const int ncol = hist_cols(nslot) + obs_cols(h->nobs);
-  {
+  // few partial rows of a fused fold whose finalisation refines the grid (one block per
+  // dimension): those blocks sum the rows they need themselves, and the column-sum
+  // launch, a fixed cost of several microseconds, is skipped
+  const bool spec = h->spec_ok && !ext_y;
+  const int direct_rows = (fused && spec && rows <= kDirectRowsMax) ? rows : 0;
+  if (!direct_rows) {
     TimedLaunch t(h, 1);
     hipExtLaunchKernelGGL(k_accsum, dim3((ncol + kColTile - 1) / kColTile, (rows + kRowTile - 1) / kRowTile),
                           dim3(256), 0, h->stream, t.e0, t.e1, 0, h->b, ncol, rows);
@@ -2168,7 +2297,7 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
     fa.nbins = h->n;
     fa.iter = h->iter;
     fa.fused = fused ? 1 : 0;
-    fa.spec = (h->spec_ok && !ext_y) ? 1 : 0;
+    fa.spec = spec ? 1 : 0;
     fa.fold_lds = fused ? h->fin_lds : 0;
     fa.obs_lds = fa.fold_lds + (fa.spec ? h->refine_lds : 0);
     fa.nobs = h->nobs;
@@ -2178,17 +2307,25 @@ int run_iteration(vegas_handle h, int64_t n_req, const float* ext_y, const float
     fa.strata_blocks = strata_blocks;
     fa.strata_adapt = adapt ? 1 : 0;
     fa.alpha = h->cfg.alpha;
+    fa.direct_rows = direct_rows;
     const int lds = fa.obs_lds + (h->nobs ? static_cast<int>(sizeof(double) * 2 * (h->nobs + 2)) : 0);
+    // with the refinement done here, one block per dimension (block 0 also forms the
+    // results; a re-fold falls back to block 0 alone)
+    const unsigned fblocks = fa.spec ? static_cast<unsigned>(h->D) : 1u;
     TimedLaunch t(h, 2);
     if (h->nobs)
-      hipExtLaunchKernelGGL(k_finalize<true>, dim3(1), dim3(fused || fa.spec ? 1024 : 256), lds, h->stream, t.e0,
-                            t.e1, 0, fa);
+      hipExtLaunchKernelGGL(k_finalize<true>, dim3(fblocks), dim3(fused || fa.spec ? kFinThreads : 256), lds, h->stream,
+                            t.e0, t.e1, 0, fa);
     else
-      hipExtLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(fused || fa.spec ? 1024 : 256), lds, h->stream, t.e0,
-                            t.e1, 0, fa);
+      hipExtLaunchKernelGGL(k_finalize<false>, dim3(fblocks), dim3(fused || fa.spec ? kFinThreads : 256), lds, h->stream,
+                            t.e0, t.e1, 0, fa);
     VG_HIP(t.done());
     h->spec_ready = fa.spec != 0;
   }
+  // the next iteration's slots become the current ones
+  std::swap(h->b.maxw, h->b.maxw_next);
+  std::swap(h->b.cnt, h->b.cnt_next);
+  std::swap(h->b.fxs, h->b.fxs_next);
   h->scale_valid = true;
   const uint32_t j = h->iter;
   h->iter++;
