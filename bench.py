@@ -52,11 +52,11 @@ sys.path.insert(0, ROOT)
 EVENT_KERNEL_WORK = {
     ("w_plus", "fp64"): {"algorithmic_f64": 326.6, "f64": 345.2, "f32": 0.0, "traffic": 22_179_573,
                          "events": 1_000_000},
-    ("ww_4l", "fp64"): {"algorithmic_f64": 1135.2, "f64": 1157.4, "f32": 0.0, "traffic": 173_536_818,
+    ("ww_4l", "fp64"): {"algorithmic_f64": 1128.2, "f64": 1157.4, "f32": 0.0, "traffic": 173_536_818,
                         "events": 10_000_000},
     ("ww_4l", "fp32me"): {"algorithmic_f64": None, "f64": 688.4, "f32": 506.0, "traffic": None,
                           "events": 10_000_000},
-    ("ww_had", "fp64"): {"algorithmic_f64": 1437.2, "f64": 1445.1, "f32": 0.0, "traffic": 228_166_734,
+    ("ww_had", "fp64"): {"algorithmic_f64": 1423.2, "f64": 1445.1, "f32": 0.0, "traffic": 228_166_734,
                          "events": 10_000_000},
 }
 # FP64 FLOPs of one call of the library functions the integrands use, measured on gfx950

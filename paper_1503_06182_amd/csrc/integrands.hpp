@@ -61,28 +61,67 @@ struct PhysConst {
 // sin and cos of |y| <= pi/4 by their Taylor series up to y^17 and y^18 (the next
 // terms are below 2^-62 of the sums there)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double poly_coef(double c) {
+  // a coefficient materialised in a scalar register pair where it is used: an FMA then
+  // takes it as its SGPR operand, instead of a copy of a loop-invariant vector register
+  // into the accumulating FMA's destination before each step
+  VG_OPAQUE_SGPR(c);
+  return c;
+}
+
 __device__ __forceinline__ void sincos_taylor(double y, double& sn, double& cs) {
   const double y2 = y * y;
   // sin y = y + y^3 sum_k (-1)^(k+1) y^2k / (2k + 3)!, cos y = 1 + y^2 sum_k (-1)^(k+1) y^2k / (2k + 2)!
-  double ps = 1.0 / 355687428096000.0;            // 1/17!
-  ps = __fma_rn(ps, y2, -1.0 / 1307674368000.0);  // 1/15!
-  ps = __fma_rn(ps, y2, 1.0 / 6227020800.0);      // 1/13!
-  ps = __fma_rn(ps, y2, -1.0 / 39916800.0);       // 1/11!
-  ps = __fma_rn(ps, y2, 1.0 / 362880.0);          // 1/9!
-  ps = __fma_rn(ps, y2, -1.0 / 5040.0);           // 1/7!
-  ps = __fma_rn(ps, y2, 1.0 / 120.0);             // 1/5!
-  ps = __fma_rn(ps, y2, -1.0 / 6.0);              // 1/3!
-  double pc = -1.0 / 6402373705728000.0;          // 1/18!
-  pc = __fma_rn(pc, y2, 1.0 / 20922789888000.0);  // 1/16!
-  pc = __fma_rn(pc, y2, -1.0 / 87178291200.0);    // 1/14!
-  pc = __fma_rn(pc, y2, 1.0 / 479001600.0);       // 1/12!
-  pc = __fma_rn(pc, y2, -1.0 / 3628800.0);        // 1/10!
-  pc = __fma_rn(pc, y2, 1.0 / 40320.0);           // 1/8!
-  pc = __fma_rn(pc, y2, -1.0 / 720.0);            // 1/6!
-  pc = __fma_rn(pc, y2, 1.0 / 24.0);              // 1/4!
-  pc = __fma_rn(pc, y2, -0.5);                    // 1/2!
+  double ps = poly_coef(1.0 / 355687428096000.0);             // 1/17!
+  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 1307674368000.0));  // 1/15!
+  ps = __fma_rn(ps, y2, poly_coef(1.0 / 6227020800.0));      // 1/13!
+  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 39916800.0));       // 1/11!
+  ps = __fma_rn(ps, y2, poly_coef(1.0 / 362880.0));          // 1/9!
+  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 5040.0));           // 1/7!
+  ps = __fma_rn(ps, y2, poly_coef(1.0 / 120.0));             // 1/5!
+  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 6.0));              // 1/3!
+  double pc = poly_coef(-1.0 / 6402373705728000.0);          // 1/18!
+  pc = __fma_rn(pc, y2, poly_coef(1.0 / 20922789888000.0));  // 1/16!
+  pc = __fma_rn(pc, y2, poly_coef(-1.0 / 87178291200.0));    // 1/14!
+  pc = __fma_rn(pc, y2, poly_coef(1.0 / 479001600.0));       // 1/12!
+  pc = __fma_rn(pc, y2, poly_coef(-1.0 / 3628800.0));        // 1/10!
+  pc = __fma_rn(pc, y2, poly_coef(1.0 / 40320.0));           // 1/8!
+  pc = __fma_rn(pc, y2, poly_coef(-1.0 / 720.0));            // 1/6!
+  pc = __fma_rn(pc, y2, poly_coef(1.0 / 24.0));              // 1/4!
+  pc = __fma_rn(pc, y2, -0.5);                               // 1/2!
   sn = __fma_rn(y * y2, ps, y);
   cs = __fma_rn(y2, pc, 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// atan(v) by the method of Moshier's Cephes library (atan.c): fold |v| to
+// |x| <= 0.66 with atan(|v|) = pi/2 + atan(-1/|v|) above tan(3 pi/8) and
+// pi/4 + atan((|v| - 1)/(|v| + 1)) above 0.66, then atan(x) = x + x z P(z)/Q(z),
+// z = x^2, with its degree-4 / 5 rational fit; the low part of pi/2 (resp. half of
+// it) is added last.  Branch-free here: the fold is one division (n / d with d = 1 on
+// the low range), and P/Q the second; the coefficients are scalar-register operands.
+// Relative error about 2 units in the last place (checked on the CPU against atanl).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double atan_rr(double v) {
+  constexpr double kT3p8 = 2.41421356237309504880, kPio2 = 1.57079632679489661923,
+                   kPio4 = 0.78539816339744830962, kMoreBits = 6.123233995736765886130e-17;
+  const double a = fabs(v);
+  const bool hi = a > kT3p8, mid = !hi && a > 0.66;
+  const double x = div_nr(hi ? -1.0 : (mid ? a - 1.0 : a), hi ? a : (mid ? a + 1.0 : 1.0));
+  const double z = x * x;
+  double p = poly_coef(-8.750608600031904122785e-1);
+  p = __fma_rn(p, z, poly_coef(-1.615753718733365076637e1));
+  p = __fma_rn(p, z, poly_coef(-7.500855792314704667340e1));
+  p = __fma_rn(p, z, poly_coef(-1.228866684490136173410e2));
+  p = __fma_rn(p, z, poly_coef(-6.485021904942025371773e1));
+  double q = z + poly_coef(2.485846490142306297962e1);
+  q = __fma_rn(q, z, poly_coef(1.650270098316988542046e2));
+  q = __fma_rn(q, z, poly_coef(4.328810604912902668951e2));
+  q = __fma_rn(q, z, poly_coef(4.853903996359136964868e2));
+  q = __fma_rn(q, z, poly_coef(1.945506571482613964425e2));
+  const double r = __fma_rn(x, z * div_nr(p, q), x);
+  const double y = hi ? kPio2 + (r + kMoreBits) : (mid ? kPio4 + (r + 0.5 * kMoreBits) : r);
+  return copysign(y, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,7 +575,7 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     const double tau = exp(L);
     sh = tau * c.S;
     rs = sqrt_nr(sh);
-    rho_rng = atan((sh - c.M2) * c.invMG) - c.rho_lo;
+    rho_rng = atan_rr((sh - c.M2) * c.invMG) - c.rho_lo;
     lum = 2.0 * (tau * c.Ldiff) * (-L) * pdf_pair(c, tau, L, expm1(l1) * expm1(l2));
     hd.rs = rs;
     hd.sh = sh;
@@ -548,7 +587,7 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
   double mp, imp;
   sqrt_rsqrt_nr(mp2, mp, imp);
   const double up = (rs - mp) * (rs - mp);
-  const double rrng2 = atan((up - c.M2) * c.invMG) - c.rho_lo;
+  const double rrng2 = atan_rr((up - c.M2) * c.invMG) - c.rho_lo;
   const double mm2 = bw_map(c, x[1], rrng2, jm);
   if (!(mm2 > 0.0)) return 0.0;
   double mm, imm;

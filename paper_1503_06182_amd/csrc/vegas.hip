@@ -287,7 +287,7 @@ constexpr double kExtLo = 0x1p-40, kExtHi = 1.0 - 0x1p-40;
 
 template <int PROC>
 constexpr int event_min_waves() {
-  return (PROC == VEGAS_WW_4L || PROC == VEGAS_WW_HAD) ? 2 : (PROC == VEGAS_W_PLUS ? 3 : 4);
+  return PROC == VEGAS_WW_HAD ? 2 : (PROC == VEGAS_WW_4L ? 3 : 4);
 }
 
 // EXT: the point is the learned proposal's y (binary32, kept inside the open unit

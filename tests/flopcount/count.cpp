@@ -4,7 +4,8 @@
 // compiled for the host with binary64 replaced by a counting scalar: every addition,
 // subtraction and multiplication counts 1, every fused multiply-add 2, each hardware
 // reciprocal / inverse-square-root estimate 1 (the rocprof counter's convention), and
-// each call of a library function (atan, log, exp, expm1) its price in FP64 FLOPs
+// each call of a library function (log, exp, expm1; atan, which the integrands no
+// longer call, is kept for comparison) its price in FP64 FLOPs
 // measured on gfx950 with ocml_price.hip (given on the command line).  Operations whose
 // operands are all uniform (literals, the configuration's constants) are not counted:
 // the GPU computes them once per thread, outside the event loop.  Comparisons, selects,
