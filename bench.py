@@ -50,13 +50,13 @@ sys.path.insert(0, ROOT)
 #    x 2 + WRITE_SIZE x 1 KiB, the factors read from a plain 1 GiB device copy).
 # The counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"algorithmic_f64": 326.6, "f64": 345.2, "f32": 0.0, "traffic": 22_179_573,
+    ("w_plus", "fp64"): {"algorithmic_f64": 326.6, "f64": 345.3, "f32": 0.0, "traffic": 25_497_497,
                          "events": 1_000_000},
-    ("ww_4l", "fp64"): {"algorithmic_f64": 1128.2, "f64": 1157.4, "f32": 0.0, "traffic": 173_536_818,
+    ("ww_4l", "fp64"): {"algorithmic_f64": 1128.2, "f64": 1153.7, "f32": 0.0, "traffic": 180_147_627,
                         "events": 10_000_000},
-    ("ww_4l", "fp32me"): {"algorithmic_f64": None, "f64": 688.4, "f32": 506.0, "traffic": None,
+    ("ww_4l", "fp32me"): {"algorithmic_f64": None, "f64": 684.6, "f32": 506.0, "traffic": None,
                           "events": 10_000_000},
-    ("ww_had", "fp64"): {"algorithmic_f64": 1423.2, "f64": 1445.1, "f32": 0.0, "traffic": 228_166_734,
+    ("ww_had", "fp64"): {"algorithmic_f64": 1423.2, "f64": 1437.8, "f32": 0.0, "traffic": 216_933_959,
                          "events": 10_000_000},
 }
 # FP64 FLOPs of one call of the library functions the integrands use, measured on gfx950
@@ -65,7 +65,7 @@ EVENT_KERNEL_WORK = {
 OCML_FLOP_PER_CALL = {"atan": 58.0, "log": 79.0, "exp": 27.0, "expm1": 32.0}
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count
-HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 10_272_637, ("ww_4l", 10_000_000): 13_875_692}
+HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 13_565_011, ("ww_4l", 10_000_000): 20_432_973}
 # FP64 FLOPs of the adjoint's event kernel per (event, parameter point), and its HBM
 # bytes per call at 64 points x 1e6 events, from the same kind of counter runs
 ADJOINT_KERNEL_WORK = {"f64": 264.9, "traffic": 48_225_306, "events": 1_000_000}
@@ -720,6 +720,11 @@ def measure_vegas(args, cfg, prec, N):
             "eff": 1.0 / (eps * eps * T), "kish": kish / T}
 
 
+def progress(msg):
+    """one line on stderr per finished phase (the JSON line stays alone on stdout)"""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -750,12 +755,17 @@ def main():
     prec = P.FP32_ME if args.precision == "fp32me" else P.FP64
     m = measure_vegas(args, cfg, prec, N)
     make, Wn, st, reps, timed, shape = m["make"], m["Wn"], m["st"], m["reps"], m["timed"], m["shape"]
+    progress(f"{args.workload}: headline measured ({m['T'] / args.steps * 1e3:.3f} ms per step)")
 
     legs = not args.no_legs
     obs_leg = observable_leg(args, make, Wn, N, min(reps), st["event"]) \
         if legs and args.workload in OBS_BINNING else None
+    if obs_leg is not None:
+        progress("observable leg done")
     strata = strata_leg(args, make, Wn, N, cfg["ndim"], min(reps), timed) \
         if legs and args.strata != 0 else None
+    if strata is not None:
+        progress("stratified legs done")
 
     ms_ev, n_ev = st["event"]
     avg_ev = ms_ev / max(n_ev, 1) * 1e-3
@@ -820,7 +830,9 @@ def main():
             "speedup_min_ms_per_step_vs_fp64": min(reps) / min(m32["reps"]),
             "kernel_ms_per_step": {k: v[0] / args.steps for k, v in m32["st"].items()},
             "roofline": roof32}
+        progress("binary32 matrix-element leg done")
         fl = bench_flow(args, emit=False)
+        progress("learned-proposal leg done")
         line["flow"] = {
             "events_per_s": fl["value"], "effective_events_per_s": fl["effective_events_per_s"],
             "ms_per_step": fl["ms_per_step"],
@@ -835,8 +847,10 @@ def main():
     if not args.no_cpu_baseline:
         it_s, ev_s = CPU_SAMPLE[args.workload]
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters or it_s, min(args.cpu_events or ev_s, 10 * N))
+        progress("oracle on one core timed")
         it_a, ev_a = CPU_SAMPLE_ALL_CORES[args.workload]
         line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(cfg, it_a, min(ev_a, 10 * N))
+        progress("oracle on all cores timed")
         line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
