@@ -249,21 +249,51 @@ __host__ __device__ __forceinline__ double fx2_value(long long D0, long long D1,
 }
 
 // ---------------------------------------------------------------------------
-// wave64 reductions (butterfly over all 64 lanes)
+// wave64 reductions by DPP (row shifts 1, 2, 4, 8 within each row of 16 lanes, then
+// row 0 into row 1 and row 2 into row 3, then rows 0-1 into rows 2-3): the moves stay in
+// the VALU, where a butterfly's cross-lane permutes go through the LDS unit and wait
+// for it.  Lane 63 ends with the total, which is read out for every lane (call with
+// all 64 lanes active; integer sums and maxima are exact, so the order is free)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ long long wave_sum_i64(long long v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xf, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(v >> 32), CTRL, ROW_MASK, 0xf, BOUND);
+  return (static_cast<unsigned long long>(static_cast<unsigned int>(hi)) << 32) | static_cast<unsigned int>(lo);
+}
+
+__device__ __forceinline__ unsigned long long read_lane63_u64(unsigned long long v) {
+  const unsigned int lo = __builtin_amdgcn_readlane(static_cast<int>(v), 63);
+  const unsigned int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), 63);
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long x) {
+  unsigned long long v = static_cast<unsigned long long>(x);  // two's complement: wrap-around sums
+  v += dpp_u64<0x111, 0xf, true>(v);
+  v += dpp_u64<0x112, 0xf, true>(v);
+  v += dpp_u64<0x114, 0xf, true>(v);
+  v += dpp_u64<0x118, 0xf, true>(v);
+  v += dpp_u64<0x142, 0xa, false>(v);
+  v += dpp_u64<0x143, 0xc, false>(v);
+  return static_cast<long long>(read_lane63_u64(v));
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(v, off, 64);
-    v = o > v ? o : v;
-  }
-  return v;
+  unsigned long long o;
+  o = dpp_u64<0x111, 0xf, true>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x112, 0xf, true>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x114, 0xf, true>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x118, 0xf, true>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x142, 0xa, false>(v);
+  v = o > v ? o : v;
+  o = dpp_u64<0x143, 0xc, false>(v);
+  v = o > v ? o : v;
+  return read_lane63_u64(v);
 }
 
 }  // namespace vg

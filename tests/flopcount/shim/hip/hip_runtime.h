@@ -14,3 +14,6 @@
 #define __builtin_amdgcn_rsq(x) fc_rsq(x)
 #define __builtin_amdgcn_bitop3_b32(a, b, c, imm) fc_xor3(a, b, c)
 #define VG_OPAQUE_SGPR(x) (void)(x)
+// cross-lane builtins of the wave reductions (not on the counted path): one lane
+#define __builtin_amdgcn_update_dpp(old, v, ctrl, rmask, bmask, bound) (v)
+#define __builtin_amdgcn_readlane(v, lane) (v)
