@@ -291,7 +291,7 @@ def bench_paper_schedule(args):
                      cfg["params"], max_events=max(sched))
     s0 = g.get_state()
 
-    def one():
+    def one_by_one():
         g.set_state(s0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -301,11 +301,26 @@ def bench_paper_schedule(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    Wn = warm_up(args, one)
-    times = [one() for _ in range(args.steps)]
+    def recorded():
+        # the same schedule through vegas_run_schedule: recorded as a HIP graph on the
+        # first call, replayed from the restored state on every later one
+        g.set_state(s0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.run_schedule(sched)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    Wn = warm_up(args, one_by_one)
+    times_calls = [one_by_one() for _ in range(args.steps)]
+    r_calls = g.result(first=first)
+    warm_up(args, recorded)
+    times = [recorded() for _ in range(args.steps)]
     T = sum(times)
     r, rall = g.result(first=first), g.result()
+    assert r == r_calls, "the recorded schedule must give the plain calls' result"
     eps = r["sigma"] / abs(r["I"])
+    one = one_by_one  # the timing pass binds HIP events to each dispatch: calls one by one
     # event-kernel time per schedule from a pass with HIP events bound to each dispatch
     g.set_timing(True)
     g.stage_times(reset=True)
@@ -335,6 +350,13 @@ def bench_paper_schedule(args):
         "integral_all_iterations_pb": rall["I"],
         "kernel_ms_per_step": {k: v[0] for k, v in st.items()},
         "roofline": roof,
+        "calls_one_by_one": {"ms_per_step": sum(times_calls) / args.steps * 1e3,
+                             "ms_per_step_min_avg_max": [min(times_calls) * 1e3,
+                                                         sum(times_calls) / args.steps * 1e3,
+                                                         max(times_calls) * 1e3],
+                             "ms_per_iteration": sum(times_calls) / args.steps / len(sched) * 1e3,
+                             "events_per_s": args.steps * sum(sched) / sum(times_calls)},
+        "path": "vegas_run_schedule (the schedule's launches recorded once as a HIP graph, replayed)",
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -156,6 +156,22 @@ int vegas_iterate(vegas_handle h, int64_t n_events, vegas_iter_result *out);
  * Errors: VEGAS_ESTATE (no iteration since init or since the last refine). */
 int vegas_refine(vegas_handle h);
 
+/* A schedule of count iterations (Sec. 3.2: the paper's timing runs are a warm-up
+ * stage and a production stage of fixed event counts), iteration j with
+ * n_events[j] events and, if refine != 0, vegas_refine after each: the same results,
+ * bit for bit, as those calls made one by one.  With small iterations each step is a
+ * few short kernels, so the first call records the schedule's launches as a HIP graph
+ * on the handle's stream and a later call with the same event counts, from the same
+ * host state (iteration index, buffer roles, fold scales, launch settings), replays it
+ * with one launch; any other call records anew (one recorded schedule per handle).
+ * Stratified or timed handles run the calls one by one.  Asynchronous on the stream.
+ * n_events (host, count entries) is read during the call only.
+ * Errors: VEGAS_EINVAL (count < 1, an entry < 2 or above max_events), VEGAS_ESTATE
+ * (the schedule would exceed VEGAS_MAX_ITER iterations, or a refinement without an
+ * iteration), VEGAS_EHIP (also when the recording fails; the handle's state is then
+ * unchanged). */
+int vegas_run_schedule(vegas_handle h, const int64_t *n_events, int32_t count, int32_t refine);
+
 /* Inverse-variance combination of all iterations so far (Sec. 2.1: several
  * iterations of sets of events): integral, its error and chi^2 per degree of
  * freedom.  If an iteration has zero variance the plain mean of such

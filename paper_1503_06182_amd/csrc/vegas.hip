@@ -1733,6 +1733,13 @@ struct vegas_state {
   size_t gbuf_doubles;
   double* scratch;            // this device's copy of the static scratch array (vegas_grad_noalloc)
   std::string scratch_error;  // why its address could not be taken, if it could not
+  // a recorded schedule (vegas_run_schedule): its event counts, the host state it starts
+  // from and the one it leaves, and the instantiated graph of its launches
+  hipGraphExec_t sched_exec = nullptr;
+  hipStream_t cap_stream = nullptr;  // the recording's own stream (the caller's may be the null stream)
+  std::vector<int64_t> sched_n;
+  int sched_refine = 0;
+  unsigned char sched_pre[256], sched_post[256];
 };
 
 #define VG_HIP(call)                                                  \
@@ -2082,6 +2089,8 @@ int vegas_destroy(vegas_handle h) {
     (void)hipEventDestroy(p.second.second);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->sched_exec) (void)hipGraphExecDestroy(h->sched_exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->gbuf) (void)hipFree(h->gbuf);
   if (h->s_sig) (void)hipFree(h->s_sig);
   if (h->s_cnt) (void)hipFree(h->s_cnt);
@@ -2398,6 +2407,142 @@ int vegas_refine(vegas_handle h) {
   }
   h->spec_ready = false;
   h->have_hist = false;
+  return VEGAS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// the host state that iterations and refinements read and leave behind, packed
+// field by field (no padding bytes) so that two states compare by their bytes
+struct HostIter {
+  unsigned char bytes[256];
+  size_t n = 0;
+  template <class T>
+  void put(const T& v) {
+    std::memcpy(bytes + n, &v, sizeof(T));
+    n += sizeof(T);
+  }
+};
+static_assert(sizeof(DevBufs) + 64 <= 256, "host iteration state exceeds its buffer");
+
+HostIter host_iter(const vegas_state* h) {
+  HostIter s;
+  s.put(h->b);
+  s.put(h->iter);
+  s.put(h->last_n);
+  s.put(h->last_strata_npc);
+  const unsigned char f[8] = {h->have_hist, h->any_iter, h->last_flow, h->spec_ready,
+                              h->obs_have,  h->scale_valid, h->s_have_sig, 0};
+  s.put(f);
+  // the configuration a launch sequence depends on
+  s.put(h->wpb);
+  s.put(h->max_blocks);
+  s.put(h->nobs);
+  s.put(h->obs_first);
+  return s;
+}
+
+void set_host_iter(vegas_state* h, const unsigned char* p) {
+  size_t n = 0;
+  auto get = [&](auto& v) {
+    std::memcpy(&v, p + n, sizeof(v));
+    n += sizeof(v);
+  };
+  get(h->b);
+  get(h->iter);
+  get(h->last_n);
+  get(h->last_strata_npc);
+  unsigned char f[8];
+  get(f);
+  h->have_hist = f[0];
+  h->any_iter = f[1];
+  h->last_flow = f[2];
+  h->spec_ready = f[3];
+  h->obs_have = f[4];
+  h->scale_valid = f[5];
+  h->s_have_sig = f[6];
+}
+
+int run_schedule_eager(vegas_handle h, const int64_t* n_events, int32_t count, int32_t refine) {
+  for (int32_t j = 0; j < count; ++j) {
+    const int rc = run_iteration(h, n_events[j], nullptr, nullptr, nullptr);
+    if (rc != VEGAS_OK) return rc;
+    if (refine) {
+      const int rr = vegas_refine(h);
+      if (rr != VEGAS_OK) return rr;
+    }
+  }
+  return VEGAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vegas_run_schedule(vegas_handle h, const int64_t* n_events, int32_t count, int32_t refine) {
+  if (!h || !n_events || count < 1 || count > VEGAS_MAX_ITER) return VEGAS_EINVAL;
+  for (int32_t j = 0; j < count; ++j)
+    if (n_events[j] < 2 || n_events[j] > h->maxN) return VEGAS_EINVAL;
+  if (static_cast<int64_t>(h->iter) + count > VEGAS_MAX_ITER) return VEGAS_ESTATE;
+  // stratified runs may allocate and synchronise on the way, and timed runs bind events
+  // to each launch: both run as plain calls
+  if (h->strata_m > 0 || h->timing != 0) return run_schedule_eager(h, n_events, count, refine);
+  const HostIter pre = host_iter(h);
+  const std::vector<int64_t> ns(n_events, n_events + count);
+  if (h->sched_exec && h->sched_refine == refine && h->sched_n == ns &&
+      std::memcmp(h->sched_pre, pre.bytes, pre.n) == 0) {
+    VG_HIP(hipGraphLaunch(h->sched_exec, h->stream));
+    set_host_iter(h, h->sched_post);
+    return VEGAS_OK;
+  }
+  if (h->sched_exec) {
+    VG_HIP(hipGraphExecDestroy(h->sched_exec));
+    h->sched_exec = nullptr;
+  }
+  // record: the same calls, captured instead of executed -- on a stream of the
+  // library's own (a capture cannot begin on the null stream), which stands in for the
+  // handle's stream while the calls are made; the graph then runs on the handle's stream
+  if (!h->cap_stream) VG_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  const hipStream_t user_stream = h->stream;
+  h->stream = h->cap_stream;
+  hipError_t eb = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+  int rc = VEGAS_OK;
+  hipGraph_t g = nullptr;
+  hipError_t ec = hipSuccess;
+  if (eb == hipSuccess) {
+    rc = run_schedule_eager(h, n_events, count, refine);
+    ec = hipStreamEndCapture(h->stream, &g);
+  }
+  h->stream = user_stream;
+  if (eb != hipSuccess) {
+    set_host_iter(h, pre.bytes);
+    g_last_hip_error = std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb);
+    return VEGAS_EHIP;
+  }
+  if (rc != VEGAS_OK || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    set_host_iter(h, pre.bytes);
+    if (rc != VEGAS_OK) return rc;
+    g_last_hip_error = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+    return VEGAS_EHIP;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    set_host_iter(h, pre.bytes);
+    g_last_hip_error = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+    return VEGAS_EHIP;
+  }
+  const HostIter post = host_iter(h);
+  h->sched_exec = x;
+  h->sched_n = ns;
+  h->sched_refine = refine;
+  std::memcpy(h->sched_pre, pre.bytes, pre.n);
+  std::memcpy(h->sched_post, post.bytes, post.n);
+  VG_HIP(hipGraphLaunch(h->sched_exec, h->stream));
   return VEGAS_OK;
 }
 

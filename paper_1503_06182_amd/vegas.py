@@ -24,7 +24,8 @@ MAX_OBS_BINS = 254
 SCRATCH_DOUBLES = 1 << 21          # static scratch of the allocation-free calls
 ETOOBIG = -5                       # request larger than that scratch
 
-EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_result",
+EXPORTS = ["vegas_workspace_size", "vegas_init", "vegas_iterate", "vegas_refine", "vegas_run_schedule",
+           "vegas_result",
            "vegas_result_from", "vegas_set_observable", "vegas_get_observable", "vegas_set_strata",
            "vegas_set_strata_beta", "vegas_get_strata_counts",
            "vegas_get_grid", "vegas_set_grid", "vegas_get_hist", "vegas_get_weights",
@@ -71,6 +72,7 @@ def load(path: str = LIB_PATH):
     L.vegas_init.argtypes = [C.POINTER(Config), i64, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.vegas_iterate.argtypes = [vp, i64, C.POINTER(IterResult)]
     L.vegas_refine.argtypes = [vp]
+    L.vegas_run_schedule.argtypes = [vp, C.POINTER(i64), i32, i32]
     L.vegas_result.argtypes = [vp, dp, dp, dp, C.POINTER(i32)]
     L.vegas_result_from.argtypes = [vp, i32, dp, dp, dp, C.POINTER(i32)]
     L.vegas_set_observable.argtypes = [vp, i32, C.c_double, C.c_double, i32]
@@ -197,6 +199,13 @@ class Integrator:
 
     def refine(self):
         _check(self._L.vegas_refine(self._h), "vegas_refine")
+
+    def run_schedule(self, n_events, refine=True):
+        """Iterations of n_events[j] events (and a refinement after each): the first call
+        records the launches as a HIP graph, a repeat from the same state replays it."""
+        arr = (C.c_int64 * len(n_events))(*[int(n) for n in n_events])
+        _check(self._L.vegas_run_schedule(self._h, arr, len(n_events), 1 if refine else 0),
+               "vegas_run_schedule")
 
     def result(self, first=0):
         """Combined estimate over iterations first .. last (first > 0 drops warm-up iterations)."""
