@@ -34,13 +34,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Work per event of the event kernel (the dominant kernel).
-#  algorithmic_f64: the FP64 FLOPs of the kernels' formulation per event, counted on the
-#    host by tests/flopcount/count.cpp (the integrand headers compiled with a counting
-#    scalar: add, sub, mul = 1, fma = 2, each hardware reciprocal / inverse-square-root
-#    estimate 1, each library function at OCML_FLOP_PER_CALL; work on uniform values not
-#    counted), through a grid the oracle adapted for five iterations; plus the grid map,
-#    the uniforms and the accumulation (S1, w^2, S2, one addition per dimension).
-#    tests/test_flop_count.py recounts it.  This is the roofline's numerator.
+#  algorithmic_f64: the FP64 FLOPs of the method per event with the amplitudes as the
+#    kernels state them, counted on the host by tests/flopcount/count.cpp (the integrand
+#    headers compiled with a counting scalar: add, sub, mul = 1, fma = 2; each evaluation
+#    of a mathematical function -- division or reciprocal, square root, tan, sine and
+#    cosine of an angle, atan, log, exp, expm1 -- at what one call of the library's
+#    version costs, OCML_FLOP_PER_CALL, however the kernel evaluates it; work on uniform
+#    values not counted), through a grid the oracle adapted for five iterations; plus the
+#    grid map, the uniforms and the accumulation (S1, w^2, S2, one addition per
+#    dimension).  tests/test_flop_count.py recounts it.  This is the roofline's numerator.
 #  f64 / f32: the FLOPs the kernel as built executes per event, from the rocprofv3
 #    counter SQ_INSTS_VALU_FLOPS_FP64 (FP32) x 64 lanes / events (add, mul,
 #    transcendental instruction = 1, fma = 2), reported beside it as the VALU
@@ -50,19 +52,21 @@ sys.path.insert(0, ROOT)
 #    x 2 + WRITE_SIZE x 1 KiB, the factors read from a plain 1 GiB device copy).
 # The counter summaries are under profiles/.
 EVENT_KERNEL_WORK = {
-    ("w_plus", "fp64"): {"algorithmic_f64": 326.6, "f64": 345.3, "f32": 0.0, "traffic": 25_497_497,
+    ("w_plus", "fp64"): {"algorithmic_f64": 373.5, "f64": 345.3, "f32": 0.0, "traffic": 25_497_497,
                          "events": 1_000_000},
-    ("ww_4l", "fp64"): {"algorithmic_f64": 1128.2, "f64": 1153.7, "f32": 0.0, "traffic": 180_147_627,
+    ("ww_4l", "fp64"): {"algorithmic_f64": 1360.7, "f64": 1153.7, "f32": 0.0, "traffic": 180_147_627,
                         "events": 10_000_000},
     ("ww_4l", "fp32me"): {"algorithmic_f64": None, "f64": 684.6, "f32": 506.0, "traffic": None,
                           "events": 10_000_000},
-    ("ww_had", "fp64"): {"algorithmic_f64": 1423.2, "f64": 1437.8, "f32": 0.0, "traffic": 216_933_959,
+    ("ww_had", "fp64"): {"algorithmic_f64": 1687.8, "f64": 1437.8, "f32": 0.0, "traffic": 216_933_959,
                          "events": 10_000_000},
 }
-# FP64 FLOPs of one call of the library functions the integrands use, measured on gfx950
-# with tests/flopcount/ocml_price.hip under rocprofv3 (SQ_INSTS_VALU_FLOPS_FP64 x 64 /
-# calls, arguments spread over the ranges the integrands pass)
-OCML_FLOP_PER_CALL = {"atan": 58.0, "log": 79.0, "exp": 27.0, "expm1": 32.0}
+# FP64 FLOPs of one call of the library's version of each mathematical function the
+# integrands evaluate, measured on gfx950 with tests/flopcount/ocml_price.hip under
+# rocprofv3 (SQ_INSTS_VALU_FLOPS_FP64 x 64 / calls, arguments spread over the ranges the
+# integrands pass; div is 1.0 / x, sincos one sincos() call)
+OCML_FLOP_PER_CALL = {"atan": 58.0, "log": 79.0, "exp": 27.0, "expm1": 32.0, "tan": 88.0, "sincos": 57.0,
+                      "sqrt": 17.0, "div": 14.0}
 # HBM bytes of one histogram-stage launch (k_accsum), from the same counters, at the
 # workload's default event count
 HIST_STAGE_TRAFFIC = {("w_plus", 1_000_000): 13_565_011, ("ww_4l", 10_000_000): 20_432_973}

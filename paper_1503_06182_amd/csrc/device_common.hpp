@@ -13,6 +13,14 @@ namespace vg {
 #define VG_OPAQUE_SGPR(x) asm volatile("" : "+s"(x))
 #endif
 
+// marks a routine that evaluates a mathematical function (division, square root, tan,
+// ...): nothing in the GPU build; the host build that counts the kernels' FLOPs prices
+// the call at what the library's version of that function costs and does not count
+// the routine's own operations
+#ifndef VG_PRICED
+#define VG_PRICED(kind, x)
+#endif
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Every event owns its
 // counter (event index, iteration, call), so the set of events of an iteration
@@ -89,6 +97,7 @@ __device__ __forceinline__ void event_uniforms(uint64_t seed, uint32_t it, uint6
 // ---------------------------------------------------------------------------
 // 1 / d for normal d (either sign)
 __device__ __forceinline__ double rcp_nr(double d) {
+  VG_PRICED(div, d);
   double r = __builtin_amdgcn_rcp(d);
   double e = __fma_rn(-d, r, 1.0);
   r = __fma_rn(r, e, r);
@@ -98,6 +107,7 @@ __device__ __forceinline__ double rcp_nr(double d) {
 
 // n / d for normal d: n times the reciprocal, then one residual correction
 __device__ __forceinline__ double div_nr(double n, double d) {
+  VG_PRICED(div, d);
   const double r = rcp_nr(d);
   const double q = n * r;
   return __fma_rn(__fma_rn(-d, q, n), r, q);
@@ -105,6 +115,7 @@ __device__ __forceinline__ double div_nr(double n, double d) {
 
 // sqrt(a) and 1 / sqrt(a) for normal a > 0 (Goldschmidt: g -> sqrt(a), h -> 1/(2 sqrt(a)))
 __device__ __forceinline__ void sqrt_rsqrt_nr(double a, double& g, double& inv) {
+  VG_PRICED(sqrt_div, a);
   const double y = __builtin_amdgcn_rsq(a);
   g = a * y;
   double h = 0.5 * y;
@@ -121,6 +132,7 @@ __device__ __forceinline__ void sqrt_rsqrt_nr(double a, double& g, double& inv) 
 
 // sqrt(a) for a >= 0 (0 for a == 0)
 __device__ __forceinline__ double sqrt_nr(double a) {
+  VG_PRICED(sqrt, a);
   const double y = __builtin_amdgcn_rsq(a);
   double g = a * y;
   double h = 0.5 * y;

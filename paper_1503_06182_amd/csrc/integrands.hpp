@@ -57,40 +57,12 @@ struct PhysConst {
   double ga[16], gw[16];
 };
 
-// ---------------------------------------------------------------------------
-// sin and cos of |y| <= pi/4 by their Taylor series up to y^17 and y^18 (the next
-// terms are below 2^-62 of the sums there)
-// ---------------------------------------------------------------------------
+// a polynomial coefficient materialised in a scalar register pair where it is used: an
+// FMA then takes it as its SGPR operand, instead of a copy of a loop-invariant vector
+// register into the accumulating FMA's destination before each step
 __device__ __forceinline__ double poly_coef(double c) {
-  // a coefficient materialised in a scalar register pair where it is used: an FMA then
-  // takes it as its SGPR operand, instead of a copy of a loop-invariant vector register
-  // into the accumulating FMA's destination before each step
   VG_OPAQUE_SGPR(c);
   return c;
-}
-
-__device__ __forceinline__ void sincos_taylor(double y, double& sn, double& cs) {
-  const double y2 = y * y;
-  // sin y = y + y^3 sum_k (-1)^(k+1) y^2k / (2k + 3)!, cos y = 1 + y^2 sum_k (-1)^(k+1) y^2k / (2k + 2)!
-  double ps = poly_coef(1.0 / 355687428096000.0);             // 1/17!
-  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 1307674368000.0));  // 1/15!
-  ps = __fma_rn(ps, y2, poly_coef(1.0 / 6227020800.0));      // 1/13!
-  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 39916800.0));       // 1/11!
-  ps = __fma_rn(ps, y2, poly_coef(1.0 / 362880.0));          // 1/9!
-  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 5040.0));           // 1/7!
-  ps = __fma_rn(ps, y2, poly_coef(1.0 / 120.0));             // 1/5!
-  ps = __fma_rn(ps, y2, poly_coef(-1.0 / 6.0));              // 1/3!
-  double pc = poly_coef(-1.0 / 6402373705728000.0);          // 1/18!
-  pc = __fma_rn(pc, y2, poly_coef(1.0 / 20922789888000.0));  // 1/16!
-  pc = __fma_rn(pc, y2, poly_coef(-1.0 / 87178291200.0));    // 1/14!
-  pc = __fma_rn(pc, y2, poly_coef(1.0 / 479001600.0));       // 1/12!
-  pc = __fma_rn(pc, y2, poly_coef(-1.0 / 3628800.0));        // 1/10!
-  pc = __fma_rn(pc, y2, poly_coef(1.0 / 40320.0));           // 1/8!
-  pc = __fma_rn(pc, y2, poly_coef(-1.0 / 720.0));            // 1/6!
-  pc = __fma_rn(pc, y2, poly_coef(1.0 / 24.0));              // 1/4!
-  pc = __fma_rn(pc, y2, -0.5);                               // 1/2!
-  sn = __fma_rn(y * y2, ps, y);
-  cs = __fma_rn(y2, pc, 1.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -103,6 +75,7 @@ __device__ __forceinline__ void sincos_taylor(double y, double& sn, double& cs) 
 // Relative error about 2 units in the last place (checked on the CPU against atanl).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double atan_rr(double v) {
+  VG_PRICED(atan, v);
   constexpr double kT3p8 = 2.41421356237309504880, kPio2 = 1.57079632679489661923,
                    kPio4 = 0.78539816339744830962, kMoreBits = 6.123233995736765886130e-17;
   const double a = fabs(v);
@@ -127,19 +100,52 @@ __device__ __forceinline__ double atan_rr(double v) {
 // ---------------------------------------------------------------------------
 // tan(x) for |x| < pi/2 (the Breit-Wigner map's arguments): |x| > pi/4 is folded to
 // y = pi/2 - |x| (pi/2 as the sum of two binary64 numbers; the first difference is
-// exact, both being within a factor 2), then tan = sin/cos or cos/sin of y.  A few
-// units in the last place, against half a unit for the library's general tan, at
-// well under half its instructions.
+// exact, both being within a factor 2), and tan y = y + y z P(z)/Q(z), z = y^2, with the
+// degree-2 / 4 rational fit of Moshier's Cephes library (tan.c) on |y| <= pi/4, taken
+// here as N/Q with N = y (Q + z P): one division gives tan y = N/Q or cot y = Q/N.  A
+// few units in the last place (checked on the CPU against tanl).
 // ---------------------------------------------------------------------------
+// sin y and cos y for |y| <= pi/4 by the minimax polynomials of the fdlibm / FreeBSD msun
+// kernels (k_sin.c, k_cos.c; Sun Microsystems): sin y = y + y^3 (S1 + z R(z)), z = y^2,
+// and cos y = 1 - z/2 + z^2 C(z), the leading 1 - z/2 carried with its rounding error.
+// About one unit in the last place (checked on the CPU against sinl and cosl).
+__device__ __forceinline__ void sincos_pio4(double y, double& sn, double& cs) {
+  const double z = y * y, w = z * z;
+  const double rs = __fma_rn(z, __fma_rn(z, poly_coef(2.75573137070700676789e-06), poly_coef(-1.98412698298579493134e-04)),
+                             poly_coef(8.33333333332248946124e-03)) +
+                    z * w * __fma_rn(z, poly_coef(1.58969099521155010221e-10), poly_coef(-2.50507602534068634195e-08));
+  sn = __fma_rn(z * y, __fma_rn(z, rs, poly_coef(-1.66666666666666324348e-01)), y);
+  const double rc = z * __fma_rn(z, __fma_rn(z, poly_coef(2.48015872894767294178e-05), poly_coef(-1.38888888888741095749e-03)),
+                                 poly_coef(4.16666666666666019037e-02)) +
+                    w * w * __fma_rn(z, __fma_rn(z, poly_coef(-1.13596475577881948265e-11), poly_coef(2.08757232129817482790e-09)),
+                                     poly_coef(-2.75573143513906633035e-07));
+  const double hz = 0.5 * z, v = 1.0 - hz;
+  cs = v + (((1.0 - v) - hz) + z * rc);
+}
+
+// tan y = nm / q on |y| <= pi/4 (the rational fit above)
+__device__ __forceinline__ void tan_nq(double y, double& nm, double& q) {
+  const double z = y * y;
+  double p = poly_coef(-1.30936939181383777646e4);
+  p = __fma_rn(p, z, poly_coef(1.15351664838587416140e6));
+  p = __fma_rn(p, z, poly_coef(-1.79565251976484877988e7));
+  q = z + poly_coef(1.36812963470692954678e4);
+  q = __fma_rn(q, z, poly_coef(-1.32089234440210967447e6));
+  q = __fma_rn(q, z, poly_coef(2.50083801823357915839e7));
+  q = __fma_rn(q, z, poly_coef(-5.38695755929454629881e7));
+  nm = y * __fma_rn(z, p, q);
+}
+
 __device__ __forceinline__ double tan_halfpi(double x) {
+  VG_PRICED(tan, x);
   constexpr double kPio4 = 0.78539816339744830962, kPio2Hi = 1.5707963267948966,
                    kPio2Lo = 6.123233995736766e-17;
   const double a = fabs(x);
   const bool big = a > kPio4;
   const double y = big ? (kPio2Hi - a) + kPio2Lo : a;
-  double sn, cs;
-  sincos_taylor(y, sn, cs);
-  const double t = big ? div_nr(cs, sn) : div_nr(sn, cs);
+  double nm, q;
+  tan_nq(y, nm, q);
+  const double t = big ? div_nr(q, nm) : div_nr(nm, q);
   return copysign(t, x);
 }
 
@@ -541,10 +547,11 @@ __device__ __forceinline__ void boost_pair(const R Q[4], R m, R im, const R k[4]
 // (r exact: x and q/4 are within a factor 2 of each other when q > 0), y = 2 pi r, then
 // the rotation by q quarter turns
 __device__ __forceinline__ void sincos_2pi(double x, double& s, double& c) {
+  VG_PRICED(sincos, x);
   const double q = rint(4.0 * x);
   const double y = (x - 0.25 * q) * 6.283185307179586477;
   double sn, cs;
-  sincos_taylor(y, sn, cs);
+  sincos_pio4(y, sn, cs);
   const int qi = static_cast<int>(q) & 3;
   const double a = (qi & 1) ? cs : sn, b = (qi & 1) ? sn : cs;
   s = qi >= 2 ? -a : a;

@@ -1,12 +1,17 @@
-// count.cpp -- FLOPs per event of the kernels' own formulation, counted on the host.
+// count.cpp -- FLOPs per event of the kernels' formulation, counted on the host.
 //
 // The integrand headers of the GPU library (integrands.hpp, device_common.hpp) are
 // compiled for the host with binary64 replaced by a counting scalar: every addition,
 // subtraction and multiplication counts 1, every fused multiply-add 2, each hardware
-// reciprocal / inverse-square-root estimate 1 (the rocprof counter's convention), and
-// each call of a library function (log, exp, expm1; atan, which the integrands no
-// longer call, is kept for comparison) its price in FP64 FLOPs
-// measured on gfx950 with ocml_price.hip (given on the command line).  Operations whose
+// reciprocal / inverse-square-root estimate outside a priced routine 1 (the rocprof
+// counter's convention).  Each evaluation of a mathematical function -- a division or
+// reciprocal, a square root, tan, the sine and cosine of one angle, atan, log, exp,
+// expm1 -- counts what one call of the library's version of it costs in FP64 FLOPs on
+// gfx950 (measured with ocml_price.hip, given on the command line), whatever the kernel
+// uses to evaluate it: the routines the headers mark with VG_PRICED are priced so and
+// their own operations are not counted, and so is every '/' on per-event values.  The
+// count is therefore the method's arithmetic with the amplitudes as the kernels state
+// them, independent of how the kernels evaluate the functions.  Operations whose
 // operands are all uniform (literals, the configuration's constants) are not counted:
 // the GPU computes them once per thread, outside the event loop.  Comparisons, selects,
 // sign changes, truncations and integer work count nothing.  The event's point comes
@@ -35,7 +40,10 @@ struct Tally {
   double lib = 0.0;     // FLOPs of library-function calls
 };
 inline Tally g;
-inline double price_atan = 0, price_log = 0, price_exp = 0, price_expm1 = 0;
+inline double price_atan = 0, price_log = 0, price_exp = 0, price_expm1 = 0, price_tan = 0, price_sincos = 0,
+              price_sqrt = 0, price_div = 0, price_sqrt_div = 0;
+// > 0 inside a priced routine: its own operations are not counted
+inline int suspend = 0;
 
 struct F64 {
   double v;
@@ -50,12 +58,26 @@ struct F64 {
 };
 
 constexpr void count(double n, bool uniform) {
-  if (!std::is_constant_evaluated() && !uniform) g.flop += n;
+  if (!std::is_constant_evaluated() && !uniform && suspend == 0) g.flop += n;
 }
+inline void priced(double price, bool uniform) {
+  if (!uniform && suspend == 0) g.lib += price, g.flop += price;
+}
+// a routine that evaluates a mathematical function: priced once, its body not counted
+struct Priced {
+  Priced(double price, bool uniform) {
+    priced(price, uniform);
+    ++suspend;
+  }
+  ~Priced() { --suspend; }
+};
 constexpr F64 operator+(F64 a, F64 b) { count(1, a.u && b.u); return {a.v + b.v, a.u && b.u}; }
 constexpr F64 operator-(F64 a, F64 b) { count(1, a.u && b.u); return {a.v - b.v, a.u && b.u}; }
 constexpr F64 operator*(F64 a, F64 b) { count(1, a.u && b.u); return {a.v * b.v, a.u && b.u}; }
-constexpr F64 operator/(F64 a, F64 b) { count(1, a.u && b.u); return {a.v / b.v, a.u && b.u}; }
+constexpr F64 operator/(F64 a, F64 b) {
+  if (!std::is_constant_evaluated()) priced(price_div, a.u && b.u);
+  return {a.v / b.v, a.u && b.u};
+}
 constexpr F64 operator-(F64 a) { return {-a.v, a.u}; }
 inline F64& operator+=(F64& a, F64 b) { return a = a + b; }
 inline F64& operator-=(F64& a, F64 b) { return a = a - b; }
@@ -74,11 +96,11 @@ inline F64 fma_c(F64 a, F64 b, F64 c) {
   return {std::fma(a.v, b.v, c.v), uni};
 }
 inline F64 hw_est(double v, bool uni) {
-  if (!uni) g.trans += 1, g.flop += 1;
+  if (!uni && suspend == 0) g.trans += 1, g.flop += 1;
   return {v, uni};
 }
 inline F64 lib_call(double v, bool uni, double price) {
-  if (!uni) g.lib += price, g.flop += price;
+  priced(price, uni);
   return {v, uni};
 }
 }  // namespace fc
@@ -208,10 +230,10 @@ vg::PhysConst wplus_const() {
 }  // namespace
 
 // usage: count <process: ww_4l | ww_had | w_plus> <grid file: D lines of n + 1 edges> <events>
-//              <atan> <log> <exp> <expm1>   (FP64 FLOPs per call)
+//              <atan> <log> <exp> <expm1> <tan> <sincos> <sqrt> <div>   (FP64 FLOPs per call)
 int main(int argc, char** argv) {
-  if (argc != 8) {
-    std::fprintf(stderr, "usage: count process gridfile events atan log exp expm1\n");
+  if (argc != 12) {
+    std::fprintf(stderr, "usage: count process gridfile events atan log exp expm1 tan sincos sqrt div\n");
     return 2;
   }
   const std::string proc = argv[1];
@@ -233,6 +255,11 @@ int main(int argc, char** argv) {
   fc::price_log = std::atof(argv[5]);
   fc::price_exp = std::atof(argv[6]);
   fc::price_expm1 = std::atof(argv[7]);
+  fc::price_tan = std::atof(argv[8]);
+  fc::price_sincos = std::atof(argv[9]);
+  fc::price_sqrt = std::atof(argv[10]);
+  fc::price_div = std::atof(argv[11]);
+  fc::price_sqrt_div = fc::price_sqrt + fc::price_div;  // a square root and its reciprocal
   const vg::PhysConst c = wp ? wplus_const() : ww_const(had);
   double per[4] = {0, 0, 0, 0};  // uniforms + grid map, integrand, weight + accumulation
   long nonzero = 0;

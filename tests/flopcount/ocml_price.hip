@@ -29,19 +29,33 @@ PRICE_KERNEL(k_tan, tan(x))
 PRICE_KERNEL(k_sqrt, sqrt(x))
 PRICE_KERNEL(k_div, 1.0 / x)
 
+// the sine and cosine of one angle (both stored: the second half of o)
+__global__ void k_sincos(const double* __restrict__ a, double* __restrict__ o, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double s, c;
+    sincos(a[i], &s, &c);
+    o[i] = s;
+    o[n + i] = c;
+  }
+}
+
 int main() {
   const int n = 1 << 22;
   // arguments in the integrands' ranges: atan of (m^2 - M^2)/(M G) for masses from 0 to
   // sqrt(shat) (about -40 .. 1500), log of tau = m^2 / S (1e-9 .. 1), exp of ln tau,
-  // expm1 of x ln tau (-20 .. 0), tan on (-pi/2, pi/2), sqrt and reciprocal of (0.1, 1e4)
+  // expm1 of x ln tau (-20 .. 0), tan on (-pi/2, pi/2), sqrt and reciprocal of (0.1, 1e4),
+  // sincos of an azimuth on [0, 2 pi)
   struct Case { const char* name; void (*k)(const double*, double*, int); double lo, hi; bool logscale; };
   const Case cases[] = {{"identity", k_identity, 0.1, 10.0, false}, {"atan", k_atan, -40.0, 1500.0, false},
                         {"log", k_log, 1e-9, 1.0, true},            {"exp", k_exp, -20.0, 0.0, false},
                         {"expm1", k_expm1, -20.0, 0.0, false},      {"tan", k_tan, -1.5, 1.5, false},
-                        {"sqrt", k_sqrt, 0.1, 1e4, true},           {"div", k_div, 0.1, 1e4, true}};
+                        {"sqrt", k_sqrt, 0.1, 1e4, true},           {"div", k_div, 0.1, 1e4, true},
+                        {"sincos", k_sincos, 0.0, 6.283185307179586, false}};
   std::vector<double> h(n);
   double *a = nullptr, *o = nullptr;
-  if (hipMalloc(&a, sizeof(double) * n) != hipSuccess || hipMalloc(&o, sizeof(double) * n) != hipSuccess) return 1;
+  if (hipMalloc(&a, sizeof(double) * n) != hipSuccess || hipMalloc(&o, 2 * sizeof(double) * n) != hipSuccess)
+    return 1;
   for (const Case& c : cases) {
     for (int i = 0; i < n; ++i) {
       const double t = (i + 0.5) / n;

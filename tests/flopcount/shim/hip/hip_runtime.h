@@ -14,6 +14,8 @@
 #define __builtin_amdgcn_rsq(x) fc_rsq(x)
 #define __builtin_amdgcn_bitop3_b32(a, b, c, imm) fc_xor3(a, b, c)
 #define VG_OPAQUE_SGPR(x) (void)(x)
+// a mathematical function priced at its library cost, its own operations not counted
+#define VG_PRICED(kind, x) ::fc::Priced vg_priced_(::fc::price_##kind, (x).u)
 // cross-lane builtins of the wave reductions (not on the counted path): one lane
 #define __builtin_amdgcn_update_dpp(old, v, ctrl, rmask, bmask, bound) (v)
 #define __builtin_amdgcn_readlane(v, lane) (v)

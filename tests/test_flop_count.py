@@ -48,6 +48,14 @@ def _prices():
     return bench.OCML_FLOP_PER_CALL
 
 
+KINDS = ("atan", "log", "exp", "expm1", "tan", "sincos", "sqrt", "div")
+
+
+def prices(p, **over):
+    """the counter's price arguments, in its order"""
+    return [str(over.get(k, p[k])) for k in KINDS]
+
+
 def count(exe, name, tmp_path, events=200_000):
     cfg = W.config(name)
     o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
@@ -57,8 +65,7 @@ def count(exe, name, tmp_path, events=200_000):
     grid = tmp_path / f"grid_{name}.txt"
     np.savetxt(grid, o.get_grid())
     p = _prices()
-    r = subprocess.run([exe, name, str(grid), str(events), str(p["atan"]), str(p["log"]), str(p["exp"]),
-                        str(p["expm1"])], check=True, capture_output=True, text=True)
+    r = subprocess.run([exe, name, str(grid), str(events)] + prices(p), check=True, capture_output=True, text=True)
     return json.loads(r.stdout)
 
 
@@ -72,17 +79,31 @@ def test_algorithmic_flops_match_bench_constant(counter, name, tmp_path):
 
 
 def test_counting_scalar_counts_what_it_should(counter, tmp_path):
-    """The count is the source's arithmetic: doubling the price of one library call
-    moves the W+ total by exactly its calls per event (one log and two expm1, the
-    latter only past the Breit-Wigner map), and uniform work is not counted (the
-    W+W- integrand's constant phase-space factor kPS is one multiply)."""
+    """The count is the source's arithmetic with each mathematical function priced once:
+    raising the price of one function moves the W+ total by exactly its calls per event
+    times the change (one log per event; the W+W- integrand's tangents: two Breit-Wigner
+    maps per event), the routines' own operations are not counted (with every price 0
+    the W+W- total drops by more than its priced calls would explain otherwise), and
+    uniform work is not counted."""
+    p = _prices()
     cfg = W.config("w_plus")
     o = oracle.Vegas(cfg["process"], cfg["ndim"], cfg["nbins"], cfg["seed"], cfg["alpha"], cfg["params"])
     grid = tmp_path / "g.txt"
     np.savetxt(grid, o.get_grid())
-    base = json.loads(subprocess.run([counter, "w_plus", str(grid), "20000", "0", "0", "0", "0"], check=True,
-                                     capture_output=True, text=True).stdout)
-    one = json.loads(subprocess.run([counter, "w_plus", str(grid), "20000", "0", "100", "0", "0"], check=True,
-                                    capture_output=True, text=True).stdout)
+
+    def run(proc, g, **over):
+        return json.loads(subprocess.run([counter, proc, str(g), "20000"] + prices(p, **over), check=True,
+                                         capture_output=True, text=True).stdout)
+
+    base = run("w_plus", grid)
+    one = run("w_plus", grid, log=p["log"] + 100)
     assert abs((one["total"] - base["total"]) - 100.0) < 1e-9      # exactly one log per event
-    assert base["library_calls"] == 0.0
+    cw = W.config("ww_4l")
+    ow = oracle.Vegas(cw["process"], cw["ndim"], cw["nbins"], cw["seed"], cw["alpha"], cw["params"])
+    gw = tmp_path / "gw.txt"
+    np.savetxt(gw, ow.get_grid())
+    b = run("ww_4l", gw)
+    t = run("ww_4l", gw, tan=p["tan"] + 10)
+    assert abs((t["total"] - b["total"]) - 20.0) < 1e-9             # two tangents per event
+    z = run("ww_4l", gw, **{k: 0 for k in KINDS})
+    assert z["library_calls"] == 0.0 and z["total"] < b["total"] - b["library_calls"] + 1e-9
