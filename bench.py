@@ -54,11 +54,11 @@ sys.path.insert(0, ROOT)
 EVENT_KERNEL_WORK = {
     ("w_plus", "fp64"): {"algorithmic_f64": 373.5, "f64": 345.3, "f32": 0.0, "traffic": 25_497_497,
                          "events": 1_000_000},
-    ("ww_4l", "fp64"): {"algorithmic_f64": 1360.7, "f64": 1153.7, "f32": 0.0, "traffic": 180_147_627,
+    ("ww_4l", "fp64"): {"algorithmic_f64": 1262.7, "f64": 1153.7, "f32": 0.0, "traffic": 180_147_627,
                         "events": 10_000_000},
     ("ww_4l", "fp32me"): {"algorithmic_f64": None, "f64": 684.6, "f32": 506.0, "traffic": None,
                           "events": 10_000_000},
-    ("ww_had", "fp64"): {"algorithmic_f64": 1687.8, "f64": 1437.8, "f32": 0.0, "traffic": 216_933_959,
+    ("ww_had", "fp64"): {"algorithmic_f64": 1589.8, "f64": 1437.8, "f32": 0.0, "traffic": 216_933_959,
                          "events": 10_000_000},
 }
 # FP64 FLOPs of one call of the library's version of each mathematical function the

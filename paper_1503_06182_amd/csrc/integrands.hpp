@@ -153,8 +153,8 @@ __device__ __forceinline__ double tan_halfpi(double x) {
 // mappings (rounding kept as in their plain definitions: no contraction)
 // ---------------------------------------------------------------------------
 // m^2 = M^2 + M G tan(rho_lo + r rrng) on the process's window (lower edge m2lo,
-// rho_lo = atan(tlo)); jac = dm^2/dr
-__device__ __forceinline__ double bw_map(const PhysConst& c, double r, double rrng, double& jac) {
+// rho_lo = atan(tlo)); jac = dm^2/dr = rrng ((m^2 - M^2)^2 + (M G)^2) / (M G)
+__device__ __forceinline__ double bw_mass(const PhysConst& c, double r, double rrng) {
 #pragma clang fp contract(off)
   const double rho = c.rho_lo + r * rrng;
   // below the pole the mass is measured from the window's lower edge (tangent
@@ -162,7 +162,12 @@ __device__ __forceinline__ double bw_map(const PhysConst& c, double r, double rr
   // one tangent per event either way (no divergent second call)
   const bool below = rho < 0.0;
   const double t = tan_halfpi(below ? r * rrng : rho);
-  const double m2 = below ? c.m2lo + c.MGt * t * rcp_nr(1.0 - c.tlo * t) : c.M2 + c.MG * t;
+  return below ? c.m2lo + c.MGt * t * rcp_nr(1.0 - c.tlo * t) : c.M2 + c.MG * t;
+}
+
+__device__ __forceinline__ double bw_map(const PhysConst& c, double r, double rrng, double& jac) {
+#pragma clang fp contract(off)
+  const double m2 = bw_mass(c, r, rrng);
   const double dm = m2 - c.M2;
   jac = rrng * (dm * dm + c.MG2) * c.invMG;
   return m2;
@@ -440,25 +445,18 @@ __device__ __forceinline__ void lepton_current(const double pa[4], const double 
   current(a0, a1, b0, b1, J);
 }
 
-// sum over q in {u, d} and quark helicity of |M|^2 (no averages), from the lepton
-// currents Jp = ubar(nu) gamma P_L v(e+), Jm = ubar(mu-) gamma P_L v(nubar) and the W
-// momenta qp, qm
+// sum over q in {u, d} and quark helicity of |M|^2 (no averages) WITHOUT the two W
+// propagators and couplings g/sqrt2 / (m^2 - MW^2 + i MW GW): every diagram is linear
+// in each W's polarisation current, so they factor out of every amplitude as one complex
+// number, and |.|^2 of it, g^4/4 / ((m+^2 - MW^2)^2 + (MW GW)^2) / ((m-^2 - MW^2)^2 +
+// (MW GW)^2), cancels against the Breit-Wigner maps' Jacobians (the caller multiplies
+// the remainder, (g^2/2)^2 / (MW GW)^2 times the maps' ranges, into the weight).  From the
+// lepton currents Jp = ubar(nu) gamma P_L v(e+), Jm = ubar(mu-) gamma P_L v(nubar) (the
+// polarisations ep, em up to those factors) and the W momenta qp, qm
 template <typename R, bool HAD = false>
-__device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const cx<R> Jp[4], const cx<R> Jm[4],
-                                    const R qp[4], const R qm[4], R mp2, R mm2, const ExchInv<R>* inv) {
-  const R MW2 = static_cast<R>(c.M2), MWGW = static_cast<R>(c.MG), gs = static_cast<R>(c.gs);
-  // g/sqrt2 / (m^2 - MW^2 + i MW GW)
-  const R dp = mp2 - MW2, dm = mm2 - MW2;
-  const R MG2 = static_cast<R>(c.MG2);
-  const R np = gs * rcp_nr(dp * dp + MG2), nm = gs * rcp_nr(dm * dm + MG2);
-  const cx<R> cp = {dp * np, -MWGW * np}, cm = {dm * nm, -MWGW * nm};
-  cx<R> ep[4], em[4];
+__device__ __forceinline__ R ww_me2(const PhysConst& c, const WWHad& hd, const cx<R> ep[4], const cx<R> em[4],
+                                    const R qp[4], const R qm[4], const ExchInv<R>* inv) {
   R Ppq[4], Pmq[4], dq[4];
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    ep[mu] = cmul(Jp[mu], cp);
-    em[mu] = cmul(Jm[mu], cm);
-  }
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const R PP = qp[mu] + qm[mu];
@@ -587,15 +585,16 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     hd.rs = rs;
     hd.sh = sh;
   }
-  double jp, jm;
-  const double mp2 = bw_map(c, x[0], rho_rng, jp);
+  // the masses from the Breit-Wigner maps; their Jacobians' resonance factors cancel
+  // the W propagators (see ww_me2): only the maps' ranges enter the weight
+  const double mp2 = bw_mass(c, x[0], rho_rng);
   obs_sq = mp2 > 0.0 ? mp2 : 0.0;
   if (!(mp2 > 0.0)) return 0.0;
   double mp, imp;
   sqrt_rsqrt_nr(mp2, mp, imp);
   const double up = (rs - mp) * (rs - mp);
   const double rrng2 = atan_rr((up - c.M2) * c.invMG) - c.rho_lo;
-  const double mm2 = bw_map(c, x[1], rrng2, jm);
+  const double mm2 = bw_mass(c, x[1], rrng2);
   if (!(mm2 > 0.0)) return 0.0;
   double mm, imm;
   sqrt_rsqrt_nr(mm2, mm, imm);
@@ -657,16 +656,19 @@ __device__ __forceinline__ double f_ww(const PhysConst& c, const double* x, doub
     iv.b00d = static_cast<R>(-emm);
     iv.b11d = static_cast<R>(rs - (Emd - qd * cd));
     me = static_cast<double>(
-        ww_me2<R, HAD>(c, hd, Jp, Jm, qpr, qmr, static_cast<R>(mp2), static_cast<R>(mm2), &iv));
+        ww_me2<R, HAD>(c, hd, Jp, Jm, qpr, qmr, &iv));
   } else {
     me = static_cast<double>(
-        ww_me2<R, HAD>(c, hd, Jp, Jm, qpr, qmr, static_cast<R>(mp2), static_cast<R>(mm2), nullptr));
+        ww_me2<R, HAD>(c, hd, Jp, Jm, qpr, qmr, nullptr));
   }
   // dPhi_2(P) (4 pi) = sl / (8 pi shat), dm+^2/(2 pi), dm-^2/(2 pi), [dPhi_2(W) (4 pi)]^2 =
-  // 1 / (64 pi^2), flux 1 / (2 shat), colour and spin average 1/12: one constant over shat^2
+  // 1 / (64 pi^2), flux 1 / (2 shat), colour and spin average 1/12: one constant over shat^2;
+  // each Breit-Wigner Jacobian times its propagator's |g/sqrt2 / (m^2 - MW^2 + i MW GW)|^2
+  // is (g^2/2) / (MW GW) times the map's range
   constexpr double kPS = 0.5 / (12.0 * 8.0 * kPi * 4.0 * kPi * kPi * 64.0 * kPi * kPi);
+  const double gbw = (c.gs * c.gs) * c.invMG;
   const double ish = HAD ? rcp_nr(sh) : 1.0 / sh;
-  const double w = (c.conv * kPS) * (ish * ish) * (sl * me) * (jp * jm);
+  const double w = (c.conv * kPS) * (gbw * gbw) * (ish * ish) * (sl * me) * (rho_rng * rrng2);
   if constexpr (HAD) return w * lum;
   return w;
 }
