@@ -103,19 +103,25 @@ __device__ __forceinline__ void mlp_tile32(const float* __restrict__ m, const ui
   __syncthreads();
 }
 
+// x of lane i ^ 1 (CTRL 0xB1) or i ^ 2 (0x4E) within each group of four lanes (DPP quad_perm)
+template <int CTRL>
+__device__ __forceinline__ float quad_xor(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
 // one coupling layer over a batch; SAMPLE: inverse splines (z -> y), else forward (y -> z).
 // vout may alias vin.  logq[i] += sum of log s' of the four transformed coordinates.
-// Tiles of 64 events; each wave keeps the B operands of its output columns (W2: 2
-// column blocks, W3: 3) for all eight k-steps in registers for the whole launch.
+// Tiles of 64 events; each wave keeps the weight fragments of its output units (W2: 2
+// blocks of 16, W3: 3) for all eight k-steps in registers for the whole launch.
 template <bool SAMPLE>
 __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__ master,
                                                         const uint16_t* __restrict__ wb, int l, const float* vin,
                                                         float* vout, float* logq, int64_t B) {
   // h1 is dead once the second layer has run (a barrier follows it), so the spline
   // parameters the third layer writes share its space: 44 KB per block, 3 blocks per CU
-  static_assert(FL_TILE_F * FL_LDH * sizeof(_Float16) >= FL_TILE_F * FL_LDA * sizeof(uint16_t), "h1 / par union");
+  static_assert(FL_TILE_F * FL_LDQ * sizeof(_Float16) >= FL_TILE_F * FL_LDA * sizeof(uint16_t), "h1 / par union");
   __shared__ float cond[FL_TILE_F][4];
-  __shared__ __align__(16) _Float16 h1_par[FL_TILE_F * FL_LDH];
+  __shared__ __align__(16) _Float16 h1_par[FL_TILE_F * FL_LDQ];
   __shared__ __align__(16) uint16_t h2[FL_TILE_F * FL_LDA];
   uint16_t* const h1 = reinterpret_cast<uint16_t*>(h1_par);
   _Float16* const par = h1_par;
@@ -123,78 +129,166 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
   const float* m = master + l * FL_LAYER;
   const uint16_t* w = wb + static_cast<int64_t>(l) * FB_LAYER;
   bf16x8_t b2[2][FL_HID / 32], b3[3][FL_HID / 32];
+  // second layer: forward, output columns (2 w + cc) 16 + lane % 16; sampling, the units
+  // of the paired-tile order (the lanes of a group receive 8 consecutive units of an event)
 #pragma unroll
-  for (int cc = 0; cc < 2; ++cc)
+  for (int cc = 0; cc < 2; ++cc) {
+    const int row = SAMPLE ? pair_unit(wave, cc, lane & 15) : (2 * wave + cc) * 16 + (lane & 15);
 #pragma unroll
-    for (int ks = 0; ks < FL_HID / 32; ++ks) b2[cc][ks] = load_bfrag(w + FB_W2T, FL_HID, (2 * wave + cc) * 16, ks * 32, lane);
-#pragma unroll
-  for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-    for (int ks = 0; ks < FL_HID / 32; ++ks) b3[cc][ks] = load_bfrag(w + FB_W3T, FL_HID, (3 * wave + cc) * 16, ks * 32, lane);
-  float bias2[2], bias3[3];
-#pragma unroll
-  for (int cc = 0; cc < 2; ++cc) bias2[cc] = m[FO_B2 + (2 * wave + cc) * 16 + (lane & 15)];
+    for (int ks = 0; ks < FL_HID / 32; ++ks)
+      b2[cc][ks] = *reinterpret_cast<const bf16x8_t*>(w + FB_W2T + row * FL_HID + ks * 32 + 8 * (lane >> 4));
+  }
+  // third layer: forward, output columns 48 w .. 48 w + 47 in the parameters' order;
+  // sampling, the 47 parameters of coordinate w (the 48th slot takes zero row 188 of the
+  // padded copy), so that wave w's outputs are exactly the parameters of the spline of
+  // coordinate w: tiles 0 and 1 give parameters 0 .. 31 in the paired-tile order,
+  // tile 2 parameters 32 .. 47 in order
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
-    const int col = (3 * wave + cc) * 16 + (lane & 15);
-    bias3[cc] = col < FL_NOUT ? m[FO_B3 + col] : 0.f;
+    const int s = lane & 15;
+    const int slot = cc < 2 ? 8 * (s >> 2) + 4 * cc + (s & 3) : 32 + s;
+    const int row = SAMPLE ? (slot < FL_NPAR ? wave * FL_NPAR + slot : FL_NOUT) : 48 * wave + 16 * cc + s;
+#pragma unroll
+    for (int ks = 0; ks < FL_HID / 32; ++ks)
+      b3[cc][ks] = *reinterpret_cast<const bf16x8_t*>(w + FB_W3T + row * FL_HID + ks * 32 + 8 * (lane >> 4));
+  }
+  // biases: forward, of the lane's output column (C = A Bt with the activations as A),
+  // in registers; sampling, of the lane's four output rows (C^T = Bt^T A^T: the
+  // weights are the A operand, so a lane receives four consecutive outputs of one
+  // event and stores them in one 8-byte write), read from LDS as the accumulators'
+  // initial values (registers held through the splines would spill)
+  __shared__ __align__(16) float bias_s[SAMPLE ? FL_HID + FL_NOUTP : 1];
+  float bias2[2], bias3[3];
+  if constexpr (SAMPLE) {
+    for (int i = tid; i < FL_HID + FL_NOUTP; i += blockDim.x) {
+      const int c = (i - FL_HID) / 48, slot = (i - FL_HID) % 48;
+      bias_s[i] = i < FL_HID ? m[FO_B2 + i] : (slot < FL_NPAR ? m[FO_B3 + c * FL_NPAR + slot] : 0.f);
+    }
+  } else {
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) bias2[cc] = m[FO_B2 + (2 * wave + cc) * 16 + (lane & 15)];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const int col = (3 * wave + cc) * 16 + (lane & 15);
+      bias3[cc] = col < FL_NOUT ? m[FO_B3 + col] : 0.f;
+    }
   }
   const H1Frag u1 = load_h1_frag(m, wave, lane);
   const int ri = lane & 15, kq = 4 * (lane >> 4), kq8 = 8 * (lane >> 4);
-  for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE_F; e0 < B;
-       e0 += static_cast<int64_t>(gridDim.x) * FL_TILE_F) {
-    {
-      const int e = tid >> 2, c = tid & 3;
-      const int64_t ev = e0 + e;
-      cond[e][c] = ev < B ? vin[ev * FL_NDIM + kFlowC[l][c]] : 0.5f;
+  // thread (event e, slot c) of a tile: its conditioning input c goes to LDS, and it
+  // transforms coordinate kFlowX[l][c] after the MLP.  Both inputs of the next tile are
+  // loaded while the current one runs (tiles hold disjoint events, so an in-place
+  // layer's stores never touch them).
+  const int e = tid >> 2, c = tid & 3;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * FL_TILE_F;
+  const int xc = kFlowX[l][c], cc_in = kFlowC[l][c];
+  int64_t e0 = static_cast<int64_t>(blockIdx.x) * FL_TILE_F;
+  float cn = 0.5f, vn = 0.f;
+  if (e0 + e < B) {
+    cn = vin[(e0 + e) * FL_NDIM + cc_in];
+    vn = vin[(e0 + e) * FL_NDIM + xc];
+  }
+  for (; e0 < B; e0 += stride) {
+    const int64_t ev = e0 + e;
+    cond[e][c] = cn;
+    const float vx = vn;
+    if (ev + stride < B) {
+      cn = vin[(ev + stride) * FL_NDIM + cc_in];
+      vn = vin[(ev + stride) * FL_NDIM + xc];
     }
     __syncthreads();
     mlp_h1(u1, cond, h1, FL_TILE_F);
     __syncthreads();
+    if constexpr (SAMPLE) {
+      // the bias is the accumulators' initial value; ReLU and the bfloat16 rounding on
+      // pairs (v_cvt_pk_bf16_f32, v_pk_max_i16)
+      // the biases of the lane's slots, read once per layer and tile
+      const f32x4_t bb2[2] = {*reinterpret_cast<const f32x4_t*>(bias_s + 32 * wave + 2 * kq),
+                              *reinterpret_cast<const f32x4_t*>(bias_s + 32 * wave + 2 * kq + 4)};
 #pragma unroll
-    for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
+      for (int rb = 0; rb < FL_TILE_F / 16; ++rb) {
+        f32x4_t acc[2];
 #pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+        for (int cc = 0; cc < 2; ++cc) {
+          acc[cc] = bb2[cc];
 #pragma unroll
-        for (int ks = 0; ks < FL_HID / 32; ++ks) {
-          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h1 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
-          acc = mfma_step(a, b2[cc][ks], acc);
+          for (int ks = 0; ks < FL_HID / 32; ++ks) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h1 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
+            acc[cc] = mfma_step(b2[cc][ks], a, acc[cc]);
+          }
         }
-        const int col = (2 * wave + cc) * 16 + ri;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) h2[(rb * 16 + kq + j) * FL_LDA + col] = f2bf(fmaxf(acc[j] + bias2[cc], 0.f));
+        *reinterpret_cast<uint4*>(h2 + (rb * 16 + ri) * FL_LDA + 32 * wave + 2 * kq) = pack_relu_bf16x8(acc[0], acc[1]);
       }
-    __syncthreads();
+      __syncthreads();
+      const f32x4_t bb3[3] = {*reinterpret_cast<const f32x4_t*>(bias_s + FL_HID + 48 * wave + 2 * kq),
+                              *reinterpret_cast<const f32x4_t*>(bias_s + FL_HID + 48 * wave + 2 * kq + 4),
+                              *reinterpret_cast<const f32x4_t*>(bias_s + FL_HID + 48 * wave + 32 + kq)};
 #pragma unroll
-    for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
+      for (int rb = 0; rb < FL_TILE_F / 16; ++rb) {
+        f32x4_t acc[3];
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+        for (int cc = 0; cc < 3; ++cc) {
+          acc[cc] = bb3[cc];
 #pragma unroll
-        for (int ks = 0; ks < FL_HID / 32; ++ks) {
-          const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h2 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
-          acc = mfma_step(a, b3[cc][ks], acc);
+          for (int ks = 0; ks < FL_HID / 32; ++ks) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h2 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
+            acc[cc] = mfma_step(b3[cc][ks], a, acc[cc]);
+          }
         }
-        const int col = (3 * wave + cc) * 16 + ri;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) par[(rb * 16 + kq + j) * FL_LDH + col] = static_cast<_Float16>(acc[j] + bias3[cc]);
+        _Float16* const q = par + (rb * 16 + ri) * FL_LDQ + wave * FL_SPS;
+        *reinterpret_cast<uint4*>(q + 2 * kq) = make_uint4(pack_f16x2(acc[0][0], acc[0][1]), pack_f16x2(acc[0][2], acc[0][3]),
+                                                           pack_f16x2(acc[1][0], acc[1][1]), pack_f16x2(acc[1][2], acc[1][3]));
+        *reinterpret_cast<uint2*>(q + 32 + kq) = make_uint2(pack_f16x2(acc[2][0], acc[2][1]), pack_f16x2(acc[2][2], acc[2][3]));
       }
+    } else {
+      // the forward adds the bias after the products, as the backward's recomputation
+      // of the MLP does, so that the two agree bit for bit
+#pragma unroll
+      for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+          f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ks = 0; ks < FL_HID / 32; ++ks) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h1 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
+            acc = mfma_step(a, b2[cc][ks], acc);
+          }
+          const int col = (2 * wave + cc) * 16 + ri;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) h2[(rb * 16 + kq + j) * FL_LDA + col] = f2bf(fmaxf(acc[j] + bias2[cc], 0.f));
+        }
+      __syncthreads();
+#pragma unroll
+      for (int rb = 0; rb < FL_TILE_F / 16; ++rb)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ks = 0; ks < FL_HID / 32; ++ks) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(h2 + (rb * 16 + ri) * FL_LDA + ks * 32 + kq8);
+            acc = mfma_step(a, b3[cc][ks], acc);
+          }
+          const int col = (3 * wave + cc) * 16 + ri;  // parameter col % 47 of coordinate col / 47
+          if (col < FL_NOUT) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              par[(rb * 16 + kq + j) * FL_LDQ + (col / FL_NPAR) * FL_SPS + col % FL_NPAR] =
+                  static_cast<_Float16>(acc[j] + bias3[cc]);
+          }
+        }
+    }
     __syncthreads();
     {
-      const int e = tid >> 2, j = tid & 3;
-      const int64_t ev = e0 + e;
       float ld = 0.f;
       if (ev < B) {
-        const int d = kFlowX[l][j];
-        const float v = vin[ev * FL_NDIM + d];
-        const float o = spline_eval<SAMPLE>(par + e * FL_LDH + j * FL_NPAR, v, ld);
-        vout[ev * FL_NDIM + d] = o;
-        if (vout != vin) vout[ev * FL_NDIM + kFlowC[l][j]] = cond[e][j];
+        const float o = spline_eval<SAMPLE>(par + e * FL_LDQ + c * FL_SPS, vx, ld);
+        vout[ev * FL_NDIM + xc] = o;
+        if (vout != vin) vout[ev * FL_NDIM + cc_in] = cond[e][c];
       }
-      ld += __shfl_xor(ld, 1, 64);
-      ld += __shfl_xor(ld, 2, 64);
-      if (j == 0 && ev < B) logq[ev] += ld;
+      // the event's four log s' (lanes 4e .. 4e+3): sums over lane pairs, then pairs of pairs
+      ld += quad_xor<0xB1>(ld);
+      ld += quad_xor<0x4E>(ld);
+      if (c == 0 && ev < B) logq[ev] += ld;
     }
     __syncthreads();
   }

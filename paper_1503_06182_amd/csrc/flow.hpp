@@ -35,10 +35,18 @@ constexpr int FB_W2T = 0, FB_W3T = 16384, FB_W2N = 16384 + 24576, FB_W3N = 2 * 1
 constexpr int FB_LAYER = 2 * 16384 + 2 * 24576;  // 81920 bf16 per layer
 constexpr float FL_EPS = 1e-3f;
 // LDS row strides: whole 16-byte units (the matrix-core operands are 16-byte loads),
-// offset from a power of two against bank conflicts
-constexpr int FL_LDA = FL_HID + 8;   // bf16 activation tiles
+// offset from a power of two against bank conflicts.  The activation tiles' stride is
+// 72 four-byte words: on gfx950 the 16-byte fragment loads of 16 rows are free of bank
+// conflicts when the stride in words is 8 modulo 16 (measured: two-way conflicts at
+// 68, 76 or 84 words, eight-way at 64)
+constexpr int FL_LDA = FL_HID + 16;  // bf16 activation tiles
 constexpr int FL_LDP = FL_NOUTP + 8; // fp32 spline-parameter tile of the backward (and its bf16 gradient)
-constexpr int FL_LDH = FL_NOUTP + 8; // LDS row stride (binary16) of the spline-parameter tile (forward)
+// spline-parameter tile of the forward kernels (binary16): coordinate c's 47 parameters at
+// [56 c, 56 c + 47) of a 248-element row, so every spline's parameters start on a 16-byte
+// boundary (a 16-byte LDS load that is not 16-byte aligned costs about 16 aligned ones on
+// gfx950).  The row of 124 words keeps both the third layer's 8-byte stores and the
+// splines' 16-byte loads at two-way bank conflicts at most (measured).
+constexpr int FL_SPS = 56, FL_LDQ = 248;
 constexpr int FL_TILE_F = 64;        // events per tile of the forward kernels
 constexpr float FL_DSHIFT = 0.53974242f;  // log(expm1(1 - eps)) for eps = 1e-3: raw 0 gives derivative 1
 
@@ -59,12 +67,17 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(stati
 // spline parameters are rounded to binary16 (round to nearest even) in both directions
 __device__ __forceinline__ float round_h(float x) { return static_cast<float>(static_cast<_Float16>(x)); }
 
+// Output slots of a wave's two 16-unit tiles t = 0, 1 over its 32 units [32 w, 32 w + 32):
+// slot s of tile t is unit 32 w + 8 (s / 4) + 4 t + s % 4, so the lanes of group
+// g = l / 16, which receive slots 4 g .. 4 g + 3 of both tiles, hold the 8 consecutive
+// units 32 w + 8 g .. + 7 of their event and store them in one 16-byte write.
+__device__ __forceinline__ int pair_unit(int wave, int t, int s) { return 32 * wave + 8 * (s >> 2) + 4 * t + (s & 3); }
+
 // first MLP layer on the matrix cores, binary32 (K = the 4 conditioning inputs), by a
 // block of 4 waves: wave w computes hidden units [32 w, 32 w + 32) as two 16-unit tiles.
 // Tile (t, event rows r0 .. r0+15): h1^T = W1^T cond^T + b1 on v_mfma_f32_16x16x4_f32 --
-// lane l supplies W1[l/16][u0 + l%16] (A) and cond[r0 + l%16][l/16] (B), starts from
-// the biases of units u0 + 4(l/16) .. +3 and receives those four units of event
-// r0 + l%16, stored as four bf16 in one 8-byte write.
+// lane l supplies W1[l/16][unit of slot l%16] (A) and cond[r0 + l%16][l/16] (B), starts
+// from the biases of its four slots and receives those four units of event r0 + l%16.
 struct H1Frag {
   float w[2], b[2][4];
 };
@@ -73,18 +86,40 @@ __device__ __forceinline__ H1Frag load_h1_frag(const float* __restrict__ m, int 
   H1Frag f;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int u0 = (2 * wave + t) * 16;
-    f.w[t] = m[FO_W1 + (lane >> 4) * FL_HID + u0 + (lane & 15)];
+    f.w[t] = m[FO_W1 + (lane >> 4) * FL_HID + pair_unit(wave, t, lane & 15)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) f.b[t][j] = m[FO_B1 + u0 + 4 * (lane >> 4) + j];
+    for (int j = 0; j < 4; ++j) f.b[t][j] = m[FO_B1 + pair_unit(wave, t, 4 * (lane >> 4) + j)];
   }
   return f;
 }
 
-// four binary32 values -> four bf16 (round to nearest even) in one 8-byte word
-__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
-  return make_uint2(static_cast<uint32_t>(f2bf(a)) | (static_cast<uint32_t>(f2bf(b)) << 16),
-                    static_cast<uint32_t>(f2bf(c)) | (static_cast<uint32_t>(f2bf(d)) << 16));
+typedef float __attribute__((ext_vector_type(2))) f32x2_t;
+typedef __bf16 __attribute__((ext_vector_type(2))) bf16x2_t;
+typedef _Float16 __attribute__((ext_vector_type(2))) f16x2_t;
+typedef short __attribute__((ext_vector_type(2))) i16x2_t;
+
+// max(round_bf16(a), 0), max(round_bf16(b), 0) in one word (v_cvt_pk_bf16_f32, then
+// v_pk_max_i16 on the bit patterns: a bfloat16 with the sign bit set is a negative
+// 16-bit integer, so the integer maximum with 0 is the ReLU).  Rounding to nearest
+// keeps the sign and ReLU(x) is 0 or x, so this equals the rounding of max(x, 0)
+// bit for bit for every x but a NaN (a negative x gives +0 either way).
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  const f32x2_t v = {a, b};
+  const i16x2_t r = __builtin_bit_cast(i16x2_t, __builtin_convertvector(v, bf16x2_t));
+  const i16x2_t z = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(r, z));
+}
+
+// the ReLU of the four values of a0, then of a1, as eight bf16 in one 16-byte word
+__device__ __forceinline__ uint4 pack_relu_bf16x8(f32x4_t a0, f32x4_t a1) {
+  return make_uint4(relu_bf16x2(a0[0], a0[1]), relu_bf16x2(a0[2], a0[3]), relu_bf16x2(a1[0], a1[1]),
+                    relu_bf16x2(a1[2], a1[3]));
+}
+
+// two binary32 values -> two binary16 (round to nearest even, v_cvt_pk_f16_f32) in one word
+__device__ __forceinline__ uint32_t pack_f16x2(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2_t));
 }
 
 // h1 of `rows` events (a multiple of 16; cond [rows][4] in LDS) -> bf16 in LDS (stride
@@ -93,14 +128,12 @@ __device__ __forceinline__ void mlp_h1(const H1Frag& f, const float (*cond)[4], 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r0 = 0; r0 < rows; r0 += 16) {
     const float c = cond[r0 + (lane & 15)][lane >> 4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      f32x4_t acc = {f.b[t][0], f.b[t][1], f.b[t][2], f.b[t][3]};
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w[t], c, acc, 0, 0, 0);
-      const int u = (2 * wave + t) * 16 + 4 * (lane >> 4);
-      *reinterpret_cast<uint2*>(h1 + (r0 + (lane & 15)) * FL_LDA + u) =
-          pack_bf16x4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f), fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
-    }
+    f32x4_t a0 = {f.b[0][0], f.b[0][1], f.b[0][2], f.b[0][3]};
+    f32x4_t a1 = {f.b[1][0], f.b[1][1], f.b[1][2], f.b[1][3]};
+    a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w[0], c, a0, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(f.w[1], c, a1, 0, 0, 0);
+    *reinterpret_cast<uint4*>(h1 + (r0 + (lane & 15)) * FL_LDA + 32 * wave + 8 * (lane >> 4)) =
+        pack_relu_bf16x8(a0, a1);
   }
 }
 
@@ -145,9 +178,12 @@ __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 __device__ __forceinline__ float flog(float x) { return __logf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float softplus_f(float z) { return z > 20.f ? z : flog(1.f + fexp(z)); }
-__device__ __forceinline__ float knot_step(float e, float inv) {  // eps + (1 - 16 eps) softmax
-  return __fmaf_rn(1.f - FL_NB * FL_EPS, e * inv, FL_EPS);
-}
+// knot i (0 < i < 16) of the partition whose bins are eps + (1 - 16 eps) softmax(r):
+// i eps + (1 - 16 eps) S_i / S_16, S_i = e_0 + ... + e_{i-1} the partial sums of the
+// softmax numerators, with c = (1 - 16 eps) / S_16 (the same function as the running
+// sum of the bin widths, one rounding per knot); knots 0 and 16 are 0 and 1 exactly
+constexpr float FL_KSCALE = 1.f - FL_NB * FL_EPS;
+__device__ __forceinline__ float knot_at(float S, float c, int i) { return __fmaf_rn(S, c, static_cast<float>(i) * FL_EPS); }
 
 // the four numbers of the rational-quadratic map on one bin, and its evaluation
 struct Bin {
@@ -186,47 +222,69 @@ __device__ __forceinline__ float rq_inverse(const Bin& q, float y, float& ld) {
   return x;
 }
 
-// softmax numerators e_i = exp(r_i - max r) of 16 logits and 1 / sum
-template <typename T>
-__device__ __forceinline__ float softmax16(const T* r, float* e) {
-  float m = static_cast<float>(r[0]);
+// largest of 16 logits (binary16 in LDS: packed three-operand maxima, v_pk_maximum3_f16, exact)
+__device__ __forceinline__ float max16(const _Float16* r) {
+  f16x2_t m[4];
 #pragma unroll
-  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, static_cast<float>(r[i]));
-  float s = 0.f;
+  for (int i = 0; i < 4; ++i) {
+    const f16x2_t a = {r[4 * i], r[4 * i + 1]}, b = {r[4 * i + 2], r[4 * i + 3]};
+    m[i] = __builtin_elementwise_maximum(a, b);
+  }
+  const f16x2_t t = __builtin_elementwise_maximum(__builtin_elementwise_maximum(m[0], m[1]),
+                                                  __builtin_elementwise_maximum(m[2], m[3]));
+  return static_cast<float>(__builtin_elementwise_maximum(t.x, t.y));
+}
+__device__ __forceinline__ float max16(const float* r) {
+  float m = r[0];
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) m = fmaxf(m, r[i]);
+  return m;
+}
+
+// softmax numerators e_i = exp(r_i - max r) of 16 logits, as exp2(r_i log2 e - max r log2 e)
+// (one fused multiply-add per logit: the common rounding of max r log2 e scales every
+// numerator alike and cancels in the ratios), and their partial sums S[i] = e_0 + ... +
+// e_{i-1}, accumulated left to right (S[16] the sum)
+template <typename T>
+__device__ __forceinline__ void softmax16(const T* r, float* e, float* S) {
+  constexpr float kLog2e = 1.44269504088896341f;
+  const float nm = -max16(r) * kLog2e;
+  S[0] = 0.f;
 #pragma unroll
   for (int i = 0; i < FL_NB; ++i) {
-    e[i] = fexp(static_cast<float>(r[i]) - m);
-    s += e[i];
+    e[i] = __builtin_amdgcn_exp2f(__fmaf_rn(static_cast<float>(r[i]), kLog2e, nm));
+    S[i + 1] = S[i] + e[i];
   }
-  return frcp(s);
 }
 
 // spline of one coordinate from its 47 parameters (forward: x -> y; INV: y -> x) and
-// log s' of the forward map; the bin is the number of interior knots below v (of the
-// x knots forward, of the y knots inverse)
+// log s' of the forward map; the bin k is the number of interior knots below v (of the
+// x knots forward, of the y knots inverse).  The knots below v form a prefix of 1..15,
+// so the last one below v is knot k and the one after it knot k + 1.
 template <bool INV, typename T>
 __device__ __forceinline__ float spline_eval(const T* p, float v, float& ld) {
-  float ew[FL_NB], eh[FL_NB];
-  const float iw = softmax16(p, ew), ih = softmax16(p + FL_NB, eh);
-  Bin q{0.f, 1.f, 0.f, 1.f, 1.f, 1.f};
-  int k = FL_NB - 1;
-  bool found = false;
-  float cx = 0.f, cy = 0.f;
+  float ew[FL_NB], eh[FL_NB], Sw[FL_NB + 1], Sh[FL_NB + 1];
+  softmax16(p, ew, Sw);
+  softmax16(p + FL_NB, eh, Sh);
+  const float cw = FL_KSCALE * frcp(Sw[FL_NB]), ch = FL_KSCALE * frcp(Sh[FL_NB]);
+  float xk[FL_NB + 1], yk[FL_NB + 1];
+  xk[0] = yk[0] = 0.f;
+  xk[FL_NB] = yk[FL_NB] = 1.f;
 #pragma unroll
-  for (int i = 0; i < FL_NB; ++i) {
-    const float nx = i == FL_NB - 1 ? 1.f : cx + knot_step(ew[i], iw);
-    const float ny = i == FL_NB - 1 ? 1.f : cy + knot_step(eh[i], ih);
-    const bool here = !found && (i == FL_NB - 1 || !((INV ? ny : nx) < v));
-    if (here) {
-      q.x0 = cx;
-      q.x1 = nx;
-      q.y0 = cy;
-      q.y1 = ny;
-      k = i;
-      found = true;
-    }
-    cx = nx;
-    cy = ny;
+  for (int i = 1; i < FL_NB; ++i) {
+    xk[i] = knot_at(Sw[i], cw, i);
+    yk[i] = knot_at(Sh[i], ch, i);
+  }
+  Bin q{0.f, xk[1], 0.f, yk[1], 1.f, 1.f};
+  int k = 0;
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) {
+    const bool below = (INV ? yk[i] : xk[i]) < v;
+    q.x0 = below ? xk[i] : q.x0;
+    q.x1 = below ? xk[i + 1] : q.x1;
+    q.y0 = below ? yk[i] : q.y0;
+    q.y1 = below ? yk[i + 1] : q.y1;
+    k = below ? i : k;
   }
   q.d0 = k == 0 ? 1.f : FL_EPS + softplus_f(static_cast<float>(p[2 * FL_NB + k - 1]) + FL_DSHIFT);
   q.d1 = k == FL_NB - 1 ? 1.f : FL_EPS + softplus_f(static_cast<float>(p[2 * FL_NB + k]) + FL_DSHIFT);
@@ -240,19 +298,24 @@ struct Knots {
 };
 
 __device__ __forceinline__ void make_knots(const float* raw, Knots& K) {
-  float ew[FL_NB], eh[FL_NB];
-  const float iw = softmax16(raw, ew), ih = softmax16(raw + FL_NB, eh);
-  float cx = 0.f, cy = 0.f;
+  float ew[FL_NB], eh[FL_NB], Sw[FL_NB + 1], Sh[FL_NB + 1];
+  softmax16(raw, ew, Sw);
+  softmax16(raw + FL_NB, eh, Sh);
+  const float iw = frcp(Sw[FL_NB]), ih = frcp(Sh[FL_NB]);
+  const float cw = FL_KSCALE * iw, ch = FL_KSCALE * ih;
   K.xk[0] = 0.f;
   K.yk[0] = 0.f;
+  K.xk[FL_NB] = 1.f;
+  K.yk[FL_NB] = 1.f;
 #pragma unroll
   for (int i = 0; i < FL_NB; ++i) {
     K.pw[i] = ew[i] * iw;
     K.ph[i] = eh[i] * ih;
-    cx = i == FL_NB - 1 ? 1.f : cx + knot_step(ew[i], iw);
-    cy = i == FL_NB - 1 ? 1.f : cy + knot_step(eh[i], ih);
-    K.xk[i + 1] = cx;
-    K.yk[i + 1] = cy;
+  }
+#pragma unroll
+  for (int i = 1; i < FL_NB; ++i) {
+    K.xk[i] = knot_at(Sw[i], cw, i);
+    K.yk[i] = knot_at(Sh[i], ch, i);
   }
   K.dk[0] = 1.f;
   K.dk[FL_NB] = 1.f;
