@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
                                                         const uint16_t* __restrict__ wb, int l, const float* vin,
                                                         float* vout, float* logq, int64_t B) {
   // h1 is dead once the second layer has run (a barrier follows it), so the spline
-  // parameters the third layer writes share its space: 44 KB per block, 3 blocks per CU
+  // parameters the third layer writes share its space: 52 KB per block, 3 blocks per CU
   static_assert(FL_TILE_F * FL_LDQ * sizeof(_Float16) >= FL_TILE_F * FL_LDA * sizeof(uint16_t), "h1 / par union");
   __shared__ float cond[FL_TILE_F][4];
   __shared__ __align__(16) _Float16 h1_par[FL_TILE_F * FL_LDQ];
@@ -155,8 +155,8 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
   // biases: forward, of the lane's output column (C = A Bt with the activations as A),
   // in registers; sampling, of the lane's four output rows (C^T = Bt^T A^T: the
   // weights are the A operand, so a lane receives four consecutive outputs of one
-  // event and stores them in one 8-byte write), read from LDS as the accumulators'
-  // initial values (registers held through the splines would spill)
+  // event, eight over a pair of tiles, stored in one 16-byte write), read from LDS as
+  // the accumulators' initial values (registers held through the splines would spill)
   __shared__ __align__(16) float bias_s[SAMPLE ? FL_HID + FL_NOUTP : 1];
   float bias2[2], bias3[3];
   if constexpr (SAMPLE) {
@@ -200,9 +200,9 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
     mlp_h1(u1, cond, h1, FL_TILE_F);
     __syncthreads();
     if constexpr (SAMPLE) {
-      // the bias is the accumulators' initial value; ReLU and the bfloat16 rounding on
-      // pairs (v_cvt_pk_bf16_f32, v_pk_max_i16)
-      // the biases of the lane's slots, read once per layer and tile
+      // the bias is the accumulators' initial value (the lane's slots' biases, read
+      // once per layer and tile); ReLU and the bfloat16 rounding on pairs
+      // (v_cvt_pk_bf16_f32, v_pk_max_i16)
       const f32x4_t bb2[2] = {*reinterpret_cast<const f32x4_t*>(bias_s + 32 * wave + 2 * kq),
                               *reinterpret_cast<const f32x4_t*>(bias_s + 32 * wave + 2 * kq + 4)};
 #pragma unroll

@@ -10,12 +10,14 @@
 // inverse splines.  Base density uniform on [0,1]^8.
 //
 // The forward kernels give each block (256 threads = 4 waves) tiles of 64
-// events: the first layer of the MLP on the VALU (K = 4), the two 128-wide
-// contractions on v_mfma_f32_16x16x32_bf16 (A from LDS; B, the layer's weights,
-// held in each wave's registers for the whole launch), the spline parameters
-// rounded to binary16 in LDS, then one thread per (event, transformed
-// coordinate) for the spline.  The backward kernel recomputes the same MLP
-// (tiles of 32, B from global memory, the same MFMA sequence, so the same bits).
+// events: the first layer of the MLP on v_mfma_f32_16x16x4_f32 (K = 4), the two
+// 128-wide contractions on v_mfma_f32_16x16x32_bf16 (activations from LDS, the
+// layer's weights held in each wave's registers for the whole launch; the density
+// direction takes the activations as the A operand, the sampling direction the
+// weights), the spline parameters rounded to binary16 in LDS, then one thread per
+// (event, transformed coordinate) for the spline.  The backward kernel recomputes
+// the density direction's MLP (tiles of 32, weights from global memory, the same
+// MFMA sequence, so the same bits).
 #pragma once
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
