@@ -118,6 +118,30 @@ def test_sampling_inverts_density(env):
     assert_rounding_noise((lqs.cpu().to(torch.float64) - lqo).abs().numpy(), "sample log q")
 
 
+def test_batch_and_position_invariance(env):
+    """Every event's sampling and density are computed on their own: the first k events
+    of a batch give the same bits alone (k = 1, 3, 63, 64, 65, 130: a lone event,
+    partial, whole and ragged 64-event tiles), and a permuted batch the permuted bits,
+    so neither the tile an event lands in nor its row there, nor the padding rows of a
+    ragged tile, changes anything."""
+    P, torch = env
+    theta = random_theta(torch, 12)
+    f = P.Flow(max_batch=1000)
+    f.set_params(theta)
+    z = points(torch, 1000, 13).cuda()
+    y, lq = f.sample(z)
+    for k in (1, 3, 63, 64, 65, 130):
+        yk, lqk = f.sample(z[:k])
+        assert torch.equal(yk, y[:k]) and torch.equal(lqk, lq[:k]), k
+    perm = torch.randperm(1000, generator=torch.Generator().manual_seed(3)).cuda()
+    yp, lqp = f.sample(z[perm])
+    assert torch.equal(yp, y[perm]) and torch.equal(lqp, lq[perm])
+    d = f.density(y)
+    for k in (1, 65):
+        assert torch.equal(f.density(y[:k]), d[:k]), k
+    assert torch.equal(f.density(y[perm]), d[perm])
+
+
 def test_loss_and_gradient_match_oracle(env, capsys):
     """Loss and all 248424 gradient entries on 600 weighted points.  The backward
     path rounds the gradients of the spline parameters and of h2 to bfloat16 before
