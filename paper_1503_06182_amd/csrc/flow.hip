@@ -197,6 +197,12 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
       vn = vin[(ev + stride) * FL_NDIM + xc];
     }
     __syncthreads();
+    // the three products run at a raised wave priority and the splines at the base one:
+    // a SIMD then issues the products of one block's waves ahead of another block's
+    // spline work, which keeps the co-resident blocks in different phases, the matrix
+    // cores busy beside the vector ALUs (measured 9 % faster than equal priorities, and
+    // 5 % faster than the reverse order)
+    __builtin_amdgcn_s_setprio(2);
     mlp_h1(u1, cond, h1, FL_TILE_F);
     __syncthreads();
     if constexpr (SAMPLE) {
@@ -279,6 +285,7 @@ __global__ __launch_bounds__(256, 3) void k_flow_layer(const float* __restrict__
     }
     __syncthreads();
     {
+      __builtin_amdgcn_s_setprio(0);
       float ld = 0.f;
       if (ev < B) {
         const float o = spline_eval<SAMPLE>(par + e * FL_LDQ + c * FL_SPS, vx, ld);
