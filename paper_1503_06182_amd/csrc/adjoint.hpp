@@ -95,6 +95,10 @@ __global__ __launch_bounds__(256) void k_dy_grad(GradArgs a) {
   for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     const int64_t tile = grp * wpb + wave;
     const bool tile_ok = tile < a.ntiles;
+    // wave priorities: phase 1 (uniforms, grid map, kinematics) at the base priority,
+    // phase 2 (the parameter points' sums) raised, so that waves of a block drift apart
+    // in phase (measured 1.7 % faster than equal priorities)
+    __builtin_amdgcn_s_setprio(0);
     // ---- phase 1: lane = event, theta-independent part at the nominal proposal
     if (tile_ok) {
       const int64_t i = tile * 64 + lane;
@@ -143,6 +147,7 @@ __global__ __launch_bounds__(256) void k_dy_grad(GradArgs a) {
       ev[lane * 5 + 4] = Ls;
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(3);
     // ---- phase 2: lane = parameter point, events of the tile in order
     if (tile_ok && lane < a.B) {
       double S[kGradVals] = {0, 0, 0, 0, 0, 0};
