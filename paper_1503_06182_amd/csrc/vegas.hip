@@ -343,10 +343,10 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
   const int32_t nev32 = static_cast<int32_t>(a.nev);
   for (int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x); i < nev32; i += step) {
     double u[D > 0 ? D : VEGAS_MAX_DIM], x[D > 0 ? D : VEGAS_MAX_DIM];
-    // wave priorities: the uniforms and the grid map (integer work and the LDS loads
-    // of the grid) at the base priority, the integrand at a raised one, so that a
-    // SIMD issues the floating-point work of waves already past their loads first and
-    // the waves of a block drift apart in phase (W+W- 340 against 366 us per 1e7-event
+    // wave priorities: the uniforms (integer work) at the base priority, the grid map
+    // (the grid's LDS loads) one step up, the integrand at the top, so that a SIMD
+    // issues the floating-point work of waves already past their loads first and the
+    // waves of a block drift apart in phase (W+W- 340 against 366 us per 1e7-event
     // launch, hadronic W+W- 490 against 532, with the fold there back at the base
     // priority; the light W+ kernel is unchanged)
     __builtin_amdgcn_s_setprio(0);
@@ -372,6 +372,7 @@ __global__ __launch_bounds__(MAXT, (MAXT == 256 ? event_min_waves<PROC>() : 1)) 
         }
       }
     }
+    __builtin_amdgcn_s_setprio(1);
     const double J = grid_map<D>(e_lds, n, nd, u, x, bins);
     __builtin_amdgcn_s_setprio(3);
     // the bins, 4 of 8 bits per word.  With 10 or more fixed dimensions they are
